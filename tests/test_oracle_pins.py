@@ -1,0 +1,354 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Nothing here re-types the oracle's recurrences: each check uses another
+definition (critical lattice paths, minimum over all orders, all n! schedules,
+closed forms for special instances, hand-worked examples) so that a dropped
+term, a wrong sign or index or a transposed operand in the oracle fails at
+least one of them.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1206_4973_amd import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ----------------------------------------------------------------------------
+# Independent definitions used only by the pins
+# ----------------------------------------------------------------------------
+def lattice_makespan(p, seq, machine=None):
+    """Makespan as the heaviest monotone lattice path (Sec. II.B problem):
+    from (first job, machine 0) to (last job, machine k), stepping to the next
+    job or the next machine, summing the operations visited.  Enumerated path
+    by path, not by a recurrence."""
+    m = p.shape[1]
+    k_end = m - 1 if machine is None else machine
+    L = len(seq)
+    best = 0
+    # a path = choice of which of the (L-1)+(k_end) steps are "next job"
+    steps = (L - 1) + k_end
+    for job_steps in itertools.combinations(range(steps), L - 1):
+        i, k = 0, 0
+        tot = p[seq[0]][0]
+        js = set(job_steps)
+        for s in range(steps):
+            if s in js:
+                i += 1
+            else:
+                k += 1
+            tot += p[seq[i]][k]
+        best = max(best, tot)
+    return best
+
+
+def relaxed_pair_value(p, prefix, k, l, r, q):
+    """Optimal value of the two-machine relaxation of pair (k,l), by brute
+    force over every order of the unscheduled jobs, each order evaluated by its
+    critical path (a closed form, not the recurrence): the last job on l
+    finishes at max(r_l + sum b, max_i r_k + sum_{<=i} a + lag_i + sum_{>=i} b)."""
+    n = p.shape[0]
+    U = [j for j in range(n) if j not in prefix]
+    best = None
+    for order in itertools.permutations(U):
+        a = [int(p[j][k]) for j in order]
+        b = [int(p[j][l]) for j in order]
+        lag = [int(sum(p[j][k + 1:l])) for j in order]
+        val = r[l] + sum(b)
+        for i in range(len(order)):
+            val = max(val, r[k] + sum(a[:i + 1]) + lag[i] + sum(b[i:]))
+        best = val if best is None else min(best, val)
+    return best + q[l]
+
+
+def random_prefix(rng, n, d):
+    return [int(x) for x in rng.permutation(n)[:d]]
+
+
+# ----------------------------------------------------------------------------
+# Makespan recurrence
+# ----------------------------------------------------------------------------
+def test_makespan_equals_heaviest_lattice_path(orc):
+    rng = np.random.default_rng(1)
+    for _ in range(60):
+        n, m = int(rng.integers(1, 6)), int(rng.integers(1, 5))
+        p = rng.integers(0, 20, size=(n, m)).astype(np.int32)
+        seq = [int(x) for x in rng.permutation(n)[: int(rng.integers(1, n + 1))]]
+        assert orc.makespan(p, seq) == lattice_makespan(p, seq)
+        F = orc.front(p, seq)
+        for k in range(m):
+            assert F[k] == lattice_makespan(p, seq, machine=k)
+
+
+def test_makespan_single_job_and_single_machine(orc):
+    rng = np.random.default_rng(2)
+    p = rng.integers(1, 99, size=(1, 7)).astype(np.int32)
+    assert orc.makespan(p, [0]) == int(p.sum())
+    p = rng.integers(1, 99, size=(6, 1)).astype(np.int32)
+    assert orc.makespan(p, list(range(6))) == int(p.sum())
+
+
+# ----------------------------------------------------------------------------
+# Johnson orders
+# ----------------------------------------------------------------------------
+def test_johnson_order_is_a_johnson_sequence(orc):
+    """Permutation of the given jobs; jobs with a < b (lag-shifted) come first
+    in non-decreasing a, then the rest in non-increasing b (Johnson's rule)."""
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        n, m = int(rng.integers(1, 12)), int(rng.integers(2, 7))
+        p = rng.integers(0, 15, size=(n, m)).astype(np.int32)
+        k, l = sorted(rng.choice(m, size=2, replace=False))
+        jobs = [int(x) for x in rng.permutation(n)[: int(rng.integers(0, n + 1))]]
+        order = [int(x) for x in orc.johnson_order(p, int(k), int(l), jobs)]
+        assert sorted(order) == sorted(jobs)
+        A = [int(p[j][k] + p[j][k + 1:l].sum()) for j in order]
+        B = [int(p[j][l] + p[j][k + 1:l].sum()) for j in order]
+        first = [i for i in range(len(order)) if A[i] < B[i]]
+        assert first == list(range(len(first)))
+        for i in range(1, len(first)):
+            assert A[i - 1] <= A[i]
+        for i in range(len(first) + 1, len(order)):
+            assert B[i - 1] >= B[i]
+
+
+# ----------------------------------------------------------------------------
+# Exactness on two machines (Johnson 1954)
+# ----------------------------------------------------------------------------
+def test_two_machines_root_bound_is_optimum(orc):
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        n = int(rng.integers(1, 8))
+        p = rng.integers(0, 30, size=(n, 2)).astype(np.int32)
+        opt, _ = orc.brute_force(p)
+        assert orc.lower_bound(p, []) == opt
+
+
+def test_two_machines_every_node_bound_is_best_completion(orc):
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        n = int(rng.integers(1, 7))
+        p = rng.integers(0, 30, size=(n, 2)).astype(np.int32)
+        for d in range(n + 1):
+            pre = random_prefix(rng, n, d)
+            assert orc.lower_bound(p, pre) == orc.best_completion(p, pre)
+
+
+# ----------------------------------------------------------------------------
+# Validity, exactness near the leaves, monotonicity
+# ----------------------------------------------------------------------------
+def test_bound_never_exceeds_any_completion(orc):
+    rng = np.random.default_rng(6)
+    for _ in range(150):
+        n, m = int(rng.integers(1, 7)), int(rng.integers(3, 7))
+        p = rng.integers(0, 40, size=(n, m)).astype(np.int32)
+        pre = random_prefix(rng, n, int(rng.integers(0, n + 1)))
+        assert orc.lower_bound(p, pre) <= orc.best_completion(p, pre)
+
+
+def test_exact_with_zero_or_one_job_left(orc):
+    rng = np.random.default_rng(7)
+    for _ in range(100):
+        n, m = int(rng.integers(1, 10)), int(rng.integers(2, 9))
+        p = rng.integers(0, 99, size=(n, m)).astype(np.int32)
+        perm = [int(x) for x in rng.permutation(n)]
+        assert orc.lower_bound(p, perm) == orc.makespan(p, perm)
+        assert orc.lower_bound(p, perm[:-1]) == orc.makespan(p, perm)
+
+
+def test_identical_jobs_closed_form(orc):
+    """Every job has the same times c: any schedule has makespan
+    sum(c) + (n-1) max(c), and the root bound reaches it."""
+    rng = np.random.default_rng(8)
+    for _ in range(30):
+        n, m = int(rng.integers(1, 9)), int(rng.integers(2, 8))
+        c = rng.integers(0, 50, size=m).astype(np.int32)
+        p = np.tile(c, (n, 1)).astype(np.int32)
+        want = int(c.sum()) + (n - 1) * int(c.max())
+        assert orc.lower_bound(p, []) == want
+        assert orc.makespan(p, list(range(n))) == want
+
+
+def test_bound_is_monotone_along_branches(orc):
+    rng = np.random.default_rng(9)
+    for _ in range(60):
+        n, m = int(rng.integers(2, 9)), int(rng.integers(2, 8))
+        p = rng.integers(0, 60, size=(n, m)).astype(np.int32)
+        pre = random_prefix(rng, n, int(rng.integers(0, n)))
+        lb = orc.lower_bound(p, pre)
+        for j in range(n):
+            if j not in pre:
+                assert orc.lower_bound(p, pre + [j]) >= lb
+
+
+def test_pair_values_equal_relaxation_optimum(orc):
+    """Johnson order with lags solves each pair's relaxation exactly: compare
+    with the minimum over every order of the unscheduled jobs."""
+    rng = np.random.default_rng(10)
+    for _ in range(40):
+        n, m = int(rng.integers(1, 7)), int(rng.integers(2, 6))
+        p = rng.integers(0, 25, size=(n, m)).astype(np.int32)
+        pre = random_prefix(rng, n, int(rng.integers(0, n)))
+        U = [j for j in range(n) if j not in pre]
+        F = orc.front(p, pre) if pre else np.zeros(m, np.int64)
+        r = [max(int(F[k]), int(F[0]) + min(int(p[j][:k].sum()) for j in U))
+             for k in range(m)]
+        q = [min(int(p[j][l + 1:].sum()) for j in U) for l in range(m)]
+        lb, pairs = orc.lower_bound_pairs(p, pre)
+        idx = 0
+        for k in range(m):
+            for l in range(k + 1, m):
+                assert pairs[idx] == relaxed_pair_value(p, pre, k, l, r, q), (k, l)
+                idx += 1
+        assert lb == max(pairs)
+
+
+def test_bound_invariant_under_job_relabelling(orc):
+    """Renaming jobs changes the Johnson tie-break (by id) but not the bound."""
+    rng = np.random.default_rng(11)
+    for _ in range(60):
+        n, m = int(rng.integers(2, 10)), int(rng.integers(2, 7))
+        p = rng.integers(0, 6, size=(n, m)).astype(np.int32)  # many ties
+        pre = random_prefix(rng, n, int(rng.integers(0, n)))
+        sigma = rng.permutation(n)  # new id of old job j is sigma[j]
+        p2 = np.zeros_like(p)
+        p2[sigma] = p
+        pre2 = [int(sigma[j]) for j in pre]
+        assert orc.lower_bound(p, pre) == orc.lower_bound(p2, pre2)
+
+
+def test_malformed_nodes_bound_to_minus_one(orc):
+    p = I.instance(6, 4, 12)
+    assert orc.lower_bound_record(p, [3, 1, 1, 2, 0, 0, 0]) == -1  # duplicate
+    assert orc.lower_bound_record(p, [2, 1, 6, 0, 0, 0, 0]) == -1  # id >= n
+    assert orc.lower_bound_record(p, [7, 0, 1, 2, 3, 4, 5]) == -1  # d > n
+    assert orc.lower_bound_record(p, [2, 5, 4, 9, 9, 9, 9]) >= 0   # junk after d ignored
+
+
+# ----------------------------------------------------------------------------
+# Hand-worked fixtures
+# ----------------------------------------------------------------------------
+def _load_hand_cases():
+    cases, cur = [], None
+    with open(os.path.join(HERE, "golden", "hand_examples.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            key, _, rest = line.partition(" ")
+            if key == "case":
+                cur = {"name": rest}
+                cases.append(cur)
+            elif key == "p":
+                cur["p"] = np.array([[int(x) for x in row.split()] for row in rest.split("|")],
+                                    dtype=np.int32)
+            else:
+                cur[key] = [int(x) for x in rest.split()]
+    return cases
+
+
+@pytest.mark.parametrize("case", _load_hand_cases(), ids=lambda c: c["name"])
+def test_hand_worked_examples(orc, case):
+    p, pre = case["p"], case.get("prefix", [])
+    assert p.shape == (case["n"][0], case["m"][0])
+    lb, pairs = orc.lower_bound_pairs(p, pre)
+    assert lb == case["lb"][0]
+    assert list(pairs) == case["pairs"]
+    U = [j for j in range(p.shape[0]) if j not in pre]
+    for key, val in case.items():
+        if key.startswith("order"):
+            k, l = int(key[5]), int(key[6])
+            assert [int(x) for x in orc.johnson_order(p, k, l, U)] == val
+    if "best" in case:
+        assert orc.best_completion(p, pre) == case["best"][0]
+
+
+# ----------------------------------------------------------------------------
+# Branch-and-bound, NEH, critical tree
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("rule", [0, 1])
+def test_bnb_reaches_the_brute_force_optimum(orc, rule):
+    rng = np.random.default_rng(12 + rule)
+    for _ in range(25):
+        n, m = int(rng.integers(1, 8)), int(rng.integers(2, 7))
+        p = rng.integers(1, 99, size=(n, m)).astype(np.int32)
+        opt, _ = orc.brute_force(p)
+        c, perm, st = orc.bnb(p, 0, rule)
+        assert c == opt and st.complete == 1
+        assert sorted(perm.tolist()) == list(range(n))
+        assert orc.makespan(p, perm) == opt
+        assert st.root_lb <= opt
+
+
+def test_bnb_tiny_config_nine_jobs_five_machines(orc):
+    """The 9x5 configuration: DFS optimum equals the minimum over all 9!."""
+    p = I.instance(9, 5, 1000)
+    opt, bperm = orc.brute_force(p)
+    c, perm, st = orc.bnb(p)
+    assert c == opt == orc.makespan(p, perm) == orc.makespan(p, bperm)
+    assert orc.lower_bound(p, []) <= opt <= orc.neh(p)[0]
+
+
+def test_neh_is_a_valid_upper_bound(orc):
+    rng = np.random.default_rng(14)
+    for _ in range(30):
+        n, m = int(rng.integers(1, 8)), int(rng.integers(2, 6))
+        p = rng.integers(1, 99, size=(n, m)).astype(np.int32)
+        c, perm = orc.neh(p)
+        assert sorted(perm.tolist()) == list(range(n))
+        assert orc.makespan(p, perm) == c
+        assert c >= orc.brute_force(p)[0]
+    # two jobs: NEH tries both orders, so it is optimal
+    for _ in range(20):
+        p = rng.integers(1, 99, size=(2, int(rng.integers(2, 6)))).astype(np.int32)
+        assert orc.neh(p)[0] == orc.brute_force(p)[0]
+
+
+def _critical_tree_count(orc, p, opt, rule):
+    """Bounded-node count of any complete search started with UB = opt,
+    enumerated breadth-first: a node is branched iff it is incomplete and
+    kept (LB < opt for rule 0, LB <= opt for rule 1); every child of a
+    branched node is bounded once."""
+    n = p.shape[0]
+    keep = (lambda lb: lb < opt) if rule == 0 else (lambda lb: lb <= opt)
+    count = 1
+    frontier = [[]] if keep(orc.lower_bound(p, [])) else []
+    while frontier:
+        nxt = []
+        for pre in frontier:
+            for j in range(n):
+                if j in pre:
+                    continue
+                child = pre + [j]
+                count += 1
+                if len(child) < n and keep(orc.lower_bound(p, child)):
+                    nxt.append(child)
+        frontier = nxt
+    return count
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_critical_tree_is_order_independent(orc, rule):
+    rng = np.random.default_rng(20 + rule)
+    for _ in range(12):
+        n, m = int(rng.integers(2, 8)), int(rng.integers(2, 6))
+        p = rng.integers(1, 99, size=(n, m)).astype(np.int32)
+        opt, _ = orc.brute_force(p)
+        c, _, st = orc.bnb(p, opt, rule)
+        assert c == opt and st.found == 0 and st.complete == 1
+        assert st.nodes_bounded == _critical_tree_count(orc, p, opt, rule)
+
+
+def test_pool_bounding_matches_single_node_calls(orc):
+    p = I.instance(12, 6, 15)
+    pool = I.random_pool(12, 300, 0, 12, 16)
+    lb1 = orc.bound_pool(p, pool, nthreads=1)
+    lb4 = orc.bound_pool(p, pool, nthreads=4)
+    assert np.array_equal(lb1, lb4)
+    for i in range(0, 300, 7):
+        d = int(pool[i, 0])
+        assert lb1[i] == orc.lower_bound(p, pool[i, 1:1 + d].tolist())
