@@ -1,0 +1,224 @@
+// instance.hip -- loading an instance and building its device tables.
+//
+// The tables are built on the device by three small kernels:
+//   stage_rows   one thread per job: padded p, head sums H, tail sums Q
+//   stage_totals one thread per machine: column totals
+//   stage_pairs  one workgroup per machine pair: every job ranks itself in
+//                Johnson's order for that pair (comparison counting, no sort)
+//                and writes its record at its rank.
+// Johnson's rule with Mitten's lags (the two-machine relaxation of the bound
+// whose O(m^2 n log n) cost is quoted in Sec. V.D): with A = a + lag and
+// B = b + lag, jobs with A < B come first by A ascending, then the others by
+// B descending; equal keys by job id.  Restricting this order to any subset of
+// jobs gives that subset's Johnson order, which is why one table per pair
+// serves every node.
+#include <cstring>
+#include <new>
+
+#include "fsp_internal.hpp"
+
+using namespace fspi;
+
+namespace {
+
+__global__ void stage_rows(const int32_t *__restrict__ p_in, int n, int m,
+                           int mp, int32_t *__restrict__ p,
+                           int32_t *__restrict__ H, int32_t *__restrict__ Q) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int row = 0;
+  for (int k = 0; k < m; ++k) row += p_in[j * m + k];
+  int before = 0;
+  for (int k = 0; k < mp; ++k) {
+    int v = k < m ? p_in[j * m + k] : 0;
+    p[j * mp + k] = v;
+    H[j * mp + k] = k < m ? before : 0;
+    Q[j * mp + k] = k < m ? row - before - v : 0;
+    before += v;
+  }
+}
+
+__global__ void stage_totals(const int32_t *__restrict__ p, int n, int mp,
+                             int32_t *__restrict__ tot) {
+  int k = threadIdx.x;
+  if (k >= mp) return;
+  int s = 0;
+  for (int j = 0; j < n; ++j) s += p[j * mp + k];
+  tot[k] = s;
+}
+
+__global__ __launch_bounds__(256) void stage_pairs(
+    const int32_t *__restrict__ p, int n, int m, int mp, int npad, int wide,
+    void *__restrict__ rec_out) {
+  __shared__ int sA[256], sB[256];
+  const int pi = blockIdx.x;
+  // (k,l) of pair pi in lexicographic order
+  int k = 0, rem = pi;
+  while (rem >= m - 1 - k) {
+    rem -= m - 1 - k;
+    ++k;
+  }
+  const int l = k + 1 + rem;
+  const int j = threadIdx.x;
+  int a = 0, b = 0, lag = 0;
+  if (j < n) {
+    a = p[j * mp + k];
+    b = p[j * mp + l];
+    for (int h = k + 1; h < l; ++h) lag += p[j * mp + h];
+    sA[j] = a + lag;
+    sB[j] = b + lag;
+  }
+  __syncthreads();
+  int pos = j;  // padding slots keep their own index
+  if (j < n) {
+    const int A = a + lag, B = b + lag;
+    const bool first = A < B;
+    int rank = 0;
+    for (int o = 0; o < n; ++o) {
+      const int Ao = sA[o], Bo = sB[o];
+      const bool ofirst = Ao < Bo;
+      bool before;
+      if (ofirst != first)
+        before = ofirst;
+      else if (first)
+        before = Ao < A || (Ao == A && o < j);
+      else
+        before = Bo > B || (Bo == B && o < j);
+      rank += before ? 1 : 0;
+    }
+    pos = rank;
+  }
+  if (j >= npad) return;
+  // Padding records are all-zero: x = 0 and y = 0 leave the pair state
+  // unchanged (see the step in bound.hip).
+  int x = 0, y = 0, job = 0;
+  if (j < n) {
+    x = 256 * (b - a);
+    y = ((lag + b) << 8) | j;
+    job = j;
+  }
+  const size_t slot = (size_t)pi * npad + pos;
+  if (wide)
+    reinterpret_cast<WideRec *>(rec_out)[slot] = make_int4(x, y, job, 0);
+  else
+    reinterpret_cast<NarrowRec *>(rec_out)[slot] = make_int2(x, y);
+}
+
+void free_device(fsp_instance *in) {
+  if (in->d_p) (void)hipFree(in->d_p);
+  if (in->d_H) (void)hipFree(in->d_H);
+  if (in->d_Q) (void)hipFree(in->d_Q);
+  if (in->d_tot) (void)hipFree(in->d_tot);
+  if (in->d_rec) (void)hipFree(in->d_rec);
+  in->d_p = in->d_H = in->d_Q = in->d_tot = nullptr;
+  in->d_rec = nullptr;
+}
+
+int build_tables(fsp_instance *in, const int32_t *p_host) {
+  const int n = in->n, m = in->m, mp = in->mp;
+  const size_t mat = (size_t)n * mp * sizeof(int32_t);
+  if (hipMalloc(&in->d_p, mat) != hipSuccess ||
+      hipMalloc(&in->d_H, mat) != hipSuccess ||
+      hipMalloc(&in->d_Q, mat) != hipSuccess ||
+      hipMalloc(&in->d_tot, mp * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&in->d_rec, in->rec_bytes) != hipSuccess)
+    return FSP_ENOMEM;
+  int32_t *d_in = nullptr;
+  if (hipMalloc(&d_in, (size_t)n * m * sizeof(int32_t)) != hipSuccess)
+    return FSP_ENOMEM;
+  hipStream_t s = nullptr;
+  int rc = FSP_OK;
+  if (hipMemcpy(d_in, p_host, (size_t)n * m * sizeof(int32_t),
+                hipMemcpyHostToDevice) != hipSuccess)
+    rc = FSP_EDEVICE;
+  if (rc == FSP_OK) {
+    hipLaunchKernelGGL(stage_rows, dim3((n + 63) / 64), dim3(64), 0, s, d_in,
+                       n, m, mp, in->d_p, in->d_H, in->d_Q);
+    hipLaunchKernelGGL(stage_totals, dim3(1), dim3(64), 0, s, in->d_p, n, mp,
+                       in->d_tot);
+    hipLaunchKernelGGL(stage_pairs, dim3(in->P), dim3(256), 0, s, in->d_p, n,
+                       m, mp, in->npad, in->wide, in->d_rec);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+      rc = FSP_EDEVICE;
+  }
+  (void)hipFree(d_in);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fsp_status_string(int32_t status) {
+  switch (status) {
+    case FSP_OK: return "ok";
+    case FSP_EINVAL: return "invalid argument";
+    case FSP_ENOMEM: return "out of memory";
+    case FSP_EDEVICE: return "HIP device error";
+    case FSP_EUNSUPPORTED: return "unsupported input for this build";
+    default: return "unknown status";
+  }
+}
+
+int fsp_load_instance(const int32_t *p_host, int32_t n, int32_t m,
+                      fsp_instance **out) {
+  if (!out) return FSP_EINVAL;
+  *out = nullptr;
+  if (!p_host || n < 1 || m < 2) return FSP_EINVAL;
+  if (n > kMaxJobs || m > kMaxMachines) return FSP_EUNSUPPORTED;
+  int64_t total = 0;
+  for (int j = 0; j < n; ++j) {
+    int64_t row = 0;
+    for (int k = 0; k < m; ++k) {
+      const int32_t v = p_host[(size_t)j * m + k];
+      if (v < 0) return FSP_EINVAL;
+      if (v > 32767) return FSP_EUNSUPPORTED;
+      row += v;
+    }
+    if (row > 65535) return FSP_EUNSUPPORTED;
+    total += row;
+  }
+  if (total >= (int64_t(1) << 22)) return FSP_EUNSUPPORTED;
+
+  fsp_instance *in = new (std::nothrow) fsp_instance();
+  if (!in) return FSP_ENOMEM;
+  in->n = n;
+  in->m = m;
+  in->mp = round_up(m, 4);
+  in->P = npairs(m);
+  in->npad = round_up(n, 4);
+  in->wide = n > 32 ? 1 : 0;
+  in->rec_bytes = (size_t)in->P * in->npad *
+                  (in->wide ? sizeof(WideRec) : sizeof(NarrowRec));
+  in->p_host.assign(p_host, p_host + (size_t)n * m);
+  if (hipGetDevice(&in->device) != hipSuccess) {
+    delete in;
+    return FSP_EDEVICE;
+  }
+  int rc = build_tables(in, p_host);
+  if (rc != FSP_OK) {
+    free_device(in);
+    delete in;
+    return rc;
+  }
+  *out = in;
+  return FSP_OK;
+}
+
+int fsp_free_instance(fsp_instance *inst) {
+  if (!inst) return FSP_OK;
+  free_device(inst);
+  delete inst;
+  return FSP_OK;
+}
+
+int fsp_instance_info(const fsp_instance *inst, int32_t *n, int32_t *m,
+                      int32_t *device) {
+  if (!inst) return FSP_EINVAL;
+  if (n) *n = inst->n;
+  if (m) *m = inst->m;
+  if (device) *device = inst->device;
+  return FSP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+"""Python binding of libfsp (the C ABI declared in include/fsp.h).
+
+Argument marshalling only: every step of the bounding path runs in the HIP
+kernels of ``libfsp.so``.  torch provides device memory and streams.  The
+library is loaded after ``import torch`` so that both share one HIP runtime
+(torch's ``libamdhip64.so.7``); if ``libfsp.so`` has not been built, every
+entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfsp.so")
+
+FSP_OK = 0
+FSP_EINVAL = -1
+FSP_ENOMEM = -2
+FSP_EDEVICE = -3
+FSP_EUNSUPPORTED = -4
+FSP_LB_INVALID = -1
+
+_lib = None
+
+
+class FspError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        self.rc = rc
+        super().__init__(f"{what}: {status_string(rc)} ({rc})")
+
+
+class _Nodes(ctypes.Structure):
+    _fields_ = [("inst", ctypes.c_void_p), ("data", ctypes.c_void_p),
+                ("stride", ctypes.c_int32)]
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1206_4973_amd.build`"
+        )
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.fsp_status_string.argtypes = [i32]
+    L.fsp_status_string.restype = ctypes.c_char_p
+    L.fsp_load_instance.argtypes = [P, i32, i32, ctypes.POINTER(P)]
+    L.fsp_load_instance.restype = ctypes.c_int
+    L.fsp_free_instance.argtypes = [P]
+    L.fsp_free_instance.restype = ctypes.c_int
+    L.fsp_instance_info.argtypes = [P, P, P, P]
+    L.fsp_instance_info.restype = ctypes.c_int
+    L.fsp_bound_pool.argtypes = [ctypes.POINTER(_Nodes), i64, P, P]
+    L.fsp_bound_pool.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_string(rc: int) -> str:
+    return lib().fsp_status_string(int(rc)).decode()
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != FSP_OK:
+        raise FspError(rc, what)
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Instance:
+    """An instance loaded on the current device (fsp_load_instance)."""
+
+    def __init__(self, p):
+        if isinstance(p, torch.Tensor):
+            p = p.detach().cpu().numpy()
+        p = np.ascontiguousarray(p, dtype=np.int32)
+        if p.ndim != 2:
+            raise ValueError("p must be a [n, m] matrix")
+        self.p = p
+        self.n, self.m = int(p.shape[0]), int(p.shape[1])
+        h = ctypes.c_void_p()
+        _check(lib().fsp_load_instance(p.ctypes.data_as(ctypes.c_void_p), self.n, self.m,
+                                       ctypes.byref(h)), "fsp_load_instance")
+        self._h = h
+        dev = ctypes.c_int32()
+        _check(lib().fsp_instance_info(h, None, None, ctypes.byref(dev)), "fsp_instance_info")
+        self.device = torch.device("cuda", dev.value)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise ValueError("instance is closed")
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().fsp_free_instance(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bound_pool(self, nodes: torch.Tensor, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+        """Bounds of a ``uint8 [count, stride]`` device pool (fsp_bound_pool).
+
+        Asynchronous on ``stream`` (default: torch's current stream)."""
+        if nodes.dtype != torch.uint8 or nodes.dim() != 2 or not nodes.is_cuda:
+            raise ValueError("nodes must be a uint8 [count, stride] device tensor")
+        if nodes.stride(1) != 1:
+            raise ValueError("records must be contiguous")
+        count, stride = int(nodes.shape[0]), int(nodes.stride(0))
+        if out is None:
+            out = torch.empty(count, dtype=torch.int32, device=nodes.device)
+        if out.dtype != torch.int32 or out.numel() < count or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 device tensor of >= count")
+        desc = _Nodes(self.handle.value, nodes.data_ptr(), stride)
+        _check(lib().fsp_bound_pool(ctypes.byref(desc), count,
+                                    ctypes.c_void_p(out.data_ptr()),
+                                    _stream_handle(stream)), "fsp_bound_pool")
+        return out

@@ -1,0 +1,89 @@
+"""The C ABI library on the CPU: it loads, exports every symbol that
+include/*.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1206_4973_amd", "libfsp.so")
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \t\*]*?\b(fsp_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(LIB):
+        pytest.fail("libfsp.so is not built (python -m paper_1206_4973_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for want in ("fsp_load_instance", "fsp_free_instance", "fsp_bound_pool",
+                 "fsp_status_string", "fsp_instance_info"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings(L):
+    L.fsp_status_string.restype = ctypes.c_char_p
+    for rc, word in ((0, b"ok"), (-1, b"invalid"), (-2, b"memory"), (-3, b"HIP"),
+                     (-4, b"unsupported"), (-99, b"unknown")):
+        assert word in L.fsp_status_string(rc)
+
+
+def _load(L, p, n=None, m=None):
+    L.fsp_load_instance.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    h = ctypes.c_void_p()
+    n = p.shape[0] if n is None else n
+    m = p.shape[1] if m is None else m
+    ptr = p.ctypes.data_as(ctypes.c_void_p) if p is not None else None
+    return L.fsp_load_instance(ptr, n, m, ctypes.byref(h)), h
+
+
+def test_load_rejects_bad_arguments_without_a_device(L):
+    p = np.ones((5, 4), np.int32)
+    assert _load(L, p, n=0)[0] == -1
+    assert _load(L, p, m=1)[0] == -1
+    assert _load(L, np.ones((5, 21), np.int32))[0] == -4         # m above 20
+    assert _load(L, np.ones((256, 4), np.int32))[0] == -4        # n above 255
+    q = p.copy(); q[2, 1] = -3
+    assert _load(L, q)[0] == -1                                   # negative time
+    q = p.copy(); q[2, 1] = 40000
+    assert _load(L, q)[0] == -4                                   # time above 32767
+    q = np.full((3, 4), 20000, np.int32)
+    assert _load(L, q)[0] == -4                                   # job total above 65535
+    L.fsp_load_instance.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_void_p]
+    assert L.fsp_load_instance(p.ctypes.data_as(ctypes.c_void_p), 5, 4, None) == -1
+    h = ctypes.c_void_p()
+    L.fsp_load_instance.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    assert L.fsp_load_instance(None, 5, 4, ctypes.byref(h)) == -1
+
+
+def test_other_entry_points_reject_null(L):
+    L.fsp_free_instance.argtypes = [ctypes.c_void_p]
+    assert L.fsp_free_instance(None) == 0
+    L.fsp_instance_info.argtypes = [ctypes.c_void_p] * 4
+    assert L.fsp_instance_info(None, None, None, None) == -1
+    L.fsp_bound_pool.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                 ctypes.c_void_p]
+    assert L.fsp_bound_pool(None, 10, None, None) == -1

@@ -1,0 +1,180 @@
+"""Parity of the HIP pool-bounding kernel with the CPU oracle, through the C ABI.
+
+Bounds are integers: every comparison is bit-exact.  Small pools span several
+256-node tiles and a ragged tail and are compared element by element; the
+full-size pools (2^22 nodes, the size the benchmark times) are compared on a
+random sample of nodes plus properties that hold for every node.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1206_4973_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 2), (2, 2), (3, 3), (5, 4), (9, 5), (16, 7), (20, 5), (20, 10), (20, 20),
+          (31, 20), (32, 20), (32, 3), (33, 20), (50, 5), (50, 10), (50, 20), (64, 13),
+          (100, 5), (100, 10), (100, 20), (200, 20), (255, 20), (255, 2)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fsp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1206_4973_amd import fsp as F
+    F.lib()  # raises if the library is missing
+    return F
+
+
+def gpu_bounds(F, inst, pool, stream=None):
+    t = torch.from_numpy(np.ascontiguousarray(pool)).cuda()
+    out = inst.bound_pool(t, stream=stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_tiny_config_pool(fsp, orc):
+    """9 jobs x 5 machines, 4096 nodes of depth 0..8."""
+    p = I.instance(9, 5, 1000)
+    pool = I.random_pool(9, 4096, 0, 8, 1000 + 500000)
+    say("tiny config: 4096 nodes, n=9 m=5")
+    inst = fsp.Instance(p)
+    got = gpu_bounds(fsp, inst, pool)
+    want = orc.bound_pool(p, pool, nthreads=8)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n,m", SHAPES, ids=[f"{n}x{m}" for n, m in SHAPES])
+def test_shapes_bit_exact(fsp, orc, n, m):
+    count = 1537 if n <= 100 else 600  # several tiles and a ragged tail
+    p = I.instance(n, m, 7000 + 31 * n + m)
+    pool = I.random_pool(n, count, 0, n, 8000 + 31 * n + m)
+    say(f"shape n={n} m={m}: {count} nodes")
+    inst = fsp.Instance(p)
+    got = gpu_bounds(fsp, inst, pool)
+    want = orc.bound_pool(p, pool, nthreads=8)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad[:10], got[bad[:10]], want[bad[:10]])
+
+
+def test_zero_times_and_ties(fsp, orc):
+    """Zero processing times and many equal keys (Johnson ties)."""
+    rng = np.random.default_rng(3)
+    for n, m in ((12, 6), (40, 9)):
+        p = rng.integers(0, 3, size=(n, m)).astype(np.int32)
+        pool = I.random_pool(n, 900, 0, n, 4 + n)
+        inst = fsp.Instance(p)
+        assert np.array_equal(gpu_bounds(fsp, inst, pool), orc.bound_pool(p, pool, 8))
+
+
+def test_identical_jobs_and_two_machines(fsp, orc):
+    c = np.array([5, 9, 2, 7], np.int32)
+    p = np.tile(c, (10, 1))
+    inst = fsp.Instance(p)
+    root = I.records([[]], 10)
+    assert gpu_bounds(fsp, inst, root)[0] == c.sum() + 9 * c.max()
+    p2 = I.instance(7, 2, 99)
+    pool = I.random_pool(7, 300, 0, 7, 98)
+    inst2 = fsp.Instance(p2)
+    got = gpu_bounds(fsp, inst2, pool)
+    for i in range(0, 300, 11):
+        d = int(pool[i, 0])
+        assert got[i] == orc.best_completion(p2, pool[i, 1:1 + d].tolist())
+
+
+def test_malformed_nodes(fsp, orc):
+    for n in (20, 60):
+        p = I.instance(n, 8, 5 + n)
+        recs = I.random_pool(n, 300, 0, n, 6 + n)
+        recs[3, 0] = n + 1                    # depth > n
+        recs[7, 0] = max(2, recs[7, 0]); recs[7, 2] = recs[7, 1]   # duplicate
+        recs[11, 0] = max(1, recs[11, 0]); recs[11, 1] = n         # id == n
+        recs[13, 0] = max(1, recs[13, 0]); recs[13, 1] = 255       # id 255
+        recs[17, 0] = 255                     # depth 255
+        inst = fsp.Instance(p)
+        got = gpu_bounds(fsp, inst, recs)
+        want = orc.bound_pool(p, recs, 8)
+        assert np.array_equal(got, want)
+        for i in (3, 7, 11, 13, 17):
+            assert got[i] == -1
+
+
+def test_count_zero_and_argument_errors(fsp):
+    inst = fsp.Instance(I.instance(8, 4, 1))
+    empty = torch.zeros((0, 16), dtype=torch.uint8, device="cuda")
+    out = inst.bound_pool(empty)
+    assert out.numel() == 0
+    short = torch.zeros((4, 8), dtype=torch.uint8, device="cuda")  # stride < n+1
+    with pytest.raises(fsp.FspError):
+        inst.bound_pool(short)
+
+
+def test_unaligned_records(fsp, orc):
+    """stride = n+1 (not a multiple of 16) and a base address offset by 1."""
+    n, m = 20, 20
+    p = I.instance(n, m, 2000)
+    pool = I.random_pool(n, 1001, 1, 19, 2001, stride=n + 1)
+    inst = fsp.Instance(p)
+    flat = torch.zeros(1 + pool.size, dtype=torch.uint8, device="cuda")
+    flat[1:] = torch.from_numpy(pool.reshape(-1)).cuda()
+    view = flat[1:].view(1001, n + 1)
+    out = inst.bound_pool(view)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), orc.bound_pool(p, pool, 8))
+
+
+def test_non_default_stream_and_reuse(fsp, orc):
+    n, m = 20, 10
+    p = I.instance(n, m, 4000)
+    inst = fsp.Instance(p)
+    s = torch.cuda.Stream()
+    pools = [I.random_pool(n, 5000 + 7 * i, 1, 19, 4100 + i) for i in range(3)]
+    with torch.cuda.stream(s):
+        outs = [inst.bound_pool(torch.from_numpy(q).cuda(), stream=s) for q in pools]
+    s.synchronize()
+    for q, o in zip(pools, outs):
+        assert np.array_equal(o.cpu().numpy(), orc.bound_pool(p, q, 8))
+
+
+def test_branching_shaped_pool(fsp, orc):
+    n, m = 20, 20
+    p = I.instance(n, m, 2000)
+    pool = I.sibling_pool(n, 150, 0, n - 1, 2002)
+    inst = fsp.Instance(p)
+    assert np.array_equal(gpu_bounds(fsp, inst, pool), orc.bound_pool(p, pool, 8))
+
+
+FULL = [(20, 20, 2000, 1, 19), (50, 20, 5000, 1, 49), (200, 20, 5001, 1, 199)]
+
+
+@pytest.mark.parametrize("n,m,seed,dlo,dhi", FULL, ids=["20x20", "50x20", "200x20"])
+def test_full_size_pool_sampled(fsp, orc, n, m, seed, dlo, dhi):
+    """2^22-node pools (one GPU's share): a random sample is compared with the
+    oracle node by node; every node must bound at least the root's bound
+    (the bound never decreases along a branch) and none may be invalid."""
+    count = 1 << 22
+    say(f"full size n={n} m={m}: generating {count} nodes")
+    p = I.instance(n, m, seed)
+    pool = I.random_pool(n, count, dlo, dhi, seed + 500000)
+    inst = fsp.Instance(p)
+    say("  bounding on the GPU")
+    got = gpu_bounds(fsp, inst, pool)
+    rng = np.random.default_rng(seed)
+    k = 4096 if n <= 50 else 512
+    idx = np.sort(rng.choice(count, size=k, replace=False))
+    say(f"  oracle on {k} sampled nodes")
+    want = orc.bound_pool(p, pool[idx], nthreads=8)
+    assert np.array_equal(got[idx], want)
+    root = orc.lower_bound(p, [])
+    assert got.min() >= root
+    # the last records of the pool
+    tail = np.arange(count - 37, count)
+    assert np.array_equal(got[tail], orc.bound_pool(p, pool[tail], nthreads=8))
