@@ -70,10 +70,13 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2-pool", type=int, default=22)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy 5 times (the reference "
+                         "kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the pool "
-              "bounding path is sharded across GPUs only by design, see DESIGN.md",
+              "bounding path shards across GPUs only by design",
               file=sys.stderr)
         return 2
 
@@ -81,6 +84,14 @@ def main() -> int:
     from paper_1206_4973_amd import fsp, inputs
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 1 << 28, "launches": 5}))
+        return 0
     n, m, seed = 20, 20, 2000
     count = 1 << args.log2_pool
     p = inputs.instance(n, m, seed)

@@ -105,6 +105,81 @@ typedef struct {
 int fsp_bound_pool(const fsp_nodes *nodes, int64_t count, int32_t *lb_out,
                    void *stream);
 
+/* ---- branch-and-bound (Sec. II.A operators, Sec. III pool loop) --------- */
+
+/* Pool-size policies.  FSP_POOL_FIXED: every pool has fixed_pool children.
+ * FSP_POOL_ADAPTIVE: the paper's dynamic parameter tuning (Algorithm 1): start
+ * at 256 threads x #compute units, double every nb_iterations pools while the
+ * size stays within the device's resident-thread maximum, keeping the size
+ * with the best measured efficiency (nodes bounded per second), then try the
+ * midpoints around the best size for nb_iterations pools each and keep the
+ * best for the rest of the run. */
+#define FSP_POOL_FIXED 0
+#define FSP_POOL_ADAPTIVE 1
+#define FSP_POOL_AUTOTUNED 2
+#define FSP_POOL_LEARNED 3
+
+/* Elimination rule (Sec. II.A eliminates a node whose bound is greater than
+ * the best makespan known).  FSP_PRUNE_GE (default) also eliminates a bound
+ * equal to it, since such a node cannot hold a strictly better schedule;
+ * FSP_PRUNE_GT keeps it, as the paper's wording does.  The optimum is the same
+ * under both; the number of nodes explored differs. */
+#define FSP_PRUNE_GE 0
+#define FSP_PRUNE_GT 1
+
+typedef struct {
+  int32_t kind;           /* FSP_POOL_*                                      */
+  int32_t nb_iterations;  /* pools per measurement/batch; <= 0: 10          */
+  int64_t fixed_pool;     /* FSP_POOL_FIXED: children per pool (>= 1)      */
+  int64_t max_pool;       /* largest pool; <= 0: resident threads of the
+                             device.  Sizes the device buffers: about
+                             n * (max_pool + n) * stride bytes of HBM.     */
+  double time_limit_s;    /* stop after this wall time; <= 0: no limit     */
+  int32_t prune_rule;     /* FSP_PRUNE_GE or FSP_PRUNE_GT                  */
+  int32_t reserved;
+  const void *model;      /* FSP_POOL_LEARNED: the policy network          */
+  const char *log_path;   /* one JSON line per batch of pools; NULL: none  */
+} fsp_pool_policy;
+
+typedef struct {
+  int32_t makespan;   /* min(initial UB, best schedule found)               */
+  int32_t found;      /* 1 if a schedule better than the initial UB was found */
+  uint8_t *perm;      /* caller's HOST buffer of n bytes (may be NULL): the
+                         best schedule when found == 1, or the NEH schedule
+                         when ub_in <= 0; untouched meaning otherwise       */
+  int32_t status;     /* 0: optimum proven (tree exhausted); 1: time limit */
+  int32_t root_lb;    /* bound of the root                                  */
+  int64_t nodes_bounded;   /* bound evaluations, root included             */
+  int64_t nodes_branched;  /* nodes whose children were generated           */
+  int64_t nodes_pruned;    /* nodes eliminated (children and stale parents) */
+  int64_t leaves;          /* complete schedules bounded                    */
+  int64_t pools;           /* pools bounded                                 */
+  double t_found_s;   /* wall time when the final UB was found (0 if none) */
+  double t_total_s;   /* wall time of the whole call                        */
+  int64_t final_pool; /* pool size in force at the end                      */
+} fsp_result;
+
+/*
+ * fsp_branch_and_bound -- exact minimum makespan of the instance (Sec. II:
+ * branching appends one unscheduled job, bounding is the pool kernel,
+ * selection takes the deepest pending nodes, elimination drops nodes that
+ * cannot beat UB; Sec. III: pools are bounded in one launch each).
+ *   ub_in > 0 : initial UB (e.g. a known optimum: then only the nodes whose
+ *               bound is below it are explored, whatever the order);
+ *   ub_in <= 0: initial UB from the NEH insertion heuristic.
+ * Synchronous; allocates and frees its own device memory and stream.  With
+ * status 0 the returned makespan is optimal.  FSP_EUNSUPPORTED for the
+ * FSP_POOL_AUTOTUNED / FSP_POOL_LEARNED kinds when this build lacks them.
+ */
+int fsp_branch_and_bound(const fsp_instance *inst,
+                         const fsp_pool_policy *policy, int32_t ub_in,
+                         fsp_result *out);
+
+/* NEH insertion heuristic (host): jobs by total time descending (ties by
+ * id), each inserted where the partial makespan is smallest (earliest
+ * position on ties).  perm_out: host buffer of n bytes (may be NULL). */
+int fsp_neh(const fsp_instance *inst, uint8_t *perm_out, int32_t *makespan_out);
+
 #ifdef __cplusplus
 }
 #endif

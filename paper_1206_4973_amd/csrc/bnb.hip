@@ -1,0 +1,594 @@
+// bnb.hip -- device-resident branch-and-bound around the pool-bounding kernel.
+//
+// The paper's loop (Sec. III, Fig. 2): select a pool of pending nodes,
+// deepest first; branch them; bound every child in one launch; eliminate the
+// children that cannot beat the best known schedule; repeat until no node is
+// pending.  Here every step stays on the device; the host only chooses the
+// pool size and reads back a few counters once per batch of pools.
+//
+// Pending nodes live in one bucket per depth (records + their bounds), in
+// HBM.  Selection takes the last K nodes of the deepest non-empty bucket
+// (LIFO inside a bucket).  Because the children of depth-d parents all go to
+// bucket d+1, and bucket d is only branched when every deeper bucket is empty,
+// a bucket never receives more than one pool of children while it is
+// non-empty, which bounds its size by the largest pool.
+//
+// One iteration = four launches, all sized from a device descriptor so that
+// the sequence can be queued back-to-back (or captured once and replayed):
+//   plan    1 thread: commit the best leaf of the previous pool, pick the
+//           depth and the number of parents, or flag the search as done;
+//   branch  one lane per (parent, child slot): a parent whose bound can no
+//           longer beat UB is eliminated (lazy re-check, Sec. II.A); the others
+//           append their unscheduled jobs in ascending id (Sec. II.B: one son
+//           per unscheduled job); children are compacted with a wave ballot;
+//   bound   the pool-bounding kernel, count read from the descriptor;
+//   prune   one lane per child: leaves propose themselves as the new best
+//           (64-bit atomic min of (makespan, index)); other children that can
+//           still beat UB are compacted into the next bucket.
+// Elimination compares with the UB in force when the pool was selected (the
+// paper eliminates after the whole pool has been bounded, Sec. III).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fsp_internal.hpp"
+#include "bnb.hpp"
+
+using namespace fspi;
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ bool keeps(int rule, int lb, int ub) {
+  return rule == FSP_PRUNE_GT ? lb <= ub : lb < ub;
+}
+
+// Wave-level compaction: returns this lane's slot in an array whose length
+// counter is *counter (one atomic per wave).  Only lanes with pred get a slot.
+__device__ __forceinline__ int wave_slot(bool pred, int32_t *counter) {
+  const uint64_t mask = __ballot(pred);
+  const int lane = __lane_id();
+  const uint64_t below = lane == 0 ? 0ull : (mask & ((~0ull) >> (64 - lane)));
+  const int rank = __popcll(below);
+  const uint64_t act = __ballot(1);
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  int base = 0;
+  if (lane == leader && mask) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  return base + rank;
+}
+
+__device__ __forceinline__ void wave_add(int64_t *counter, bool pred) {
+  const uint64_t mask = __ballot(pred);
+  const uint64_t act = __ballot(1);
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  if (__lane_id() == leader && mask)
+    atomicAdd(reinterpret_cast<unsigned long long *>(counter),
+              (unsigned long long)__popcll(mask));
+}
+
+// ---- plan ------------------------------------------------------------------
+__global__ void plan_kernel(BnbDesc *D, int32_t *bcount, const uint8_t *pool,
+                            uint8_t *best_perm, int n, int stride,
+                            const int64_t *target_dev, int commit_only) {
+  if (threadIdx.x != 0) return;
+  // commit the best leaf of the previous pool
+  const uint64_t key = D->best_key;
+  if (key != ~0ull) {
+    const int mk = (int)(key >> 32);
+    const uint32_t idx = (uint32_t)(key & 0xffffffffu);
+    if (mk < D->ub) {
+      D->ub = mk;
+      const uint8_t *rec = pool + (size_t)idx * stride;
+      for (int i = 0; i < n; ++i) best_perm[i] = rec[1 + i];
+      D->found = 1;
+      D->improved = 1;
+    }
+    D->best_key = ~0ull;
+  }
+  D->children = 0;
+  D->active = 0;
+  D->parents = 0;
+  if (D->overflow) D->done = 1;
+  if (commit_only || D->done) return;
+  int d = n - 1;
+  while (d >= 0 && bcount[d] == 0) --d;
+  if (d < 0) {
+    D->done = 1;
+    return;
+  }
+  const int u = n - d;
+  const int64_t target = *target_dev;
+  int64_t k = target / u;
+  if (k < 1) k = 1;
+  if (k > bcount[d]) k = bcount[d];
+  D->depth = d;
+  D->parents = (int)k;
+  D->parent_base = bcount[d] - (int)k;
+  bcount[d] -= (int)k;
+  D->active = 1;
+  D->pools += 1;
+}
+
+// ---- branch ----------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void branch_kernel(
+    BnbDesc *D, const uint8_t *__restrict__ bnodes,
+    const int32_t *__restrict__ blb, uint8_t *__restrict__ pool, int n,
+    int stride, int64_t cap, int rule) {
+  if (!D->active) return;
+  const int d = D->depth, u = n - d, K = D->parents, base = D->parent_base;
+  const int ub = D->ub;
+  const int64_t total = (int64_t)K * u;
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+  // iterate so that every wave of the grid takes part in each round
+  for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < total; r0 += gsz) {
+    const int64_t slot = r0 + threadIdx.x;
+    const bool in = slot < total;
+    int p = 0, c = 0;
+    bool live = false;
+    const uint8_t *prec = nullptr;
+    if (in) {
+      p = base + (int)(slot / u);
+      c = (int)(slot % u);
+      const int64_t at = (int64_t)d * cap + p;
+      prec = bnodes + at * stride;
+      live = keeps(rule, blb[at], ub);
+    }
+    wave_add(&D->nodes_branched, in && c == 0 && live);
+    wave_add(&D->nodes_pruned, in && c == 0 && !live);
+    const int pos = wave_slot(live, &D->children);
+    if (!live) continue;
+    // c-th unscheduled job of the parent, in ascending id
+    uint32_t used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < d; ++i) {
+      const int j = prec[1 + i];
+      used[j >> 5] |= 1u << (j & 31);
+    }
+    int job = -1, left = c;
+    for (int w = 0; w < 8 && job < 0; ++w) {
+      const int lo = w * 32;
+      if (lo >= n) break;
+      uint32_t freew = ~used[w];
+      if (n - lo < 32) freew &= (1u << (n - lo)) - 1u;
+      const int cnt = __popc(freew);
+      if (left < cnt) {
+        for (int t = 0; t < left; ++t) freew &= freew - 1u;
+        job = lo + __ffs(freew) - 1;
+      } else {
+        left -= cnt;
+      }
+    }
+    uint8_t *crec = pool + (size_t)pos * stride;
+    const uint4 *src = reinterpret_cast<const uint4 *>(prec);
+    uint4 *dst = reinterpret_cast<uint4 *>(crec);
+    for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
+    crec[0] = (uint8_t)(d + 1);
+    crec[1 + d] = (uint8_t)job;
+  }
+}
+
+// ---- prune + compaction ----------------------------------------------------
+__global__ __launch_bounds__(kThreads) void prune_kernel(
+    BnbDesc *D, const uint8_t *__restrict__ pool,
+    const int32_t *__restrict__ pool_lb, uint8_t *__restrict__ bnodes,
+    int32_t *__restrict__ blb, int32_t *__restrict__ bcount, int n, int stride,
+    int64_t cap, int rule) {
+  if (!D->active) return;
+  const int total = D->children;
+  const int d1 = D->depth + 1;
+  const int ub = D->ub;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    atomicAdd(reinterpret_cast<unsigned long long *>(&D->nodes_bounded),
+              (unsigned long long)total);
+  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < total; r0 += gsz) {
+    const int64_t i = r0 + threadIdx.x;
+    const bool in = i < total;
+    const int lb = in ? pool_lb[i] : 0;
+    const bool leaf = in && d1 == n;
+    const bool keep = in && !leaf && keeps(rule, lb, ub);
+    wave_add(&D->leaves, leaf);
+    wave_add(&D->nodes_pruned, in && !keep && !(leaf && lb < ub));
+    if (leaf && lb < ub) {
+      const uint64_t key = ((uint64_t)(uint32_t)lb << 32) | (uint64_t)i;
+      atomicMin(reinterpret_cast<unsigned long long *>(&D->best_key),
+                (unsigned long long)key);
+    }
+    const int pos = wave_slot(keep, &bcount[d1]);
+    if (!keep) continue;
+    if (pos >= cap) {
+      D->overflow = 1;
+      continue;
+    }
+    const int64_t at = (int64_t)d1 * cap + pos;
+    const uint4 *src = reinterpret_cast<const uint4 *>(pool + (size_t)i * stride);
+    uint4 *dst = reinterpret_cast<uint4 *>(bnodes + at * stride);
+    for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
+    blb[at] = lb;
+  }
+}
+
+// seed: place the root in bucket 0 if it can beat UB; count its bound
+__global__ void seed_kernel(BnbDesc *D, const int32_t *root_lb,
+                            uint8_t *bnodes, int32_t *blb, int32_t *bcount,
+                            int stride, int rule) {
+  if (threadIdx.x != 0) return;
+  D->nodes_bounded += 1;
+  D->root_lb = *root_lb;
+  if (keeps(rule, *root_lb, D->ub)) {
+    for (int i = 0; i < stride; ++i) bnodes[i] = 0;
+    blb[0] = *root_lb;
+    bcount[0] = 1;
+  } else {
+    D->nodes_pruned += 1;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+namespace fspi {
+
+int64_t neh_host(const std::vector<int32_t> &p, int n, int m,
+                 std::vector<uint8_t> &perm) {
+  // NEH insertion: jobs by total work (descending, ties by id), each inserted
+  // at the position giving the smallest partial makespan (earliest on ties).
+  std::vector<int> order(n);
+  std::vector<int64_t> tot(n, 0);
+  for (int j = 0; j < n; ++j) {
+    order[j] = j;
+    for (int k = 0; k < m; ++k) tot[j] += p[(size_t)j * m + k];
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return tot[a] > tot[b]; });
+  std::vector<int> seq;
+  std::vector<int64_t> c(m);
+  auto span = [&](const std::vector<int> &s) {
+    std::fill(c.begin(), c.end(), 0);
+    for (int x : s) {
+      c[0] += p[(size_t)x * m];
+      for (int k = 1; k < m; ++k) c[k] = std::max(c[k], c[k - 1]) + p[(size_t)x * m + k];
+    }
+    return c[m - 1];
+  };
+  seq.push_back(order[0]);
+  std::vector<int> trial;
+  for (int a = 1; a < n; ++a) {
+    int best_pos = 0;
+    int64_t best = -1;
+    for (int pos = 0; pos <= (int)seq.size(); ++pos) {
+      trial = seq;
+      trial.insert(trial.begin() + pos, order[a]);
+      const int64_t v = span(trial);
+      if (best < 0 || v < best) {
+        best = v;
+        best_pos = pos;
+      }
+    }
+    seq.insert(seq.begin() + best_pos, order[a]);
+  }
+  perm.assign(seq.begin(), seq.end());
+  return span(seq);
+}
+
+int BnbState::init(const fsp_instance *inst_, int64_t max_pool, int rule_) {
+  inst = inst_;
+  n = inst->n;
+  stride = round_up(n + 1, 16);
+  rule = rule_;
+  cap = max_pool + n;
+  const size_t bbytes = (size_t)n * cap * stride;
+  if (hipMalloc(&bnodes, bbytes) != hipSuccess ||
+      hipMalloc(&blb, (size_t)n * cap * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&bcount, (size_t)n * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&pool, (size_t)cap * stride) != hipSuccess ||
+      hipMalloc(&pool_lb, (size_t)cap * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&desc, sizeof(BnbDesc)) != hipSuccess ||
+      hipMalloc(&best_perm, 256) != hipSuccess ||
+      hipMalloc(&target_dev, sizeof(int64_t)) != hipSuccess ||
+      hipHostMalloc(&host_desc, sizeof(BnbDesc), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc(&host_target, sizeof(int64_t), hipHostMallocDefault) !=
+          hipSuccess)
+    return FSP_ENOMEM;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FSP_EDEVICE;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+      hipSuccess)
+    return FSP_EDEVICE;
+  if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
+    return FSP_EDEVICE;
+  return FSP_OK;
+}
+
+void BnbState::release() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  if (bnodes) (void)hipFree(bnodes);
+  if (blb) (void)hipFree(blb);
+  if (bcount) (void)hipFree(bcount);
+  if (pool) (void)hipFree(pool);
+  if (pool_lb) (void)hipFree(pool_lb);
+  if (desc) (void)hipFree(desc);
+  if (best_perm) (void)hipFree(best_perm);
+  if (target_dev) (void)hipFree(target_dev);
+  if (host_desc) (void)hipHostFree(host_desc);
+  if (host_target) (void)hipHostFree(host_target);
+  if (stream) (void)hipStreamDestroy(stream);
+  *this = BnbState();
+}
+
+int BnbState::start(int32_t ub0, const std::vector<uint8_t> &perm0) {
+  BnbDesc h{};
+  h.ub = ub0;
+  h.best_key = ~0ull;
+  FSP_HIP_TRY(hipMemcpyAsync(desc, &h, sizeof(h), hipMemcpyHostToDevice, stream));
+  FSP_HIP_TRY(hipMemsetAsync(bcount, 0, (size_t)n * sizeof(int32_t), stream));
+  std::vector<uint8_t> bp(256, 0);
+  std::copy(perm0.begin(), perm0.end(), bp.begin());
+  FSP_HIP_TRY(hipMemcpyAsync(best_perm, bp.data(), 256, hipMemcpyHostToDevice, stream));
+  // bound the root: an all-zero record in the pool buffer
+  FSP_HIP_TRY(hipMemsetAsync(pool, 0, stride, stream));
+  int rc = launch_bound(inst, pool, stride, 1, pool_lb, stream, nullptr);
+  if (rc != FSP_OK) return rc;
+  hipLaunchKernelGGL(seed_kernel, dim3(1), dim3(64), 0, stream, desc, pool_lb,
+                     bnodes, blb, bcount, stride, rule);
+  FSP_HIP_TRY(hipGetLastError());
+  FSP_HIP_TRY(hipStreamSynchronize(stream));
+  return FSP_OK;
+}
+
+int BnbState::set_target(int64_t target) {
+  *host_target = target;
+  FSP_HIP_TRY(hipMemcpyAsync(target_dev, host_target, sizeof(int64_t),
+                             hipMemcpyHostToDevice, stream));
+  return FSP_OK;
+}
+
+int BnbState::enqueue_iteration() {
+  const int grid = std::max(1, std::min<int>(cus * 4, (int)((cap + kThreads - 1) / kThreads)));
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(64), 0, stream, desc, bcount,
+                     pool, best_perm, n, stride, target_dev, 0);
+  hipLaunchKernelGGL(branch_kernel, dim3(grid), dim3(kThreads), 0, stream, desc,
+                     bnodes, blb, pool, n, stride, cap, rule);
+  FSP_HIP_TRY(hipGetLastError());
+  int rc = launch_bound(inst, pool, stride, cap, pool_lb, stream, &desc->children);
+  if (rc != FSP_OK) return rc;
+  hipLaunchKernelGGL(prune_kernel, dim3(grid), dim3(kThreads), 0, stream, desc,
+                     pool, pool_lb, bnodes, blb, bcount, n, stride, cap, rule);
+  FSP_HIP_TRY(hipGetLastError());
+  return FSP_OK;
+}
+
+int BnbState::commit() {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(64), 0, stream, desc, bcount,
+                     pool, best_perm, n, stride, target_dev, 1);
+  FSP_HIP_TRY(hipGetLastError());
+  return FSP_OK;
+}
+
+int BnbState::read_desc() {
+  FSP_HIP_TRY(hipMemcpyAsync(host_desc, desc, sizeof(BnbDesc),
+                             hipMemcpyDeviceToHost, stream));
+  FSP_HIP_TRY(hipStreamSynchronize(stream));
+  return FSP_OK;
+}
+
+// ---- pool-size policies (host) ---------------------------------------------
+
+// The paper's dynamic parameter tuning (Algorithm 1, Sec. III): start with
+// threads-per-block x #multiprocessors; every nb_iterations pools measure the
+// efficiency (nodes bounded per second of the batch) and double the number of
+// blocks while threads x blocks stays within the device's resident-thread
+// maximum; then search around the best size (lower and upper midpoints of
+// [best/2, 2 best], two rounds) and keep the best for the rest of the run.
+void AdaptivePolicy::init(int threads_per_block, int cus, int64_t max_threads,
+                          int64_t max_pool) {
+  nb_threads = threads_per_block;
+  nb_blocks = cus;
+  max_nb_threads = std::min<int64_t>(max_threads, max_pool);
+  phase = 0;
+  best_eff = -1.0;
+  best_size = (int64_t)nb_threads * nb_blocks;
+  current = best_size;
+  if (current > max_nb_threads) current = max_nb_threads;
+  lo = hi = 0;
+  rounds = 0;
+  trial = 0;
+}
+
+int64_t AdaptivePolicy::round_pool(double x) const {
+  int64_t v = (int64_t)std::llround(x / nb_threads) * nb_threads;
+  if (v < nb_threads) v = nb_threads;
+  if (v > max_nb_threads) v = max_nb_threads;
+  return v;
+}
+
+void AdaptivePolicy::observe(double efficiency) {
+  if (phase == 2) return;  // frozen
+  const bool improved = efficiency > best_eff;
+  if (improved) {
+    best_eff = efficiency;
+    best_size = current;
+  }
+  if (phase == 0) {
+    const int64_t next = (int64_t)nb_threads * nb_blocks * 2;
+    if (next <= max_nb_threads) {
+      nb_blocks *= 2;
+      current = next;
+      return;
+    }
+    // doubling reached the device maximum: search around the best size
+    phase = 1;
+    lo = best_size / 2;
+    hi = best_size * 2;
+    rounds = 0;
+    trial = 0;
+  }
+  if (phase == 1) {
+    // trials alternate: lower midpoint, upper midpoint; after both, narrow
+    // the interval around the best and start a new round
+    if (trial == 2) {
+      lo = std::max<int64_t>(lo, (lo + best_size) / 2);
+      hi = std::min<int64_t>(hi, (best_size + hi) / 2);
+      trial = 0;
+      ++rounds;
+    }
+    if (rounds >= 2) {
+      phase = 2;
+      current = best_size;
+      return;
+    }
+    const double mid = trial == 0 ? 0.5 * (double)(lo + best_size)
+                                  : 0.5 * (double)(best_size + hi);
+    current = round_pool(mid);
+    ++trial;
+  }
+}
+
+}  // namespace fspi
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int fsp_neh(const fsp_instance *inst, uint8_t *perm_out, int32_t *makespan_out) {
+  if (!inst) return FSP_EINVAL;
+  std::vector<uint8_t> perm;
+  const int64_t c = neh_host(inst->p_host, inst->n, inst->m, perm);
+  if (perm_out) std::copy(perm.begin(), perm.end(), perm_out);
+  if (makespan_out) *makespan_out = (int32_t)c;
+  return FSP_OK;
+}
+
+int fsp_branch_and_bound(const fsp_instance *inst, const fsp_pool_policy *policy,
+                         int32_t ub_in, fsp_result *out) {
+  if (!inst || !policy || !out) return FSP_EINVAL;
+  if (policy->prune_rule != FSP_PRUNE_GE && policy->prune_rule != FSP_PRUNE_GT)
+    return FSP_EINVAL;
+  if (policy->kind != FSP_POOL_FIXED && policy->kind != FSP_POOL_ADAPTIVE)
+    return FSP_EUNSUPPORTED;
+  if (policy->kind == FSP_POOL_FIXED && policy->fixed_pool < 1) return FSP_EINVAL;
+  uint8_t *user_perm = out->perm;
+  const auto t_start = std::chrono::steady_clock::now();
+  auto elapsed = [&] {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start)
+        .count();
+  };
+  const int n = inst->n;
+  int dev = 0;
+  FSP_HIP_TRY(hipGetDevice(&dev));
+  int cus = 0, max_tpm = 0;
+  FSP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  FSP_HIP_TRY(hipDeviceGetAttribute(&max_tpm, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev));
+  const int64_t device_threads = (int64_t)cus * max_tpm;
+  int64_t max_pool = policy->max_pool > 0 ? policy->max_pool : device_threads;
+  if (policy->kind == FSP_POOL_FIXED) max_pool = std::max(max_pool, policy->fixed_pool);
+  if (max_pool > (int64_t(1) << 26)) return FSP_EUNSUPPORTED;
+
+  // initial upper bound
+  std::vector<uint8_t> perm0(n);
+  int32_t ub0;
+  if (ub_in > 0) {
+    ub0 = ub_in;
+    for (int j = 0; j < n; ++j) perm0[j] = (uint8_t)j;
+  } else {
+    ub0 = (int32_t)neh_host(inst->p_host, n, inst->m, perm0);
+  }
+
+  BnbState S;
+  int rc = S.init(inst, max_pool, policy->prune_rule);
+  if (rc != FSP_OK) {
+    S.release();
+    return rc;
+  }
+  rc = S.start(ub0, perm0);
+  if (rc != FSP_OK) {
+    S.release();
+    return rc;
+  }
+
+  AdaptivePolicy ap;
+  ap.init(256, cus, device_threads, max_pool);
+  const int nb_iter = policy->nb_iterations > 0 ? policy->nb_iterations : 10;
+  FILE *log = policy->log_path ? std::fopen(policy->log_path, "w") : nullptr;
+
+  int status = 0;
+  double t_found = 0.0;
+  int64_t last_bounded = 1;
+  int64_t target = 0;
+  while (true) {
+    target = policy->kind == FSP_POOL_FIXED ? policy->fixed_pool : ap.current;
+    if ((rc = S.set_target(target)) != FSP_OK) break;
+    const double t0 = elapsed();
+    for (int it = 0; it < nb_iter && rc == FSP_OK; ++it) rc = S.enqueue_iteration();
+    if (rc != FSP_OK) break;
+    if ((rc = S.read_desc()) != FSP_OK) break;
+    const double t1 = elapsed();
+    const BnbDesc &h = *S.host_desc;
+    const int64_t batch_nodes = h.nodes_bounded - last_bounded;
+    last_bounded = h.nodes_bounded;
+    if (h.improved) t_found = t1;
+    if (log)
+      std::fprintf(log,
+                   "{\"t\": %.6f, \"pool_target\": %lld, \"nodes_bounded\": %lld, "
+                   "\"batch_nodes\": %lld, \"ub\": %d, \"pools\": %lld, \"done\": %d}\n",
+                   t1, (long long)target, (long long)h.nodes_bounded,
+                   (long long)batch_nodes, h.ub, (long long)h.pools, h.done);
+    if (h.overflow) {
+      rc = FSP_ENOMEM;
+      break;
+    }
+    if (h.done) break;
+    if (policy->time_limit_s > 0 && t1 >= policy->time_limit_s) {
+      status = 1;
+      break;
+    }
+    if (policy->kind == FSP_POOL_ADAPTIVE && t1 > t0)
+      ap.observe((double)batch_nodes / (t1 - t0));
+    // clear the "improved" flag for the next batch
+    if (h.improved &&
+        hipMemsetAsync(&S.desc->improved, 0, sizeof(int32_t), S.stream) != hipSuccess) {
+      rc = FSP_EDEVICE;
+      break;
+    }
+  }
+  if (rc == FSP_OK) rc = S.commit();
+  if (rc == FSP_OK) rc = S.read_desc();
+  if (log) std::fclose(log);
+  if (rc != FSP_OK) {
+    S.release();
+    return rc;
+  }
+  const BnbDesc &h = *S.host_desc;
+  if (h.improved) t_found = elapsed();
+  std::vector<uint8_t> perm(256);
+  if (hipMemcpy(perm.data(), S.best_perm, 256, hipMemcpyDeviceToHost) != hipSuccess) {
+    S.release();
+    return FSP_EDEVICE;
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->perm = user_perm;
+  out->makespan = h.ub;
+  out->found = h.found;
+  if (user_perm) std::copy(perm.begin(), perm.begin() + n, user_perm);
+  out->status = status;
+  out->root_lb = h.root_lb;
+  out->nodes_bounded = h.nodes_bounded;
+  out->nodes_branched = h.nodes_branched;
+  out->nodes_pruned = h.nodes_pruned;
+  out->leaves = h.leaves;
+  out->pools = h.pools;
+  out->t_found_s = h.found ? t_found : 0.0;
+  out->t_total_s = elapsed();
+  out->final_pool = target;
+  S.release();
+  return FSP_OK;
+}
+
+}  // extern "C"

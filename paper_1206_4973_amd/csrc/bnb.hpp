@@ -1,0 +1,68 @@
+// bnb.hpp -- device-resident branch-and-bound state (bnb.hip).
+#pragma once
+#include <vector>
+
+#include "fsp_internal.hpp"
+
+namespace fspi {
+
+// Iteration descriptor and counters, in device memory; the host reads a copy
+// once per batch of pools.
+struct BnbDesc {
+  int32_t active;       // the current iteration has parents
+  int32_t depth;        // parent depth of the current pool
+  int32_t parents;      // parents taken from the bucket
+  int32_t parent_base;  // index of the first taken parent in its bucket
+  int32_t children;     // children written by branch (pool size)
+  int32_t ub;           // best makespan known (UB)
+  int32_t done;         // no pending node left
+  int32_t overflow;     // a bucket ran out of room (never expected)
+  int32_t found;        // a schedule better than the initial UB was found
+  int32_t improved;     // UB improved since the host last cleared this
+  int32_t root_lb;
+  int32_t pad;
+  int64_t nodes_bounded, nodes_branched, nodes_pruned, leaves, pools;
+  uint64_t best_key;    // (makespan << 32) | pool index, best leaf of a pool
+};
+
+struct BnbState {
+  const fsp_instance *inst = nullptr;
+  int n = 0, stride = 0, rule = 0, cus = 0;
+  int64_t cap = 0;  // records per bucket and in the pool buffer
+  uint8_t *bnodes = nullptr;   // [n][cap][stride]
+  int32_t *blb = nullptr;      // [n][cap]
+  int32_t *bcount = nullptr;   // [n]
+  uint8_t *pool = nullptr;     // [cap][stride]
+  int32_t *pool_lb = nullptr;  // [cap]
+  BnbDesc *desc = nullptr;
+  uint8_t *best_perm = nullptr;  // [256]
+  int64_t *target_dev = nullptr;
+  BnbDesc *host_desc = nullptr;  // pinned
+  int64_t *host_target = nullptr;  // pinned
+  hipStream_t stream = nullptr;
+
+  int init(const fsp_instance *inst, int64_t max_pool, int rule);
+  void release();
+  int start(int32_t ub0, const std::vector<uint8_t> &perm0);
+  int set_target(int64_t target);
+  int enqueue_iteration();
+  int commit();
+  int read_desc();
+};
+
+struct AdaptivePolicy {
+  int nb_threads = 256, nb_blocks = 0;
+  int64_t max_nb_threads = 0;
+  int phase = 0;  // 0 doubling, 1 search around the best, 2 frozen
+  double best_eff = -1.0;
+  int64_t best_size = 0, current = 0, lo = 0, hi = 0;
+  int rounds = 0, trial = 0;
+  void init(int threads_per_block, int cus, int64_t max_threads, int64_t max_pool);
+  void observe(double efficiency);
+  int64_t round_pool(double x) const;
+};
+
+int64_t neh_host(const std::vector<int32_t> &p, int n, int m,
+                 std::vector<uint8_t> &perm);
+
+}  // namespace fspi

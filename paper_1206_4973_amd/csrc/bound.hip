@@ -32,6 +32,8 @@
 // Data layout in LDS (per workgroup): the pair table (whole, or chunk by
 // chunk when it does not fit), the padded p matrix for the prefix recurrence
 // and, for n > 32, one membership byte per (job, lane).
+#include <vector>
+
 #include "fsp_internal.hpp"
 
 using namespace fspi;
@@ -42,6 +44,7 @@ struct BoundParams {
   const uint8_t *nodes;
   int64_t count;
   int64_t ntiles;
+  const int32_t *count_dev;  // when set, the node count is read from here
   int stride;
   int aligned;  // records 16-byte aligned: load them as uint4
   int32_t *lb;
@@ -231,10 +234,15 @@ __global__ __launch_bounds__(kBlock, 4) void bound_kernel(const BoundParams a) {
   __syncthreads();
 
   const uint32_t full = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
+  int64_t count = a.count, ntiles = a.ntiles;
+  if (a.count_dev) {
+    count = *a.count_dev;
+    ntiles = (count + kBlock - 1) / kBlock;
+  }
 
-  for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t idx = tile * kBlock + tid;
-    const bool live = idx < a.count;
+    const bool live = idx < count;
 
     // ---- 1. decode the prefix, front recurrence, prefix column sums ----
     int F[M], Pk[M];
@@ -422,13 +430,15 @@ constexpr size_t kTableBudget = 64 * 1024;
 namespace fspi {
 
 int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
-                 int64_t count, int32_t *lb_out, hipStream_t stream) {
+                 int64_t count, int32_t *lb_out, hipStream_t stream,
+                 const int32_t *count_dev) {
   if (count == 0) return FSP_OK;
   const bool wide = inst->wide != 0;
   BoundParams a{};
   a.nodes = nodes;
   a.count = count;
   a.ntiles = (count + kBlock - 1) / kBlock;
+  a.count_dev = count_dev;
   a.stride = stride;
   a.aligned = ((reinterpret_cast<uintptr_t>(nodes) & 15) == 0 &&
                (stride & 15) == 0)
@@ -457,6 +467,15 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
   if (wide) lds += (size_t)inst->n * kBlock;
   lds = (lds + 15) & ~size_t(15);
 
+  // device attributes and per-kernel occupancy are queried once per
+  // (device, kernel, LDS size) and cached for this thread
+  struct Occ {
+    int dev;
+    BoundFn fn;
+    size_t lds;
+    int per_cu;
+  };
+  static thread_local std::vector<Occ> occ_cache;
   static thread_local int cached_dev = -1, cached_cus = 0;
   int dev = 0;
   FSP_HIP_TRY(hipGetDevice(&dev));
@@ -465,12 +484,17 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
                                       hipDeviceAttributeMultiprocessorCount, dev));
     cached_dev = dev;
   }
-  FSP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds));
-  int per_cu = 0;
-  FSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void *>(fn), kBlock, lds));
+  int per_cu = -1;
+  for (const Occ &o : occ_cache)
+    if (o.dev == dev && o.fn == fn && o.lds == lds) per_cu = o.per_cu;
+  if (per_cu < 0) {
+    FSP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+    FSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(fn), kBlock, lds));
+    occ_cache.push_back({dev, fn, lds, per_cu});
+  }
   if (per_cu < 1) return FSP_EUNSUPPORTED;
   int64_t grid = (int64_t)per_cu * cached_cus;
   if (grid > a.ntiles) grid = a.ntiles;
@@ -488,5 +512,6 @@ extern "C" int fsp_bound_pool(const fsp_nodes *nodes, int64_t count,
   if (!nodes->data || !lb_out) return FSP_EINVAL;
   if (nodes->stride < nodes->inst->n + 1) return FSP_EINVAL;
   return fspi::launch_bound(nodes->inst, nodes->data, nodes->stride, count,
-                            lb_out, reinterpret_cast<hipStream_t>(stream));
+                            lb_out, reinterpret_cast<hipStream_t>(stream),
+                            nullptr);
 }

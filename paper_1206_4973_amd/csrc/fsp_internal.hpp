@@ -57,7 +57,10 @@ struct fsp_instance {
 
 namespace fspi {
 // Launches the pool-bounding kernel (bound.hip).  Validates nothing: the
-// caller has checked every argument.
+// caller has checked every argument.  With count_dev set, the kernel reads
+// the node count from device memory when it starts (at most `count`, which
+// sizes the grid).
 int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
-                 int64_t count, int32_t *lb_out, hipStream_t stream);
+                 int64_t count, int32_t *lb_out, hipStream_t stream,
+                 const int32_t *count_dev);
 }  // namespace fspi

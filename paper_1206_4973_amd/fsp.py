@@ -38,6 +38,28 @@ class _Nodes(ctypes.Structure):
                 ("stride", ctypes.c_int32)]
 
 
+POOL_KINDS = {"fixed": 0, "adaptive": 1, "autotuned": 2, "learned": 3}
+PRUNE_RULES = {"ge": 0, "gt": 1}
+
+
+class _Policy(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nb_iterations", ctypes.c_int32),
+                ("fixed_pool", ctypes.c_int64), ("max_pool", ctypes.c_int64),
+                ("time_limit_s", ctypes.c_double), ("prune_rule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("model", ctypes.c_void_p),
+                ("log_path", ctypes.c_char_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("makespan", ctypes.c_int32), ("found", ctypes.c_int32),
+                ("perm", ctypes.c_void_p), ("status", ctypes.c_int32),
+                ("root_lb", ctypes.c_int32), ("nodes_bounded", ctypes.c_int64),
+                ("nodes_branched", ctypes.c_int64), ("nodes_pruned", ctypes.c_int64),
+                ("leaves", ctypes.c_int64), ("pools", ctypes.c_int64),
+                ("t_found_s", ctypes.c_double), ("t_total_s", ctypes.c_double),
+                ("final_pool", ctypes.c_int64)]
+
+
 def lib() -> ctypes.CDLL:
     """The loaded library (raises when it has not been built)."""
     global _lib
@@ -59,6 +81,11 @@ def lib() -> ctypes.CDLL:
     L.fsp_instance_info.restype = ctypes.c_int
     L.fsp_bound_pool.argtypes = [ctypes.POINTER(_Nodes), i64, P, P]
     L.fsp_bound_pool.restype = ctypes.c_int
+    L.fsp_branch_and_bound.argtypes = [P, ctypes.POINTER(_Policy), i32,
+                                       ctypes.POINTER(_Result)]
+    L.fsp_branch_and_bound.restype = ctypes.c_int
+    L.fsp_neh.argtypes = [P, P, ctypes.POINTER(i32)]
+    L.fsp_neh.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -133,3 +160,55 @@ class Instance:
                                     ctypes.c_void_p(out.data_ptr()),
                                     _stream_handle(stream)), "fsp_bound_pool")
         return out
+
+
+class Result:
+    """Outcome of fsp_branch_and_bound (see fsp_result in include/fsp.h)."""
+
+    def __init__(self, r: _Result, perm: np.ndarray):
+        for name, _ in _Result._fields_:
+            if name != "perm":
+                setattr(self, name, getattr(r, name))
+        self.perm = perm
+
+    def __repr__(self):
+        keys = ("makespan", "found", "status", "root_lb", "nodes_bounded", "nodes_branched",
+                "nodes_pruned", "leaves", "pools", "t_found_s", "t_total_s", "final_pool")
+        return "Result(" + ", ".join(f"{k}={getattr(self, k)}" for k in keys) + ")"
+
+
+def make_policy(kind: str = "adaptive", *, fixed_pool: int = 0, max_pool: int = 0,
+                nb_iterations: int = 10, time_limit: float | None = None,
+                prune_rule: str = "ge", model=None, log_path: str | None = None) -> _Policy:
+    pol = _Policy()
+    pol.kind = POOL_KINDS[kind]
+    pol.nb_iterations = int(nb_iterations)
+    pol.fixed_pool = int(fixed_pool)
+    pol.max_pool = int(max_pool)
+    pol.time_limit_s = float(time_limit) if time_limit else 0.0
+    pol.prune_rule = PRUNE_RULES[prune_rule]
+    pol.model = ctypes.c_void_p(model.handle.value) if model is not None else None
+    pol.log_path = log_path.encode() if log_path else None
+    return pol
+
+
+def branch_and_bound(inst: Instance, kind: str = "adaptive", ub: int | None = None,
+                     **policy) -> Result:
+    """Exact minimum makespan by device-resident B&B (fsp_branch_and_bound)."""
+    pol = make_policy(kind, **policy)
+    perm = np.zeros(max(inst.n, 1), dtype=np.uint8)
+    res = _Result()
+    res.perm = perm.ctypes.data_as(ctypes.c_void_p).value
+    _check(lib().fsp_branch_and_bound(inst.handle, ctypes.byref(pol),
+                                      int(ub) if ub else 0, ctypes.byref(res)),
+           "fsp_branch_and_bound")
+    return Result(res, perm[:inst.n].copy())
+
+
+def neh(inst: Instance):
+    """(makespan, permutation) of the NEH insertion heuristic (fsp_neh)."""
+    perm = np.zeros(inst.n, dtype=np.uint8)
+    c = ctypes.c_int32()
+    _check(lib().fsp_neh(inst.handle, perm.ctypes.data_as(ctypes.c_void_p), ctypes.byref(c)),
+           "fsp_neh")
+    return int(c.value), perm

@@ -1,0 +1,132 @@
+"""Device-resident branch-and-bound against the oracle, through the C ABI.
+
+The optimum is unique (compared exactly); the schedule is not, so a returned
+schedule is checked by recomputing its makespan.  With the initial UB set to
+the optimum the set of bounded nodes no longer depends on the order of
+exploration (every node whose bound is below the optimum is branched, every
+child of a branched node is bounded), so the node counts must equal the
+oracle's exactly under every pool policy.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1206_4973_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fsp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1206_4973_amd import fsp as F
+    F.lib()
+    return F
+
+
+def check_schedule(orc, p, res):
+    n = p.shape[0]
+    assert sorted(res.perm.tolist()) == list(range(n))
+    assert orc.makespan(p, res.perm) == res.makespan
+
+
+def test_tiny_config_against_all_schedules(fsp, orc):
+    """9 jobs x 5 machines: optimum = minimum over all 9! schedules."""
+    p = I.instance(9, 5, 1000)
+    opt, _ = orc.brute_force(p)
+    inst = fsp.Instance(p)
+    for kind, kw in (("adaptive", {}), ("fixed", {"fixed_pool": 1}),
+                     ("fixed", {"fixed_pool": 64}), ("fixed", {"fixed_pool": 5000})):
+        say(f"9x5 {kind} {kw}")
+        res = fsp.branch_and_bound(inst, kind, **kw)
+        assert res.status == 0 and res.makespan == opt
+        check_schedule(orc, p, res)
+
+
+@pytest.mark.parametrize("rule", ["ge", "gt"])
+def test_random_small_instances(fsp, orc, rule):
+    rng = np.random.default_rng(31 if rule == "ge" else 32)
+    for t in range(12):
+        n, m = int(rng.integers(2, 9)), int(rng.integers(2, 8))
+        p = rng.integers(1, 99, size=(n, m)).astype(np.int32)
+        opt, _ = orc.brute_force(p)
+        inst = fsp.Instance(p)
+        pool = int(rng.choice([1, 3, 50, 1000]))
+        res = fsp.branch_and_bound(inst, "fixed", fixed_pool=pool, prune_rule=rule)
+        assert res.makespan == opt, (n, m, pool)
+        check_schedule(orc, p, res)
+
+
+def test_neh_matches_oracle(fsp, orc):
+    for n, m, seed in ((9, 5, 1000), (20, 20, 2000), (20, 10, 4000), (50, 20, 5000)):
+        p = I.instance(n, m, seed)
+        c, perm = fsp.neh(fsp.Instance(p))
+        oc, operm = orc.neh(p)
+        assert c == oc and np.array_equal(perm, operm)
+
+
+SCREENED = [(12, 6, 61), (12, 8, 62), (13, 5, 63), (14, 7, 65), (15, 6, 67), (14, 8, 69),
+            (15, 10, 70), (20, 10, 4046), (20, 10, 4052), (20, 10, 4056)]
+
+
+@pytest.mark.parametrize("n,m,seed", SCREENED, ids=[f"{n}x{m}" for n, m, _ in SCREENED])
+def test_optimum_matches_oracle_dfs(fsp, orc, n, m, seed):
+    p = I.instance(n, m, seed)
+    oc, _, ost = orc.bnb(p)
+    assert ost.complete == 1
+    inst = fsp.Instance(p)
+    say(f"{n}x{m}: oracle {oc} after {ost.nodes_bounded} nodes")
+    res = fsp.branch_and_bound(inst, "adaptive")
+    assert res.status == 0 and res.makespan == oc
+    assert res.root_lb == ost.root_lb
+    check_schedule(orc, p, res)
+
+
+@pytest.mark.parametrize("rule", ["ge", "gt"])
+@pytest.mark.parametrize("n,m,seed", [(9, 5, 1000), (11, 7, 71), (12, 6, 61)])
+def test_critical_tree_counts_equal_oracle(fsp, orc, n, m, seed, rule):
+    p = I.instance(n, m, seed)
+    opt, _, _ = orc.bnb(p)
+    oc, _, ost = orc.bnb(p, opt, 0 if rule == "ge" else 1)
+    assert oc == opt and ost.complete == 1
+    inst = fsp.Instance(p)
+    for kind, kw in (("fixed", {"fixed_pool": 1}), ("fixed", {"fixed_pool": 37}),
+                     ("fixed", {"fixed_pool": 100000}), ("adaptive", {})):
+        res = fsp.branch_and_bound(inst, kind, ub=opt, prune_rule=rule, **kw)
+        say(f"{n}x{m} {rule} {kind} {kw}: {res.nodes_bounded} vs {ost.nodes_bounded}")
+        assert res.makespan == opt and res.found == 0 and res.status == 0
+        assert res.nodes_bounded == ost.nodes_bounded
+        assert res.nodes_branched == ost.nodes_branched
+        assert res.leaves == ost.leaves
+        assert res.nodes_pruned == ost.nodes_pruned
+
+
+def test_time_limit_returns_a_valid_schedule(fsp, orc):
+    p = I.instance(20, 10, 4000)
+    inst = fsp.Instance(p)
+    neh_c, _ = orc.neh(p)
+    res = fsp.branch_and_bound(inst, "adaptive", time_limit=1e-6)
+    assert res.status == 1
+    assert res.makespan <= neh_c
+    check_schedule(orc, p, res)
+
+
+def test_repeat_runs_give_the_same_optimum(fsp, orc):
+    p = I.instance(12, 8, 62)
+    inst = fsp.Instance(p)
+    vals = {fsp.branch_and_bound(inst, "fixed", fixed_pool=200).makespan for _ in range(6)}
+    assert len(vals) == 1
+
+
+def test_policy_errors(fsp):
+    inst = fsp.Instance(I.instance(8, 4, 3))
+    with pytest.raises(fsp.FspError):
+        fsp.branch_and_bound(inst, "fixed", fixed_pool=0)
