@@ -105,6 +105,57 @@ typedef struct {
 int fsp_bound_pool(const fsp_nodes *nodes, int64_t count, int32_t *lb_out,
                    void *stream);
 
+/* ---- batched bounding: many instances in one launch ------------------- */
+
+/* One pool of one instance.  data/lb_out: device pointers as in
+ * fsp_bound_pool; stride >= inst's n + 1; count may be 0. */
+typedef struct {
+  const fsp_instance *inst;
+  const uint8_t *data;
+  int32_t stride;
+  int64_t count;
+  int32_t *lb_out;
+} fsp_segment;
+
+/* Launch shape of a batch (NULL or 0 fields: the defaults, i.e. as many
+ * workgroups per compute unit as fit). */
+typedef struct {
+  int32_t blocks_per_cu;
+  int32_t reserved[3];
+} fsp_batch_config;
+
+typedef struct fsp_batch fsp_batch;
+
+/*
+ * fsp_batch_create -- plan one persistent launch that bounds every segment
+ * (the parallel bounding of Sec. III over a batch of pools).  The segment
+ * table (instances, device pointers, counts) is copied to the device; the
+ * node buffers themselves are read at launch time, so their contents may
+ * change between launches.  Segments of 5, 10 or 20 machines share the one
+ * persistent kernel; any other machine count is bounded by single-pool
+ * launches queued right after it.  Synchronous.  Release with fsp_batch_free
+ * once no queued launch uses it.
+ */
+int fsp_batch_create(const fsp_segment *segs, int32_t nsegs,
+                     const fsp_batch_config *cfg, fsp_batch **out);
+
+/* Queue the batch on `stream` (a counter reset and the persistent kernel). */
+int fsp_batch_launch(fsp_batch *b, void *stream);
+
+/* Same work as fsp_batch_launch, through a hipGraph captured on the first
+ * call and replayed on every call (on `stream`). */
+int fsp_batch_replay(fsp_batch *b, void *stream);
+
+/* Tiles of 256 nodes, persistent grid size, segments in the batch kernel and
+ * segments bounded by single-pool launches (any pointer may be NULL). */
+int fsp_batch_info(const fsp_batch *b, int64_t *tiles, int32_t *grid,
+                   int32_t *kernel_segments, int32_t *fallback_segments);
+
+int fsp_batch_free(fsp_batch *b);
+
+/* One-shot: create, queue on `stream`, wait for the stream, free. */
+int fsp_bound_batch(const fsp_segment *segs, int32_t nsegs, void *stream);
+
 /* ---- branch-and-bound (Sec. II.A operators, Sec. III pool loop) --------- */
 
 /* Pool-size policies.  FSP_POOL_FIXED: every pool has fixed_pool children.

@@ -27,8 +27,9 @@ constexpr int kLogBlock = 8;
 // Narrow records (n <= 32: one 32-bit job mask per node):
 //   x = 256 * (b - a)            (signed, |.| < 2^23)
 //   y = ((lag + b) << 8) | job   (unsigned, < 2^24)
-// Wide records (n > 32) add the job id as a separate field:
-//   {x, y, job, 0}
+// Wide records (n > 32) add the byte offset, in the kernels' [word][lane]
+// LDS layout of the unscheduled-job masks, of the job's 32-job word:
+//   {x, y, (job / 32) * 256 lanes * 4 bytes, 0}
 // with a = p[job][k], b = p[job][l], lag = sum_{k<h<l} p[job][h].
 using NarrowRec = int2;
 using WideRec = int4;

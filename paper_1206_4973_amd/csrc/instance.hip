@@ -91,15 +91,15 @@ __global__ __launch_bounds__(256) void stage_pairs(
   if (j >= npad) return;
   // Padding records are all-zero: x = 0 and y = 0 leave the pair state
   // unchanged (see the step in bound.hip).
-  int x = 0, y = 0, job = 0;
+  int x = 0, y = 0, woff = 0;
   if (j < n) {
     x = 256 * (b - a);
     y = ((lag + b) << 8) | j;
-    job = j;
+    woff = (j >> 5) * kBlock * 4;
   }
   const size_t slot = (size_t)pi * npad + pos;
   if (wide)
-    reinterpret_cast<WideRec *>(rec_out)[slot] = make_int4(x, y, job, 0);
+    reinterpret_cast<WideRec *>(rec_out)[slot] = make_int4(x, y, woff, 0);
   else
     reinterpret_cast<NarrowRec *>(rec_out)[slot] = make_int2(x, y);
 }

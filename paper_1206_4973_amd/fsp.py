@@ -38,6 +38,16 @@ class _Nodes(ctypes.Structure):
                 ("stride", ctypes.c_int32)]
 
 
+class _Segment(ctypes.Structure):
+    _fields_ = [("inst", ctypes.c_void_p), ("data", ctypes.c_void_p),
+                ("stride", ctypes.c_int32), ("count", ctypes.c_int64),
+                ("lb_out", ctypes.c_void_p)]
+
+
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
 POOL_KINDS = {"fixed": 0, "adaptive": 1, "autotuned": 2, "learned": 3}
 PRUNE_RULES = {"ge": 0, "gt": 1}
 
@@ -86,6 +96,19 @@ def lib() -> ctypes.CDLL:
     L.fsp_branch_and_bound.restype = ctypes.c_int
     L.fsp_neh.argtypes = [P, P, ctypes.POINTER(i32)]
     L.fsp_neh.restype = ctypes.c_int
+    L.fsp_batch_create.argtypes = [ctypes.POINTER(_Segment), i32,
+                                   ctypes.POINTER(_BatchConfig), ctypes.POINTER(P)]
+    L.fsp_batch_create.restype = ctypes.c_int
+    L.fsp_batch_launch.argtypes = [P, P]
+    L.fsp_batch_launch.restype = ctypes.c_int
+    L.fsp_batch_replay.argtypes = [P, P]
+    L.fsp_batch_replay.restype = ctypes.c_int
+    L.fsp_batch_info.argtypes = [P, P, P, P, P]
+    L.fsp_batch_info.restype = ctypes.c_int
+    L.fsp_batch_free.argtypes = [P]
+    L.fsp_batch_free.restype = ctypes.c_int
+    L.fsp_bound_batch.argtypes = [ctypes.POINTER(_Segment), i32, P]
+    L.fsp_bound_batch.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -212,3 +235,74 @@ def neh(inst: Instance):
     _check(lib().fsp_neh(inst.handle, perm.ctypes.data_as(ctypes.c_void_p), ctypes.byref(c)),
            "fsp_neh")
     return int(c.value), perm
+
+
+def _segments(items):
+    segs = (_Segment * max(1, len(items)))()
+    outs = []
+    for i, (inst, nodes, out) in enumerate(items):
+        if nodes.dtype != torch.uint8 or nodes.dim() != 2 or not nodes.is_cuda:
+            raise ValueError("nodes must be a uint8 [count, stride] device tensor")
+        count = int(nodes.shape[0])
+        if out is None:
+            out = torch.empty(count, dtype=torch.int32, device=nodes.device)
+        segs[i].inst = inst.handle.value
+        segs[i].data = nodes.data_ptr()
+        segs[i].stride = int(nodes.stride(0))
+        segs[i].count = count
+        segs[i].lb_out = out.data_ptr()
+        outs.append(out)
+    return segs, outs
+
+
+class Batch:
+    """A batch of (instance, pool) segments bounded in one persistent launch
+    (fsp_batch_create / fsp_batch_launch / fsp_batch_replay).
+
+    ``items``: list of (Instance, uint8 [count, stride] device tensor,
+    int32 [count] device tensor or None).  The tensors must stay alive (and
+    keep their storage) as long as the batch is used."""
+
+    def __init__(self, items, blocks_per_cu: int = 0):
+        self._keep = [(i, n) for i, n, _ in items]
+        segs, self.outs = _segments(items)
+        cfg = _BatchConfig()
+        cfg.blocks_per_cu = int(blocks_per_cu)
+        h = ctypes.c_void_p()
+        _check(lib().fsp_batch_create(segs, len(items), ctypes.byref(cfg), ctypes.byref(h)),
+               "fsp_batch_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().fsp_batch_launch(self._h, _stream_handle(stream)), "fsp_batch_launch")
+        return self.outs
+
+    def replay(self, stream=None):
+        _check(lib().fsp_batch_replay(self._h, _stream_handle(stream)), "fsp_batch_replay")
+        return self.outs
+
+    def info(self) -> dict:
+        tiles, grid = ctypes.c_int64(), ctypes.c_int32()
+        ks, fs = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fsp_batch_info(self._h, ctypes.byref(tiles), ctypes.byref(grid),
+                                    ctypes.byref(ks), ctypes.byref(fs)), "fsp_batch_info")
+        return {"tiles": tiles.value, "grid": grid.value, "kernel_segments": ks.value,
+                "fallback_segments": fs.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().fsp_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bound_batch(items, stream=None):
+    """One-shot batch (fsp_bound_batch): returns the bound tensors."""
+    segs, outs = _segments(items)
+    _check(lib().fsp_bound_batch(segs, len(items), _stream_handle(stream)), "fsp_bound_batch")
+    return outs

@@ -1,0 +1,118 @@
+"""One persistent launch over many instances and uneven pools, checked against
+single-pool launches and the oracle; graph replays checked after the node
+buffers change between replays."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1206_4973_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fsp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1206_4973_amd import fsp as F
+    F.lib()
+    return F
+
+
+def mixed_batch(F, count_fn, seed0, shapes):
+    items, host = [], []
+    for i, (n, m) in enumerate(shapes):
+        p = I.instance(n, m, seed0 + i)
+        cnt = count_fn(i)
+        pool = I.random_pool(n, cnt, 1, n - 1 if n > 1 else 1, seed0 + 500000 + i)
+        inst = F.Instance(p)
+        items.append((inst, torch.from_numpy(pool).cuda(), None))
+        host.append((p, pool))
+    return items, host
+
+
+SHAPES = [(20, 5), (20, 10), (20, 20), (50, 5), (50, 10), (50, 20), (100, 5), (100, 10),
+          (100, 20), (20, 7), (33, 20), (9, 5)]
+
+
+def test_mixed_batch_matches_oracle_and_single_launches(fsp, orc):
+    rng = np.random.default_rng(5)
+    counts = [int(c) for c in rng.integers(1, 2500, size=len(SHAPES))]
+    items, host = mixed_batch(fsp, lambda i: counts[i], 3100, SHAPES)
+    b = fsp.Batch(items)
+    info = b.info()
+    say("batch info", info)
+    assert info["kernel_segments"] == len(SHAPES) - 1 and info["fallback_segments"] == 1
+    outs = b.launch()
+    torch.cuda.synchronize()
+    for (inst, nodes, _), out, (p, pool) in zip(items, outs, host):
+        single = inst.bound_pool(nodes)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.array_equal(got, single.cpu().numpy())
+        assert np.array_equal(got, orc.bound_pool(p, pool, nthreads=8))
+    b.close()
+
+
+def test_one_shot_and_empty_segments(fsp, orc):
+    items, host = mixed_batch(fsp, lambda i: [0, 700, 0][i], 3200, [(20, 20), (50, 10), (9, 5)])
+    outs = fsp.bound_batch(items)
+    assert outs[0].numel() == 0 and outs[2].numel() == 0
+    assert np.array_equal(outs[1].cpu().numpy(), orc.bound_pool(*host[1], nthreads=8))
+
+
+def test_graph_replay_sees_new_node_contents(fsp, orc):
+    shapes = [(20, 20), (50, 10), (100, 5), (20, 7)]
+    items, host = mixed_batch(fsp, lambda i: 900 + 300 * i, 3300, shapes)
+    b = fsp.Batch(items)
+    for rep in range(4):
+        if rep:
+            # eager work between replays: rewrite every pool in place
+            for i, (inst, nodes, _) in enumerate(items):
+                n = shapes[i][0]
+                pool = I.random_pool(n, nodes.shape[0], 0, n, 3400 + 10 * rep + i)
+                nodes.copy_(torch.from_numpy(pool))
+                host[i] = (host[i][0], pool)
+            torch.cuda.synchronize()
+        outs = b.replay()
+        torch.cuda.synchronize()
+        for out, (p, pool) in zip(outs, host):
+            assert np.array_equal(out.cpu().numpy(), orc.bound_pool(p, pool, nthreads=8)), rep
+    b.close()
+
+
+def test_batching_config_64_instances(fsp, orc):
+    """64 instances, n in {20,50,100} x m in {5,10,20}, pools of 2^e nodes with e
+    uniform in 10..18: every segment equals its single-pool launch; a sample of
+    each segment equals the oracle."""
+    shapes = [(n, m) for n in (20, 50, 100) for m in (5, 10, 20)]
+    rng = np.random.default_rng(3000)
+    exps = [int(e) for e in rng.integers(10, 19, size=64)]
+    items, host = [], []
+    say("generating 64 pools")
+    for i in range(64):
+        n, m = shapes[i % 9]
+        p = I.instance(n, m, 3000 + i)
+        pool = I.random_pool(n, 1 << exps[i], 1, n - 1, 3000 + 500000 + i)
+        items.append((fsp.Instance(p), torch.from_numpy(pool).cuda(), None))
+        host.append((p, pool))
+    b = fsp.Batch(items)
+    say("batch info", b.info(), "nodes", sum(1 << e for e in exps))
+    outs = b.replay()
+    torch.cuda.synchronize()
+    for i, ((inst, nodes, _), out, (p, pool)) in enumerate(zip(items, outs, host)):
+        got = out.cpu().numpy()
+        ref = inst.bound_pool(nodes)
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref.cpu().numpy()), i
+        idx = np.unique(np.concatenate([rng.integers(0, len(pool), size=48),
+                                        [0, len(pool) - 1]]))
+        assert np.array_equal(got[idx], orc.bound_pool(p, pool[idx], nthreads=8)), i
+    b.close()
