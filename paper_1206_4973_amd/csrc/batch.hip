@@ -164,7 +164,8 @@ int fsp_batch_create(const fsp_segment *segs, int32_t nsegs,
   for (int i = 0; i < nsegs; ++i) {
     const fsp_segment &g = segs[i];
     if (!g.inst || g.count < 0) return FSP_EINVAL;
-    if (g.count > 0 && (!g.data || !g.lb_out)) return FSP_EINVAL;
+    if (g.count == 0) continue;  // nothing to read: pointers and stride unused
+    if (!g.data || !g.lb_out) return FSP_EINVAL;
     if (g.stride < g.inst->n + 1) return FSP_EINVAL;
   }
   fsp_batch *b = new (std::nothrow) fsp_batch();

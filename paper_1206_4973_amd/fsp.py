@@ -248,7 +248,7 @@ def _segments(items):
             out = torch.empty(count, dtype=torch.int32, device=nodes.device)
         segs[i].inst = inst.handle.value
         segs[i].data = nodes.data_ptr()
-        segs[i].stride = int(nodes.stride(0))
+        segs[i].stride = int(nodes.stride(0)) if count > 0 else int(nodes.shape[1])
         segs[i].count = count
         segs[i].lb_out = out.data_ptr()
         outs.append(out)
