@@ -231,6 +231,47 @@ int fsp_branch_and_bound(const fsp_instance *inst,
  * position on ties).  perm_out: host buffer of n bytes (may be NULL). */
 int fsp_neh(const fsp_instance *inst, uint8_t *perm_out, int32_t *makespan_out);
 
+/* ---- the pool-policy network (learned pool policy) ---------------------- */
+
+/* A 3-layer perceptron y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 over node
+ * features x (in_features <= 32, zero-padded to 32), 128 hidden units per
+ * layer, outputs <= 16.  bf16 matrix-core products with fp32 accumulation;
+ * fp32 master weights.  Parameter vector (fp32, fsp_model_param_count()
+ * entries): W1[32][128] b1[128] W2[128][128] b2[128] W3[128][16] b3[16],
+ * rows/columns beyond in_features/outputs are zero and stay zero.  The
+ * network only orders pools and sizes them; it never decides an elimination. */
+typedef struct fsp_model fsp_model;
+
+int fsp_model_create(int32_t in_features, int32_t hidden, int32_t outputs,
+                     uint64_t seed, fsp_model **out); /* hidden must be 128 */
+int fsp_model_free(fsp_model *m);
+int64_t fsp_model_param_count(void);
+int fsp_model_set_params(fsp_model *m, const float *host, int64_t n);
+int fsp_model_get_params(const fsp_model *m, float *host, int64_t n);
+int fsp_model_get_grads(const fsp_model *m, float *host, int64_t n);
+
+/* y[N][outputs] (device fp32) = network(x), x device bf16 [N][32].  Async. */
+int fsp_model_forward(const fsp_model *m, const void *x, int64_t n, float *y,
+                      void *stream);
+
+/* Gradients of sum(dy . y) w.r.t. the parameters (stored in the model,
+ * added to the previous ones when accumulate != 0) and, if dx is not NULL,
+ * w.r.t. x (device fp32 [N][32]).  dy: device fp32 [N][outputs].  Async. */
+int fsp_model_backward(fsp_model *m, const void *x, int64_t n, const float *dy,
+                       float *dx, int32_t accumulate, void *stream);
+
+/* Adam update of the parameters from the stored gradients.  Async. */
+int fsp_model_adam_step(fsp_model *m, float lr, float beta1, float beta2,
+                        float eps, float weight_decay, void *stream);
+
+/* One training step on a batch: forward, loss (output 0: squared error
+ * against target[r][0]; output 1, if present: logistic loss against
+ * target[r][1] in {0,1}), backward, Adam (lr, 0.9, 0.999, 1e-8).  target:
+ * device fp32 [N][2].  Writes the batch loss to *loss_out (host) if not NULL
+ * (then synchronises the stream). */
+int fsp_model_train_step(fsp_model *m, const void *x, const float *target,
+                         int64_t n, float lr, float *loss_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

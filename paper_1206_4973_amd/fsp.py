@@ -109,6 +109,25 @@ def lib() -> ctypes.CDLL:
     L.fsp_batch_free.restype = ctypes.c_int
     L.fsp_bound_batch.argtypes = [ctypes.POINTER(_Segment), i32, P]
     L.fsp_bound_batch.restype = ctypes.c_int
+    L.fsp_model_create.argtypes = [i32, i32, i32, ctypes.c_uint64, ctypes.POINTER(P)]
+    L.fsp_model_create.restype = ctypes.c_int
+    L.fsp_model_free.argtypes = [P]
+    L.fsp_model_free.restype = ctypes.c_int
+    L.fsp_model_param_count.argtypes = []
+    L.fsp_model_param_count.restype = i64
+    for name in ("fsp_model_set_params", "fsp_model_get_params", "fsp_model_get_grads"):
+        getattr(L, name).argtypes = [P, P, i64]
+        getattr(L, name).restype = ctypes.c_int
+    L.fsp_model_forward.argtypes = [P, P, i64, P, P]
+    L.fsp_model_forward.restype = ctypes.c_int
+    L.fsp_model_backward.argtypes = [P, P, i64, P, P, i32, P]
+    L.fsp_model_backward.restype = ctypes.c_int
+    L.fsp_model_adam_step.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, P]
+    L.fsp_model_adam_step.restype = ctypes.c_int
+    L.fsp_model_train_step.argtypes = [P, P, P, i64, ctypes.c_float,
+                                       ctypes.POINTER(ctypes.c_float), P]
+    L.fsp_model_train_step.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -306,3 +325,90 @@ def bound_batch(items, stream=None):
     segs, outs = _segments(items)
     _check(lib().fsp_bound_batch(segs, len(items), _stream_handle(stream)), "fsp_bound_batch")
     return outs
+
+
+class Model:
+    """The pool-policy network (fsp_model_*): 32 -> 128 -> 128 -> outputs."""
+
+    def __init__(self, in_features: int = 22, outputs: int = 2, seed: int = 0,
+                 hidden: int = 128):
+        h = ctypes.c_void_p()
+        _check(lib().fsp_model_create(int(in_features), int(hidden), int(outputs),
+                                      ctypes.c_uint64(seed), ctypes.byref(h)),
+               "fsp_model_create")
+        self._h = h
+        self.in_features, self.outputs = int(in_features), int(outputs)
+        self.nparams = int(lib().fsp_model_param_count())
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().fsp_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.nparams, dtype=np.float32)
+        _check(lib().fsp_model_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                          self.nparams), "fsp_model_get_params")
+        return out
+
+    def set_params(self, p: np.ndarray) -> None:
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib().fsp_model_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p),
+                                          len(p)), "fsp_model_set_params")
+
+    def grads(self) -> np.ndarray:
+        out = np.zeros(self.nparams, dtype=np.float32)
+        _check(lib().fsp_model_get_grads(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                         self.nparams), "fsp_model_get_grads")
+        return out
+
+    @staticmethod
+    def _x(x: torch.Tensor) -> torch.Tensor:
+        if x.dtype != torch.bfloat16 or x.dim() != 2 or x.shape[1] != 32 or not x.is_cuda:
+            raise ValueError("x must be a bfloat16 [N, 32] device tensor")
+        return x.contiguous()
+
+    def forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        x = self._x(x)
+        y = torch.empty((x.shape[0], self.outputs), dtype=torch.float32, device=x.device)
+        _check(lib().fsp_model_forward(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                       ctypes.c_void_p(y.data_ptr()), _stream_handle(stream)),
+               "fsp_model_forward")
+        return y
+
+    def backward(self, x: torch.Tensor, dy: torch.Tensor, want_dx: bool = False,
+                 accumulate: bool = False, stream=None):
+        x = self._x(x)
+        dy = dy.contiguous().float()
+        dx = torch.empty((x.shape[0], 32), dtype=torch.float32, device=x.device) if want_dx else None
+        _check(lib().fsp_model_backward(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                        ctypes.c_void_p(dy.data_ptr()),
+                                        ctypes.c_void_p(dx.data_ptr()) if dx is not None else None,
+                                        1 if accumulate else 0, _stream_handle(stream)),
+               "fsp_model_backward")
+        return dx
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                  weight_decay: float = 0.0, stream=None) -> None:
+        _check(lib().fsp_model_adam_step(self._h, lr, beta1, beta2, eps, weight_decay,
+                                         _stream_handle(stream)), "fsp_model_adam_step")
+
+    def train_step(self, x: torch.Tensor, target: torch.Tensor, lr: float, stream=None) -> float:
+        x = self._x(x)
+        target = target.contiguous().float()
+        loss = ctypes.c_float()
+        _check(lib().fsp_model_train_step(self._h, ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(target.data_ptr()), x.shape[0], lr,
+                                          ctypes.byref(loss), _stream_handle(stream)),
+               "fsp_model_train_step")
+        return float(loss.value)
