@@ -208,6 +208,7 @@ typedef struct {
   double t_found_s;   /* wall time when the final UB was found (0 if none) */
   double t_total_s;   /* wall time of the whole call                        */
   int64_t final_pool; /* pool size in force at the end                      */
+  double t_search_s;  /* wall time of the search loop (set-up excluded)     */
 } fsp_result;
 
 /*
@@ -219,12 +220,46 @@ typedef struct {
  *               bound is below it are explored, whatever the order);
  *   ub_in <= 0: initial UB from the NEH insertion heuristic.
  * Synchronous; allocates and frees its own device memory and stream.  With
- * status 0 the returned makespan is optimal.  FSP_EUNSUPPORTED for the
- * FSP_POOL_AUTOTUNED / FSP_POOL_LEARNED kinds when this build lacks them.
+ * status 0 the returned makespan is optimal.
+ * FSP_POOL_AUTOTUNED: pools of policy->fixed_pool children, or (when <= 0)
+ * of the size fsp_autotune_pool picks for this shape; the nb_iterations
+ * iterations of a batch are captured once in a hipGraph and replayed.
+ * FSP_POOL_LEARNED: as FSP_POOL_AUTOTUNED, and policy->model (an fsp_model
+ * with 2 + 2 min(m, 15) inputs) orders each depth: when a pool takes only
+ * part of the pending nodes of a depth, it takes those with the smallest
+ * estimated completion (bound + predicted gap).  The exact bound still
+ * decides every elimination, so the optimum does not depend on the model.
  */
 int fsp_branch_and_bound(const fsp_instance *inst,
                          const fsp_pool_policy *policy, int32_t ub_in,
                          fsp_result *out);
+
+/*
+ * fsp_autotune_pool -- the pool size (children per pool) that maximises
+ * nodes bounded per second of search for this instance's shape: FSP_POOL_
+ * AUTOTUNED searches of budget_s / #candidates seconds each (budget_s <= 0:
+ * 0.25 s per candidate) over 2^14 .. min(resident threads, 2^20); a larger
+ * pool must win by more than 3 %.  Cached per (device, n, m) for the life of
+ * the process.  rate_out (may be NULL): the winner's nodes per second.
+ */
+int fsp_autotune_pool(const fsp_instance *inst, double budget_s,
+                      int64_t *pool_out, double *rate_out);
+
+/*
+ * fsp_policy_samples -- training data for the pool-policy network, logged by
+ * the search itself: runs fsp_branch_and_bound (any kind but LEARNED) and
+ * logs each child that survives elimination with probability sample_prob
+ * (deterministic in seed), at most max_samples.  For every logged node it
+ * writes the network input (x_out, device bf16 [max_samples][32]) and two
+ * targets (target_out, device fp32 [max_samples][2]): the gap between a
+ * suffix-NEH completion of the node and its bound, over the NEH makespan;
+ * and 1 if the node's bound reaches the final UB (it would be eliminated
+ * with that UB), else 0.  *n_out: samples written; result: the search.
+ */
+int fsp_policy_samples(const fsp_instance *inst, const fsp_pool_policy *policy,
+                       int32_t ub_in, int64_t max_samples, double sample_prob,
+                       uint64_t seed, void *x_out, float *target_out,
+                       int64_t *n_out, fsp_result *result);
 
 /* NEH insertion heuristic (host): jobs by total time descending (ties by
  * id), each inserted where the partial makespan is smallest (earliest

@@ -32,6 +32,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -109,6 +110,7 @@ __global__ void plan_kernel(BnbDesc *D, int32_t *bcount, const uint8_t *pool,
   if (k > bcount[d]) k = bcount[d];
   D->depth = d;
   D->parents = (int)k;
+  D->sel_count = bcount[d];
   D->parent_base = bcount[d] - (int)k;
   bcount[d] -= (int)k;
   D->active = 1;
@@ -173,11 +175,22 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
 }
 
 // ---- prune + compaction ----------------------------------------------------
+// 32-bit mix of (pool counter, index, seed): the training-sample lottery
+__device__ __forceinline__ uint32_t sample_hash(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return (uint32_t)x;
+}
+
 __global__ __launch_bounds__(kThreads) void prune_kernel(
     BnbDesc *D, const uint8_t *__restrict__ pool,
     const int32_t *__restrict__ pool_lb, uint8_t *__restrict__ bnodes,
     int32_t *__restrict__ blb, int32_t *__restrict__ bcount, int n, int stride,
-    int64_t cap, int rule) {
+    int64_t cap, int rule, int64_t log_cap, uint32_t log_threshold, uint32_t log_seed,
+    uint8_t *__restrict__ log_nodes, int32_t *__restrict__ log_lb) {
   if (!D->active) return;
   const int total = D->children;
   const int d1 = D->depth + 1;
@@ -201,6 +214,17 @@ __global__ __launch_bounds__(kThreads) void prune_kernel(
     }
     const int pos = wave_slot(keep, &bcount[d1]);
     if (!keep) continue;
+    if (log_cap > 0 &&
+        sample_hash(((uint64_t)D->pools << 32) ^ (uint64_t)i ^ ((uint64_t)log_seed << 16)) <
+            log_threshold) {
+      const int slot = atomicAdd(&D->log_count, 1);
+      if (slot < log_cap) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(pool + (size_t)i * stride);
+        uint4 *dst = reinterpret_cast<uint4 *>(log_nodes + (size_t)slot * stride);
+        for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
+        log_lb[slot] = lb;
+      }
+    }
     if (pos >= cap) {
       D->overflow = 1;
       continue;
@@ -303,21 +327,51 @@ int BnbState::init(const fsp_instance *inst_, int64_t max_pool, int rule_) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
       hipSuccess)
     return FSP_EDEVICE;
+  grid = std::max(1, std::min<int>(cus * 4, (int)((cap + kThreads - 1) / kThreads)));
   if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
     return FSP_EDEVICE;
   return FSP_OK;
 }
 
+int BnbState::init_model(const fsp_model *model_, float inv_scale_) {
+  model = model_;
+  inv_scale = inv_scale_;
+  const int nout = model_outputs(model);
+  if (hipMalloc(&bscore, (size_t)n * cap * sizeof(float)) != hipSuccess ||
+      hipMalloc(&tnodes, (size_t)cap * stride) != hipSuccess ||
+      hipMalloc(&tlb, (size_t)cap * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&tscore, (size_t)cap * sizeof(float)) != hipSuccess ||
+      hipMalloc(&hist, 4096 * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&X, (size_t)cap * 32 * 2) != hipSuccess ||
+      hipMalloc(&Y, (size_t)cap * nout * sizeof(float)) != hipSuccess)
+    return FSP_ENOMEM;
+  FSP_HIP_TRY(hipMemsetAsync(hist, 0, 4096 * sizeof(int32_t), stream));
+  // the root (bucket 0) is alone: any score will do
+  FSP_HIP_TRY(hipMemsetAsync(bscore, 0, sizeof(float), stream));
+  return FSP_OK;
+}
+
+int BnbState::init_log(int64_t lcap, double prob, uint64_t seed) {
+  log_cap = lcap;
+  const double t = prob <= 0 ? 0.0 : (prob >= 1 ? 4294967295.0 : prob * 4294967296.0);
+  log_threshold = (uint32_t)t;
+  log_seed = (uint32_t)(seed ^ (seed >> 32));
+  if (hipMalloc(&log_nodes, (size_t)lcap * stride) != hipSuccess ||
+      hipMalloc(&log_lb, (size_t)lcap * sizeof(int32_t)) != hipSuccess)
+    return FSP_ENOMEM;
+  return FSP_OK;
+}
+
 void BnbState::release() {
   if (stream) (void)hipStreamSynchronize(stream);
-  if (bnodes) (void)hipFree(bnodes);
-  if (blb) (void)hipFree(blb);
-  if (bcount) (void)hipFree(bcount);
-  if (pool) (void)hipFree(pool);
-  if (pool_lb) (void)hipFree(pool_lb);
-  if (desc) (void)hipFree(desc);
-  if (best_perm) (void)hipFree(best_perm);
-  if (target_dev) (void)hipFree(target_dev);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  for (void *p : {(void *)bnodes, (void *)blb, (void *)bcount, (void *)pool, (void *)pool_lb,
+                  (void *)desc, (void *)best_perm, (void *)target_dev, (void *)bscore,
+                  (void *)tnodes, (void *)tlb, (void *)tscore, (void *)hist, X, (void *)Y,
+                  (void *)log_nodes, (void *)log_lb})
+    if (p) (void)hipFree(p);
   if (host_desc) (void)hipHostFree(host_desc);
   if (host_target) (void)hipHostFree(host_target);
   if (stream) (void)hipStreamDestroy(stream);
@@ -351,18 +405,47 @@ int BnbState::set_target(int64_t target) {
   return FSP_OK;
 }
 
-int BnbState::enqueue_iteration() {
-  const int grid = std::max(1, std::min<int>(cus * 4, (int)((cap + kThreads - 1) / kThreads)));
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(64), 0, stream, desc, bcount,
+int BnbState::enqueue_iteration(hipStream_t s) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(64), 0, s, desc, bcount,
                      pool, best_perm, n, stride, target_dev, 0);
-  hipLaunchKernelGGL(branch_kernel, dim3(grid), dim3(kThreads), 0, stream, desc,
+  FSP_HIP_TRY(hipGetLastError());
+  int rc;
+  if (model && (rc = policy_enqueue_select(*this, s, grid)) != FSP_OK) return rc;
+  hipLaunchKernelGGL(branch_kernel, dim3(grid), dim3(kThreads), 0, s, desc,
                      bnodes, blb, pool, n, stride, cap, rule);
   FSP_HIP_TRY(hipGetLastError());
-  int rc = launch_bound(inst, pool, stride, cap, pool_lb, stream, &desc->children);
+  rc = launch_bound(inst, pool, stride, cap, pool_lb, s, &desc->children);
   if (rc != FSP_OK) return rc;
-  hipLaunchKernelGGL(prune_kernel, dim3(grid), dim3(kThreads), 0, stream, desc,
-                     pool, pool_lb, bnodes, blb, bcount, n, stride, cap, rule);
+  hipLaunchKernelGGL(prune_kernel, dim3(grid), dim3(kThreads), 0, s, desc,
+                     pool, pool_lb, bnodes, blb, bcount, n, stride, cap, rule, log_cap,
+                     log_threshold, log_seed, log_nodes, log_lb);
   FSP_HIP_TRY(hipGetLastError());
+  if (model && (rc = policy_enqueue_score(*this, s, grid)) != FSP_OK) return rc;
+  return FSP_OK;
+}
+
+// Capture `iters` iterations once; every replay then costs one graph launch.
+// The kernels read their sizes and the pool target from device memory, so
+// one graph serves every pool size.
+int BnbState::capture(int iters) {
+  FSP_HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+  FSP_HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = FSP_OK;
+  for (int i = 0; i < iters && rc == FSP_OK; ++i) rc = enqueue_iteration(cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cap_stream, &g);
+  if (rc != FSP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return FSP_EDEVICE;
+  graph = g;
+  FSP_HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  return FSP_OK;
+}
+
+int BnbState::replay() {
+  FSP_HIP_TRY(hipGraphLaunch(exec, stream));
   return FSP_OK;
 }
 
@@ -455,25 +538,50 @@ void AdaptivePolicy::observe(double efficiency) {
 }  // namespace fspi
 
 // ---------------------------------------------------------------------------
-extern "C" {
+namespace {
 
-int fsp_neh(const fsp_instance *inst, uint8_t *perm_out, int32_t *makespan_out) {
-  if (!inst) return FSP_EINVAL;
-  std::vector<uint8_t> perm;
-  const int64_t c = neh_host(inst->p_host, inst->n, inst->m, perm);
-  if (perm_out) std::copy(perm.begin(), perm.end(), perm_out);
-  if (makespan_out) *makespan_out = (int32_t)c;
-  return FSP_OK;
+struct SampleSpec {
+  int64_t cap;      // samples to keep at most
+  double prob;      // probability that a surviving child is logged
+  uint64_t seed;
+  void *x;          // device bf16 [cap][32]
+  float *target;    // device fp32 [cap][2]
+  int64_t *n_out;   // host
+};
+
+struct TuneEntry {
+  int dev, n, m;
+  int64_t pool;
+  double rate;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_in,
+            fsp_result *out, const SampleSpec *samples);
+
+int tuned_pool(const fsp_instance *inst, int64_t *pool) {
+  int64_t p = 0;
+  double r = 0;
+  const int rc = fsp_autotune_pool(inst, 0.0, &p, &r);
+  if (rc == FSP_OK) *pool = p;
+  return rc;
 }
 
-int fsp_branch_and_bound(const fsp_instance *inst, const fsp_pool_policy *policy,
-                         int32_t ub_in, fsp_result *out) {
+int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_in,
+            fsp_result *out, const SampleSpec *samples) {
   if (!inst || !policy || !out) return FSP_EINVAL;
   if (policy->prune_rule != FSP_PRUNE_GE && policy->prune_rule != FSP_PRUNE_GT)
     return FSP_EINVAL;
-  if (policy->kind != FSP_POOL_FIXED && policy->kind != FSP_POOL_ADAPTIVE)
-    return FSP_EUNSUPPORTED;
-  if (policy->kind == FSP_POOL_FIXED && policy->fixed_pool < 1) return FSP_EINVAL;
+  const int kind = policy->kind;
+  if (kind < FSP_POOL_FIXED || kind > FSP_POOL_LEARNED) return FSP_EINVAL;
+  if (kind == FSP_POOL_FIXED && policy->fixed_pool < 1) return FSP_EINVAL;
+  const fsp_model *model = nullptr;
+  if (kind == FSP_POOL_LEARNED) {
+    model = reinterpret_cast<const fsp_model *>(policy->model);
+    if (!model) return FSP_EINVAL;
+    if (model_in_features(model) != policy_in_features(inst->m)) return FSP_EINVAL;
+  }
   uint8_t *user_perm = out->perm;
   const auto t_start = std::chrono::steady_clock::now();
   auto elapsed = [&] {
@@ -487,27 +595,40 @@ int fsp_branch_and_bound(const fsp_instance *inst, const fsp_pool_policy *policy
   FSP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   FSP_HIP_TRY(hipDeviceGetAttribute(&max_tpm, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev));
   const int64_t device_threads = (int64_t)cus * max_tpm;
+  int64_t fixed = 0;
+  if (kind == FSP_POOL_FIXED) fixed = policy->fixed_pool;
+  if (kind == FSP_POOL_AUTOTUNED || kind == FSP_POOL_LEARNED) {
+    fixed = policy->fixed_pool;
+    if (fixed < 1) {
+      const int rc = tuned_pool(inst, &fixed);
+      if (rc != FSP_OK) return rc;
+    }
+  }
   int64_t max_pool = policy->max_pool > 0 ? policy->max_pool : device_threads;
-  if (policy->kind == FSP_POOL_FIXED) max_pool = std::max(max_pool, policy->fixed_pool);
+  if (fixed > 0) max_pool = std::max(max_pool, fixed);
   if (max_pool > (int64_t(1) << 26)) return FSP_EUNSUPPORTED;
 
-  // initial upper bound
+  // initial upper bound; the learned features are scaled by the NEH makespan
+  std::vector<uint8_t> perm_neh(n);
+  const int32_t neh = (int32_t)neh_host(inst->p_host, n, inst->m, perm_neh);
   std::vector<uint8_t> perm0(n);
   int32_t ub0;
   if (ub_in > 0) {
     ub0 = ub_in;
     for (int j = 0; j < n; ++j) perm0[j] = (uint8_t)j;
   } else {
-    ub0 = (int32_t)neh_host(inst->p_host, n, inst->m, perm0);
+    ub0 = neh;
+    perm0 = perm_neh;
   }
 
   BnbState S;
   int rc = S.init(inst, max_pool, policy->prune_rule);
-  if (rc != FSP_OK) {
-    S.release();
-    return rc;
-  }
-  rc = S.start(ub0, perm0);
+  if (rc == FSP_OK && model) rc = S.init_model(model, 1.0f / (float)neh);
+  if (rc == FSP_OK && samples) rc = S.init_log(samples->cap, samples->prob, samples->seed);
+  if (rc == FSP_OK) rc = S.start(ub0, perm0);
+  const int nb_iter = policy->nb_iterations > 0 ? policy->nb_iterations : 10;
+  const bool graphed = kind == FSP_POOL_AUTOTUNED || kind == FSP_POOL_LEARNED;
+  if (rc == FSP_OK && graphed) rc = S.capture(nb_iter);
   if (rc != FSP_OK) {
     S.release();
     return rc;
@@ -515,18 +636,22 @@ int fsp_branch_and_bound(const fsp_instance *inst, const fsp_pool_policy *policy
 
   AdaptivePolicy ap;
   ap.init(256, cus, device_threads, max_pool);
-  const int nb_iter = policy->nb_iterations > 0 ? policy->nb_iterations : 10;
   FILE *log = policy->log_path ? std::fopen(policy->log_path, "w") : nullptr;
 
   int status = 0;
   double t_found = 0.0;
   int64_t last_bounded = 1;
   int64_t target = 0;
+  const double t_loop0 = elapsed();
   while (true) {
-    target = policy->kind == FSP_POOL_FIXED ? policy->fixed_pool : ap.current;
+    target = kind == FSP_POOL_ADAPTIVE ? ap.current : fixed;
     if ((rc = S.set_target(target)) != FSP_OK) break;
     const double t0 = elapsed();
-    for (int it = 0; it < nb_iter && rc == FSP_OK; ++it) rc = S.enqueue_iteration();
+    if (graphed) {
+      rc = S.replay();
+    } else {
+      for (int it = 0; it < nb_iter && rc == FSP_OK; ++it) rc = S.enqueue_iteration(S.stream);
+    }
     if (rc != FSP_OK) break;
     if ((rc = S.read_desc()) != FSP_OK) break;
     const double t1 = elapsed();
@@ -549,7 +674,7 @@ int fsp_branch_and_bound(const fsp_instance *inst, const fsp_pool_policy *policy
       status = 1;
       break;
     }
-    if (policy->kind == FSP_POOL_ADAPTIVE && t1 > t0)
+    if (kind == FSP_POOL_ADAPTIVE && t1 > t0)
       ap.observe((double)batch_nodes / (t1 - t0));
     // clear the "improved" flag for the next batch
     if (h.improved &&
@@ -558,9 +683,21 @@ int fsp_branch_and_bound(const fsp_instance *inst, const fsp_pool_policy *policy
       break;
     }
   }
+  const double t_loop = elapsed() - t_loop0;
   if (rc == FSP_OK) rc = S.commit();
   if (rc == FSP_OK) rc = S.read_desc();
   if (log) std::fclose(log);
+  if (rc == FSP_OK && samples) {
+    const BnbDesc &h = *S.host_desc;
+    const int64_t got = std::min<int64_t>(h.log_count, samples->cap);
+    rc = policy_features(inst, S.log_nodes, S.log_lb, got, S.stride, 1.0f / (float)neh,
+                         samples->x, S.stream);
+    if (rc == FSP_OK)
+      rc = policy_label(inst, S.log_nodes, S.log_lb, got, S.stride, h.ub, 1.0f / (float)neh,
+                        samples->target, S.stream);
+    if (rc == FSP_OK && hipStreamSynchronize(S.stream) != hipSuccess) rc = FSP_EDEVICE;
+    *samples->n_out = got;
+  }
   if (rc != FSP_OK) {
     S.release();
     return rc;
@@ -587,7 +724,87 @@ int fsp_branch_and_bound(const fsp_instance *inst, const fsp_pool_policy *policy
   out->t_found_s = h.found ? t_found : 0.0;
   out->t_total_s = elapsed();
   out->final_pool = target;
+  out->t_search_s = t_loop;
   S.release();
+  return FSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fsp_neh(const fsp_instance *inst, uint8_t *perm_out, int32_t *makespan_out) {
+  if (!inst) return FSP_EINVAL;
+  std::vector<uint8_t> perm;
+  const int64_t c = neh_host(inst->p_host, inst->n, inst->m, perm);
+  if (perm_out) std::copy(perm.begin(), perm.end(), perm_out);
+  if (makespan_out) *makespan_out = (int32_t)c;
+  return FSP_OK;
+}
+
+int fsp_branch_and_bound(const fsp_instance *inst, const fsp_pool_policy *policy,
+                         int32_t ub_in, fsp_result *out) {
+  return run_bnb(inst, policy, ub_in, out, nullptr);
+}
+
+int fsp_policy_samples(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_in,
+                       int64_t max_samples, double sample_prob, uint64_t seed, void *x_out,
+                       float *target_out, int64_t *n_out, fsp_result *result) {
+  if (!inst || !policy || !x_out || !target_out || !n_out || !result || max_samples < 1)
+    return FSP_EINVAL;
+  if (policy->kind == FSP_POOL_LEARNED) return FSP_EINVAL;
+  SampleSpec s{max_samples, sample_prob, seed, x_out, target_out, n_out};
+  *n_out = 0;
+  return run_bnb(inst, policy, ub_in, result, &s);
+}
+
+int fsp_autotune_pool(const fsp_instance *inst, double budget_s, int64_t *pool_out,
+                      double *rate_out) {
+  if (!inst || !pool_out) return FSP_EINVAL;
+  int dev = 0;
+  FSP_HIP_TRY(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const TuneEntry &e : g_tune)
+      if (e.dev == dev && e.n == inst->n && e.m == inst->m) {
+        *pool_out = e.pool;
+        if (rate_out) *rate_out = e.rate;
+        return FSP_OK;
+      }
+  }
+  int cus = 0, max_tpm = 0;
+  FSP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  FSP_HIP_TRY(hipDeviceGetAttribute(&max_tpm, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev));
+  const int64_t top = std::min<int64_t>((int64_t)cus * max_tpm, int64_t(1) << 20);
+  std::vector<int64_t> cand;
+  for (int64_t c = int64_t(1) << 14; c <= top; c <<= 1) cand.push_back(c);
+  if (budget_s <= 0) budget_s = 0.25 * (double)cand.size();
+  const double slice = budget_s / (double)cand.size();
+  int64_t best = cand.front();
+  double best_rate = -1.0;
+  for (int64_t c : cand) {
+    fsp_pool_policy pol{};
+    pol.kind = FSP_POOL_AUTOTUNED;
+    pol.fixed_pool = c;
+    pol.nb_iterations = 10;
+    pol.max_pool = c;
+    pol.time_limit_s = slice;
+    pol.prune_rule = FSP_PRUNE_GE;
+    fsp_result r{};
+    const int rc = run_bnb(inst, &pol, 0, &r, nullptr);
+    if (rc != FSP_OK) return rc;
+    const double rate = r.t_search_s > 0 ? (double)r.nodes_bounded / r.t_search_s : 0.0;
+    if (rate > best_rate * 1.03) {  // a larger pool must win by more than 3 %
+      best_rate = rate;
+      best = c;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.push_back({dev, inst->n, inst->m, best, best_rate});
+  }
+  *pool_out = best;
+  if (rate_out) *rate_out = best_rate;
   return FSP_OK;
 }
 

@@ -20,7 +20,10 @@ struct BnbDesc {
   int32_t found;        // a schedule better than the initial UB was found
   int32_t improved;     // UB improved since the host last cleared this
   int32_t root_lb;
-  int32_t pad;
+  int32_t sel_count;    // nodes of the parent depth before the plan took K
+  int32_t sel_T, sel_need, sel_lo, sel_hi, sel_tie;  // best-K selection
+  int32_t feat_count;   // nodes scored after the last prune
+  int32_t log_count;    // training samples logged (may exceed the capacity)
   int64_t nodes_bounded, nodes_branched, nodes_pruned, leaves, pools;
   uint64_t best_key;    // (makespan << 32) | pool index, best leaf of a pool
 };
@@ -40,15 +43,59 @@ struct BnbState {
   BnbDesc *host_desc = nullptr;  // pinned
   int64_t *host_target = nullptr;  // pinned
   hipStream_t stream = nullptr;
+  int grid = 1;  // workgroups of the branch/prune/selection kernels
+
+  // learned ordering (model != nullptr)
+  const fsp_model *model = nullptr;
+  float inv_scale = 0.f;
+  float *bscore = nullptr;    // [n][cap] estimated completion / scale
+  uint8_t *tnodes = nullptr;  // [cap][stride] selection scratch
+  int32_t *tlb = nullptr;
+  float *tscore = nullptr;
+  int32_t *hist = nullptr;    // selection histogram (kept zeroed)
+  void *X = nullptr;          // [cap][32] bf16 features
+  float *Y = nullptr;         // [cap][outputs]
+
+  // training samples (log_cap > 0)
+  int64_t log_cap = 0;
+  uint32_t log_threshold = 0;  // keep a survivor if hash < threshold
+  uint32_t log_seed = 0;
+  uint8_t *log_nodes = nullptr;  // [log_cap][stride]
+  int32_t *log_lb = nullptr;
+
+  // captured iterations
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 
   int init(const fsp_instance *inst, int64_t max_pool, int rule);
+  int init_model(const fsp_model *model, float inv_scale);
+  int init_log(int64_t cap, double prob, uint64_t seed);
   void release();
   int start(int32_t ub0, const std::vector<uint8_t> &perm0);
   int set_target(int64_t target);
-  int enqueue_iteration();
+  int enqueue_iteration(hipStream_t s);
+  int capture(int iters);
+  int replay();
   int commit();
   int read_desc();
 };
+
+// learned ordering (policy.hip)
+int policy_enqueue_select(BnbState &S, hipStream_t s, int grid);
+int policy_enqueue_score(BnbState &S, hipStream_t s, int grid);
+int policy_features(const fsp_instance *in, const uint8_t *nodes, const int32_t *lbs,
+                    int64_t count, int stride, float inv_scale, void *X, hipStream_t s);
+int policy_label(const fsp_instance *in, const uint8_t *nodes, const int32_t *lbs,
+                 int64_t count, int stride, int32_t final_ub, float inv_scale, float *target,
+                 hipStream_t s);
+int policy_in_features(int m);
+
+// network (mlp.hip)
+int model_forward_dev(const fsp_model *m, const void *x, const int32_t *n_dev, int64_t max_n,
+                      float *y, hipStream_t s);
+int model_outputs(const fsp_model *m);
+int model_in_features(const fsp_model *m);
 
 struct AdaptivePolicy {
   int nb_threads = 256, nb_blocks = 0;

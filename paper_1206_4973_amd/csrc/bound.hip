@@ -113,8 +113,8 @@ namespace fspi {
 InstView inst_view(const fsp_instance *inst, size_t table_budget) {
   InstView v{};
   v.p = inst->d_p;
-  v.H = inst->d_H;
-  v.Q = inst->d_Q;
+  v.Hp = inst->d_Hp;
+  v.Qp = inst->d_Qp;
   v.tot = inst->d_tot;
   v.rec = inst->d_rec;
   v.n = inst->n;

@@ -11,8 +11,8 @@ namespace fspi {
 // Everything the bound needs about one instance (device pointers).
 struct InstView {
   const int32_t *__restrict__ p;    // [n][mp]
-  const int32_t *__restrict__ H;    // [n][mp]
-  const int32_t *__restrict__ Q;    // [n][mp]
+  const uint32_t *__restrict__ Hp;  // [n][mp/2] head sums, packed 16-bit pairs
+  const uint32_t *__restrict__ Qp;  // [n][mp/2] tail sums, packed 16-bit pairs
   const int32_t *__restrict__ tot;  // [mp]
   const void *__restrict__ rec;     // [P][npad]
   int n, mp, npad, P;
@@ -29,7 +29,7 @@ struct LdsView {
   uint32_t *s_words;  // wide only
 };
 
-constexpr int kBig = 1 << 20;  // > any head or tail sum (<= 65535)
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 template <int M>
 __host__ __device__ constexpr int pair_index(int k, int l) {
@@ -313,54 +313,48 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
     }
   }
 
-  // ---- 2. heads, remaining work, tails (two passes over the jobs, so
-  //         that only 60 per-node values are live at a time) ----
+  // ---- 2. heads, tails, remaining work.  Head and tail sums are at most
+  //         65535 (instance limits), so the minima over the unscheduled jobs
+  //         run on packed 16-bit pairs of machines: a scheduled job's pair is
+  //         forced to 0xffff by an unsigned max with its all-ones sign mask,
+  //         then one unsigned min per pair of machines. ----
   int T256[M], R256[M], Q256[M];
   {
-    int hm[M];
+    constexpr int M2 = (M + 1) / 2;
+    u16x2 hm2[M2], qm2[M2];
 #pragma unroll
-    for (int k = 0; k < M; ++k) hm[k] = kBig;
+    for (int t = 0; t < M2; ++t) hm2[t] = qm2[t] = (u16x2){0xffff, 0xffff};
+    const int mp2 = mp / 2;
     for (int j = 0; j < n; ++j) {
-      uint32_t gone;
+      uint32_t g;
       if constexpr (WIDE)
-        gone = __builtin_amdgcn_ubfe(~words_lane[(j >> 5) * kBlock],
-                                     (uint32_t)j, 1u);
+        g = (uint32_t)__builtin_amdgcn_sbfe((int)~words_lane[(j >> 5) * kBlock], j & 31, 1);
       else
-        gone = __builtin_amdgcn_ubfe(~U, (uint32_t)j, 1u);
-      const int32_t *hr = I.H + j * mp;
+        g = (uint32_t)__builtin_amdgcn_sbfe((int)~U, j, 1);
+      const u16x2 gv = __builtin_bit_cast(u16x2, g);
+      const uint32_t *hr = I.Hp + j * mp2;
+      const uint32_t *qr = I.Qp + j * mp2;
 #pragma unroll
-      for (int k = 0; k < M; ++k)
-        hm[k] = min(hm[k], (int)__umul24(gone, kBig) + hr[k]);
+      for (int t = 0; t < M2; ++t) {
+        hm2[t] = __builtin_elementwise_min(
+            hm2[t], __builtin_elementwise_max(__builtin_bit_cast(u16x2, hr[t]), gv));
+        qm2[t] = __builtin_elementwise_min(
+            qm2[t], __builtin_elementwise_max(__builtin_bit_cast(u16x2, qr[t]), gv));
+      }
     }
-    // the column totals are loaded here, not hoisted above the head loop
-    // where they would hold 20 more registers
+    // the column totals are loaded here, not hoisted above the loop
     asm volatile("" ::: "memory");
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-      const int r = max(F[k], F[0] + hm[k]);
+      const int hmk = (k & 1) ? hm2[k >> 1].y : hm2[k >> 1].x;
+      const int qmk = (k & 1) ? qm2[k >> 1].y : qm2[k >> 1].x;
+      const int r = max(F[k], F[0] + hmk);
       R256[k] = r << 8;
       T256[k] = (r + I.tot[k] - Pk[k]) << 8;
+      Q256[k] = qmk << 8;
     }
   }
   const int last = F[M - 1];
-  {
-#pragma unroll
-    for (int k = 0; k < M; ++k) Q256[k] = kBig;
-    for (int j = 0; j < n; ++j) {
-      uint32_t gone;
-      if constexpr (WIDE)
-        gone = __builtin_amdgcn_ubfe(~words_lane[(j >> 5) * kBlock],
-                                     (uint32_t)j, 1u);
-      else
-        gone = __builtin_amdgcn_ubfe(~U, (uint32_t)j, 1u);
-      const int32_t *qr = I.Q + j * mp;
-#pragma unroll
-      for (int k = 0; k < M; ++k)
-        Q256[k] = min(Q256[k], (int)__umul24(gone, kBig) + qr[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < M; ++k) Q256[k] <<= 8;
-  }
 
   // ---- 3. every machine pair ----
   int LB256 = 0;

@@ -4,6 +4,7 @@
 //   p   [n][MP]  processing times
 //   H   [n][MP]  H[j][k] = sum_{h<k} p[j][h]    (work before machine k)
 //   Q   [n][MP]  Q[j][k] = sum_{h>k} p[j][h]    (work after machine k)
+//   Hp, Qp [n][MP/2]  H and Q as 16-bit pairs (machines 2t, 2t+1)
 //   tot [MP]     tot[k]  = sum_j p[j][k]
 //   rec [P][npad] per machine pair (lexicographic k<l), the jobs in Johnson
 //                 order with lags, one record per position, padded to npad
@@ -44,6 +45,7 @@ struct fsp_instance {
   int wide = 0;    // 1 when n > 32 (records carry the job id separately)
   int device = 0;
   int32_t *d_p = nullptr, *d_H = nullptr, *d_Q = nullptr, *d_tot = nullptr;
+  uint32_t *d_Hp = nullptr, *d_Qp = nullptr;  // H, Q as packed 16-bit pairs
   void *d_rec = nullptr;    // NarrowRec or WideRec [P][npad]
   size_t rec_bytes = 0;
   std::vector<int32_t> p_host;  // [n][m], for host-side set-up work (NEH)

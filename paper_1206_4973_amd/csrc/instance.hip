@@ -23,7 +23,8 @@ namespace {
 
 __global__ void stage_rows(const int32_t *__restrict__ p_in, int n, int m,
                            int mp, int32_t *__restrict__ p,
-                           int32_t *__restrict__ H, int32_t *__restrict__ Q) {
+                           int32_t *__restrict__ H, int32_t *__restrict__ Q,
+                           uint32_t *__restrict__ Hp, uint32_t *__restrict__ Qp) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   int row = 0;
@@ -35,6 +36,13 @@ __global__ void stage_rows(const int32_t *__restrict__ p_in, int n, int m,
     H[j * mp + k] = k < m ? before : 0;
     Q[j * mp + k] = k < m ? row - before - v : 0;
     before += v;
+  }
+  // sums are <= 65535 (a job's total time), so two fit in a word
+  for (int t = 0; t < mp / 2; ++t) {
+    Hp[j * (mp / 2) + t] =
+        (uint32_t)H[j * mp + 2 * t] | ((uint32_t)H[j * mp + 2 * t + 1] << 16);
+    Qp[j * (mp / 2) + t] =
+        (uint32_t)Q[j * mp + 2 * t] | ((uint32_t)Q[j * mp + 2 * t + 1] << 16);
   }
 }
 
@@ -110,6 +118,9 @@ void free_device(fsp_instance *in) {
   if (in->d_Q) (void)hipFree(in->d_Q);
   if (in->d_tot) (void)hipFree(in->d_tot);
   if (in->d_rec) (void)hipFree(in->d_rec);
+  if (in->d_Hp) (void)hipFree(in->d_Hp);
+  if (in->d_Qp) (void)hipFree(in->d_Qp);
+  in->d_Hp = in->d_Qp = nullptr;
   in->d_p = in->d_H = in->d_Q = in->d_tot = nullptr;
   in->d_rec = nullptr;
 }
@@ -121,7 +132,9 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
       hipMalloc(&in->d_H, mat) != hipSuccess ||
       hipMalloc(&in->d_Q, mat) != hipSuccess ||
       hipMalloc(&in->d_tot, mp * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&in->d_rec, in->rec_bytes) != hipSuccess)
+      hipMalloc(&in->d_rec, in->rec_bytes) != hipSuccess ||
+      hipMalloc(&in->d_Hp, mat / 2) != hipSuccess ||
+      hipMalloc(&in->d_Qp, mat / 2) != hipSuccess)
     return FSP_ENOMEM;
   int32_t *d_in = nullptr;
   if (hipMalloc(&d_in, (size_t)n * m * sizeof(int32_t)) != hipSuccess)
@@ -133,7 +146,7 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
     rc = FSP_EDEVICE;
   if (rc == FSP_OK) {
     hipLaunchKernelGGL(stage_rows, dim3((n + 63) / 64), dim3(64), 0, s, d_in,
-                       n, m, mp, in->d_p, in->d_H, in->d_Q);
+                       n, m, mp, in->d_p, in->d_H, in->d_Q, in->d_Hp, in->d_Qp);
     hipLaunchKernelGGL(stage_totals, dim3(1), dim3(64), 0, s, in->d_p, n, mp,
                        in->d_tot);
     hipLaunchKernelGGL(stage_pairs, dim3(in->P), dim3(256), 0, s, in->d_p, n,

@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "fsp_internal.hpp"
+#include "bnb.hpp"
 
 namespace {
 
@@ -105,11 +106,14 @@ __global__ void export_kernel(const float *__restrict__ P, bf16 *__restrict__ E)
 // ---------------------------------------------------------------------------
 // forward: x [N][kIn] bf16 -> y [N][nout] fp32
 __global__ __launch_bounds__(256) void forward_kernel(
-    const bf16 *__restrict__ X, int64_t N, const float *__restrict__ P,
-    const bf16 *__restrict__ E, float *__restrict__ Y, int nout) {
+    const bf16 *__restrict__ X, int64_t N, const int32_t *__restrict__ n_dev,
+    const float *__restrict__ P, const bf16 *__restrict__ E, float *__restrict__ Y,
+    int nout) {
   __shared__ __align__(16) bf16 sH[4][16 * kH];  // one 16-row stripe per wave
   const int w = threadIdx.x >> 6;
   bf16 *H = sH[w];
+  if (n_dev) N = *n_dev;  // row count produced on the device
+  if (N <= 0) return;
   const int64_t stripes = (N + 15) / 16;
   // every wave of the workgroup runs the same number of rounds (a wave past
   // the last stripe recomputes the clamped last rows and stores nothing), so
@@ -469,17 +473,23 @@ int ensure_scratch(fsp_model *m, int64_t rows) {
 }  // namespace
 
 namespace fspi {
-int model_forward(const fsp_model *m, const void *x, int64_t n, float *y, hipStream_t s) {
-  if (n == 0) return FSP_OK;
-  const int64_t stripes = (n + 15) / 16;
+int model_forward_dev(const fsp_model *m, const void *x, const int32_t *n_dev, int64_t max_n,
+                      float *y, hipStream_t s) {
+  if (max_n <= 0) return FSP_OK;
+  const int64_t stripes = (max_n + 15) / 16;
   int64_t grid = (stripes + 3) / 4;
   if (grid > (int64_t)m->cus * 8) grid = (int64_t)m->cus * 8;
   hipLaunchKernelGGL(forward_kernel, dim3((unsigned)grid), dim3(256), 0, s,
-                     reinterpret_cast<const bf16 *>(x), n, m->P, m->E, y, m->outputs);
+                     reinterpret_cast<const bf16 *>(x), max_n, n_dev, m->P, m->E, y,
+                     m->outputs);
   FSP_HIP_TRY(hipGetLastError());
   return FSP_OK;
 }
+int model_forward(const fsp_model *m, const void *x, int64_t n, float *y, hipStream_t s) {
+  return model_forward_dev(m, x, nullptr, n, y, s);
+}
 int model_outputs(const fsp_model *m) { return m->outputs; }
+int model_in_features(const fsp_model *m) { return m->in_features; }
 }  // namespace fspi
 
 extern "C" {

@@ -1,0 +1,378 @@
+// policy.hip -- device side of the learned pool policy.
+//
+// The policy network (mlp.hip) scores pending nodes; the scores only decide
+// which nodes of the deepest depth are branched first (and so how soon good
+// schedules, hence a low UB, are found).  The exact integer bound still
+// decides every elimination, so the optimum is untouched.
+//
+//   features   node record -> x in R^32 (bf16): depth / n, bound / scale,
+//              and for up to 15 machines the prefix completion time and the
+//              remaining work, / scale (scale = the initial UB).  2m+2
+//              features for m <= 15 machines; above, 15 evenly spaced
+//              machines.
+//   score      est = bound / scale + y0 (y0: predicted completion gap): the
+//              estimated best completion; smaller is more promising.
+//   selection  when the plan takes K < count nodes of a depth, the K nodes
+//              with the smallest est are moved to the top of the bucket
+//              (histogram of est, threshold, partition through a scratch
+//              buffer).  All sizes come from the device descriptor, so the
+//              kernels are captured with the rest of the iteration.
+//   samples    the prune step logs a deterministic pseudo-random sample of
+//              the surviving children (training data); labels come from a
+//              suffix-NEH completion of each logged node (y0 target) and
+//              from whether its bound reaches the final UB (y1 target).
+#include <hip/hip_runtime.h>
+
+#include "bnb.hpp"
+#include "fsp_internal.hpp"
+
+namespace fspi {
+
+namespace {
+
+constexpr int kFeat = 32;
+constexpr int kMaxFeatMachines = 15;
+
+__device__ __forceinline__ int feat_machine(int t, int m, int mm) {
+  return mm == m ? t : (t * (m - 1) + (mm - 1) / 2) / (mm - 1);
+}
+
+}  // namespace
+
+// ---- features of the nodes of bucket `depth + 1` --------------------------
+__global__ void features_kernel(BnbDesc *D, const int32_t *__restrict__ bcount,
+                                const uint8_t *__restrict__ bnodes,
+                                const int32_t *__restrict__ blb, int64_t cap,
+                                int stride, const int32_t *__restrict__ p,
+                                const int32_t *__restrict__ tot, int n, int m, int mp,
+                                float inv_scale, __bf16 *__restrict__ X) {
+  const bool act = D->active && D->depth + 1 < n;
+  const int d1 = D->depth + 1;
+  const int count = act ? bcount[d1] : 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) D->feat_count = count;
+  const int mm = m < kMaxFeatMachines ? m : kMaxFeatMachines;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t at = (int64_t)d1 * cap + i;
+    const uint8_t *rec = bnodes + at * stride;
+    int F[kMaxMachines], S[kMaxMachines];
+    for (int k = 0; k < m; ++k) {
+      F[k] = 0;
+      S[k] = tot[k];
+    }
+    const int d = rec[0];
+    for (int q = 0; q < d; ++q) {
+      const int j = rec[1 + q];
+      const int32_t *row = p + j * mp;
+      F[0] += row[0];
+      S[0] -= row[0];
+      for (int k = 1; k < m; ++k) {
+        F[k] = max(F[k], F[k - 1]) + row[k];
+        S[k] -= row[k];
+      }
+    }
+    __bf16 *x = X + i * kFeat;
+    float f[kFeat];
+    for (int t = 0; t < kFeat; ++t) f[t] = 0.f;
+    f[0] = (float)d / (float)n;
+    f[1] = (float)blb[at] * inv_scale;
+    for (int t = 0; t < mm; ++t) {
+      const int k = feat_machine(t, m, mm);
+      f[2 + t] = (float)F[k] * inv_scale;
+      f[2 + mm + t] = (float)S[k] * inv_scale;
+    }
+    for (int t = 0; t < kFeat; ++t) x[t] = (__bf16)f[t];
+  }
+}
+
+__global__ void score_kernel(BnbDesc *D, const int32_t *__restrict__ blb,
+                             float *__restrict__ bscore, int64_t cap,
+                             const float *__restrict__ Y, int nout, float inv_scale) {
+  const int count = D->feat_count;
+  const int d1 = D->depth + 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t at = (int64_t)d1 * cap + i;
+    bscore[at] = (float)blb[at] * inv_scale + Y[i * nout];
+  }
+}
+
+// ---- best-K selection ------------------------------------------------------
+constexpr int kBins = 4096;
+constexpr float kBinScale = 2048.f;  // est in [0, 2)
+
+__device__ __forceinline__ int est_bin(float e) {
+  const float b = e * kBinScale;
+  return b <= 0.f ? 0 : (b >= (float)(kBins - 1) ? kBins - 1 : (int)b);
+}
+
+__device__ __forceinline__ bool sel_needed(const BnbDesc *D) {
+  return D->active && D->parents < D->sel_count;
+}
+
+__global__ void sel_hist_kernel(const BnbDesc *D, const float *__restrict__ bscore,
+                                int64_t cap, int32_t *__restrict__ hist) {
+  if (!sel_needed(D)) return;
+  const int count = D->sel_count;
+  const int64_t base = (int64_t)D->depth * cap;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&hist[est_bin(bscore[base + i])], 1);
+}
+
+// one workgroup of 256 threads; clears the histogram for its next use
+__global__ __launch_bounds__(256) void sel_thresh_kernel(BnbDesc *D,
+                                                         int32_t *__restrict__ hist) {
+  if (!sel_needed(D)) return;
+  __shared__ int part[256];
+  const int t = threadIdx.x;
+  constexpr int per = kBins / 256;
+  int s = 0;
+  for (int b = 0; b < per; ++b) s += hist[t * per + b];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    const int K = D->parents;
+    int cum = 0, T = kBins - 1, above = 0;
+    for (int c = 0; c < 256; ++c) {
+      if (cum + part[c] >= K) {
+        int cb = cum;
+        for (int b = 0; b < per; ++b) {
+          const int h = hist[c * per + b];
+          if (cb + h >= K) {
+            T = c * per + b;
+            above = cb;
+            break;
+          }
+          cb += h;
+        }
+        break;
+      }
+      cum += part[c];
+    }
+    D->sel_T = T;
+    D->sel_need = K - above;
+    D->sel_lo = 0;
+    D->sel_hi = 0;
+    D->sel_tie = 0;
+  }
+  __syncthreads();
+  for (int b = 0; b < per; ++b) hist[t * per + b] = 0;
+}
+
+__global__ void sel_partition_kernel(BnbDesc *D, const uint8_t *__restrict__ bnodes,
+                                     const int32_t *__restrict__ blb,
+                                     const float *__restrict__ bscore, int64_t cap,
+                                     int stride, uint8_t *__restrict__ tnodes,
+                                     int32_t *__restrict__ tlb, float *__restrict__ tscore) {
+  if (!sel_needed(D)) return;
+  const int count = D->sel_count, K = D->parents, T = D->sel_T, need = D->sel_need;
+  const int64_t base = (int64_t)D->depth * cap;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float e = bscore[base + i];
+    const int b = est_bin(e);
+    bool take = b < T;
+    if (b == T) take = atomicAdd(&D->sel_tie, 1) < need;
+    const int pos = take ? count - K + atomicAdd(&D->sel_hi, 1) : atomicAdd(&D->sel_lo, 1);
+    const uint4 *src = reinterpret_cast<const uint4 *>(bnodes + (base + i) * stride);
+    uint4 *dst = reinterpret_cast<uint4 *>(tnodes + (int64_t)pos * stride);
+    for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
+    tlb[pos] = blb[base + i];
+    tscore[pos] = e;
+  }
+}
+
+__global__ void sel_copyback_kernel(const BnbDesc *D, uint8_t *__restrict__ bnodes,
+                                    int32_t *__restrict__ blb, float *__restrict__ bscore,
+                                    int64_t cap, int stride, const uint8_t *__restrict__ tnodes,
+                                    const int32_t *__restrict__ tlb,
+                                    const float *__restrict__ tscore) {
+  if (!sel_needed(D)) return;
+  const int count = D->sel_count;
+  const int64_t base = (int64_t)D->depth * cap;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(tnodes + i * stride);
+    uint4 *dst = reinterpret_cast<uint4 *>(bnodes + (base + i) * stride);
+    for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
+    blb[base + i] = tlb[i];
+    bscore[base + i] = tscore[i];
+  }
+}
+
+// ---- training samples --------------------------------------------------------
+
+// suffix-NEH completion of a node: the unscheduled jobs, by total work
+// descending (ties by id), are inserted one by one at the position of the
+// suffix giving the smallest makespan (earliest on ties); the prefix stays.
+__global__ void label_kernel(const uint8_t *__restrict__ nodes, const int32_t *__restrict__ lbs,
+                             int64_t count, int stride, const int32_t *__restrict__ p, int n,
+                             int m, int mp, int32_t final_ub, float inv_scale,
+                             float *__restrict__ target) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint8_t *rec = nodes + i * stride;
+  const int d = rec[0];
+  uint32_t used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int F[kMaxMachines];
+  for (int k = 0; k < m; ++k) F[k] = 0;
+  for (int q = 0; q < d; ++q) {
+    const int j = rec[1 + q];
+    used[j >> 5] |= 1u << (j & 31);
+    const int32_t *row = p + j * mp;
+    F[0] += row[0];
+    for (int k = 1; k < m; ++k) F[k] = max(F[k], F[k - 1]) + row[k];
+  }
+  uint8_t seq[256];  // the suffix being built
+  int len = 0;
+  uint32_t taken[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int step = 0; step < n - d; ++step) {
+    // next job: largest total work among the unscheduled, smallest id on ties
+    int best_j = -1, best_w = -1;
+    for (int j = 0; j < n; ++j) {
+      if ((used[j >> 5] >> (j & 31)) & 1u) continue;
+      if ((taken[j >> 5] >> (j & 31)) & 1u) continue;
+      int w = 0;
+      for (int k = 0; k < m; ++k) w += p[j * mp + k];
+      if (w > best_w) {
+        best_w = w;
+        best_j = j;
+      }
+    }
+    taken[best_j >> 5] |= 1u << (best_j & 31);
+    int best_pos = 0, best_c = 0x7fffffff;
+    for (int pos = 0; pos <= len; ++pos) {
+      int c[kMaxMachines];
+      for (int k = 0; k < m; ++k) c[k] = F[k];
+      for (int q = 0; q <= len; ++q) {
+        const int j = q < pos ? seq[q] : (q == pos ? best_j : seq[q - 1]);
+        const int32_t *row = p + j * mp;
+        c[0] += row[0];
+        for (int k = 1; k < m; ++k) c[k] = max(c[k], c[k - 1]) + row[k];
+      }
+      if (c[m - 1] < best_c) {
+        best_c = c[m - 1];
+        best_pos = pos;
+      }
+    }
+    for (int q = len; q > best_pos; --q) seq[q] = seq[q - 1];
+    seq[best_pos] = (uint8_t)best_j;
+    ++len;
+  }
+  int c_final;
+  if (len == 0) {
+    c_final = F[m - 1];
+  } else {
+    int c[kMaxMachines];
+    for (int k = 0; k < m; ++k) c[k] = F[k];
+    for (int q = 0; q < len; ++q) {
+      const int32_t *row = p + seq[q] * mp;
+      c[0] += row[0];
+      for (int k = 1; k < m; ++k) c[k] = max(c[k], c[k - 1]) + row[k];
+    }
+    c_final = c[m - 1];
+  }
+  target[i * 2 + 0] = (float)(c_final - lbs[i]) * inv_scale;
+  target[i * 2 + 1] = lbs[i] >= final_ub ? 1.f : 0.f;
+}
+
+// ---- host helpers ------------------------------------------------------------
+int policy_enqueue_select(BnbState &S, hipStream_t s, int grid) {
+  hipLaunchKernelGGL(sel_hist_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.bscore, S.cap,
+                     S.hist);
+  hipLaunchKernelGGL(sel_thresh_kernel, dim3(1), dim3(256), 0, s, S.desc, S.hist);
+  hipLaunchKernelGGL(sel_partition_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.bnodes,
+                     S.blb, S.bscore, S.cap, S.stride, S.tnodes, S.tlb, S.tscore);
+  hipLaunchKernelGGL(sel_copyback_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.bnodes,
+                     S.blb, S.bscore, S.cap, S.stride, S.tnodes, S.tlb, S.tscore);
+  FSP_HIP_TRY(hipGetLastError());
+  return FSP_OK;
+}
+
+int policy_enqueue_score(BnbState &S, hipStream_t s, int grid) {
+  const fsp_instance *in = S.inst;
+  hipLaunchKernelGGL(features_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.bcount, S.bnodes,
+                     S.blb, S.cap, S.stride, in->d_p, in->d_tot, in->n, in->m, in->mp,
+                     S.inv_scale, reinterpret_cast<__bf16 *>(S.X));
+  FSP_HIP_TRY(hipGetLastError());
+  int rc = model_forward_dev(S.model, S.X, &S.desc->feat_count, S.cap, S.Y, s);
+  if (rc != FSP_OK) return rc;
+  hipLaunchKernelGGL(score_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.blb, S.bscore, S.cap,
+                     S.Y, model_outputs(S.model), S.inv_scale);
+  FSP_HIP_TRY(hipGetLastError());
+  return FSP_OK;
+}
+
+int policy_features(const fsp_instance *in, const uint8_t *nodes, const int32_t *lbs,
+                    int64_t count, int stride, float inv_scale, void *X, hipStream_t s);
+
+int policy_label(const fsp_instance *in, const uint8_t *nodes, const int32_t *lbs,
+                 int64_t count, int stride, int32_t final_ub, float inv_scale, float *target,
+                 hipStream_t s) {
+  if (count == 0) return FSP_OK;
+  hipLaunchKernelGGL(label_kernel, dim3((unsigned)((count + 127) / 128)), dim3(128), 0, s,
+                     nodes, lbs, count, stride, in->d_p, in->n, in->m, in->mp, final_ub,
+                     inv_scale, target);
+  FSP_HIP_TRY(hipGetLastError());
+  return FSP_OK;
+}
+
+// features of an explicit list of nodes (training samples): reuse the bucket
+// kernel through a one-bucket view
+namespace {
+__global__ void features_list_kernel(const uint8_t *__restrict__ nodes,
+                                     const int32_t *__restrict__ lbs, int64_t count,
+                                     int stride, const int32_t *__restrict__ p,
+                                     const int32_t *__restrict__ tot, int n, int m, int mp,
+                                     float inv_scale, __bf16 *__restrict__ X) {
+  const int mm = m < kMaxFeatMachines ? m : kMaxFeatMachines;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint8_t *rec = nodes + i * stride;
+    int F[kMaxMachines], S[kMaxMachines];
+    for (int k = 0; k < m; ++k) {
+      F[k] = 0;
+      S[k] = tot[k];
+    }
+    const int d = rec[0];
+    for (int q = 0; q < d; ++q) {
+      const int j = rec[1 + q];
+      const int32_t *row = p + j * mp;
+      F[0] += row[0];
+      S[0] -= row[0];
+      for (int k = 1; k < m; ++k) {
+        F[k] = max(F[k], F[k - 1]) + row[k];
+        S[k] -= row[k];
+      }
+    }
+    float f[kFeat];
+    for (int t = 0; t < kFeat; ++t) f[t] = 0.f;
+    f[0] = (float)d / (float)n;
+    f[1] = (float)lbs[i] * inv_scale;
+    for (int t = 0; t < mm; ++t) {
+      const int k = feat_machine(t, m, mm);
+      f[2 + t] = (float)F[k] * inv_scale;
+      f[2 + mm + t] = (float)S[k] * inv_scale;
+    }
+    for (int t = 0; t < kFeat; ++t) X[i * kFeat + t] = (__bf16)f[t];
+  }
+}
+}  // namespace
+
+int policy_features(const fsp_instance *in, const uint8_t *nodes, const int32_t *lbs,
+                    int64_t count, int stride, float inv_scale, void *X, hipStream_t s) {
+  if (count == 0) return FSP_OK;
+  hipLaunchKernelGGL(features_list_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                     s, nodes, lbs, count, stride, in->d_p, in->d_tot, in->n, in->m, in->mp,
+                     inv_scale, reinterpret_cast<__bf16 *>(X));
+  FSP_HIP_TRY(hipGetLastError());
+  return FSP_OK;
+}
+
+int policy_in_features(int m) {
+  const int mm = m < kMaxFeatMachines ? m : kMaxFeatMachines;
+  return 2 + 2 * mm;
+}
+
+}  // namespace fspi

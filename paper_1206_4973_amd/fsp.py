@@ -67,7 +67,7 @@ class _Result(ctypes.Structure):
                 ("nodes_branched", ctypes.c_int64), ("nodes_pruned", ctypes.c_int64),
                 ("leaves", ctypes.c_int64), ("pools", ctypes.c_int64),
                 ("t_found_s", ctypes.c_double), ("t_total_s", ctypes.c_double),
-                ("final_pool", ctypes.c_int64)]
+                ("final_pool", ctypes.c_int64), ("t_search_s", ctypes.c_double)]
 
 
 def lib() -> ctypes.CDLL:
@@ -109,6 +109,13 @@ def lib() -> ctypes.CDLL:
     L.fsp_batch_free.restype = ctypes.c_int
     L.fsp_bound_batch.argtypes = [ctypes.POINTER(_Segment), i32, P]
     L.fsp_bound_batch.restype = ctypes.c_int
+    L.fsp_autotune_pool.argtypes = [P, ctypes.c_double, ctypes.POINTER(i64),
+                                    ctypes.POINTER(ctypes.c_double)]
+    L.fsp_autotune_pool.restype = ctypes.c_int
+    L.fsp_policy_samples.argtypes = [P, ctypes.POINTER(_Policy), i32, i64, ctypes.c_double,
+                                     ctypes.c_uint64, P, P, ctypes.POINTER(i64),
+                                     ctypes.POINTER(_Result)]
+    L.fsp_policy_samples.restype = ctypes.c_int
     L.fsp_model_create.argtypes = [i32, i32, i32, ctypes.c_uint64, ctypes.POINTER(P)]
     L.fsp_model_create.restype = ctypes.c_int
     L.fsp_model_free.argtypes = [P]
@@ -215,7 +222,8 @@ class Result:
 
     def __repr__(self):
         keys = ("makespan", "found", "status", "root_lb", "nodes_bounded", "nodes_branched",
-                "nodes_pruned", "leaves", "pools", "t_found_s", "t_total_s", "final_pool")
+                "nodes_pruned", "leaves", "pools", "t_found_s", "t_total_s", "t_search_s",
+                "final_pool")
         return "Result(" + ", ".join(f"{k}={getattr(self, k)}" for k in keys) + ")"
 
 
@@ -245,6 +253,35 @@ def branch_and_bound(inst: Instance, kind: str = "adaptive", ub: int | None = No
                                       int(ub) if ub else 0, ctypes.byref(res)),
            "fsp_branch_and_bound")
     return Result(res, perm[:inst.n].copy())
+
+
+def autotune_pool(inst: Instance, budget_s: float = 0.0):
+    """(pool size, nodes/s) picked by fsp_autotune_pool for this shape (cached)."""
+    pool, rate = ctypes.c_int64(), ctypes.c_double()
+    _check(lib().fsp_autotune_pool(inst.handle, float(budget_s), ctypes.byref(pool),
+                                   ctypes.byref(rate)), "fsp_autotune_pool")
+    return int(pool.value), float(rate.value)
+
+
+def policy_samples(inst: Instance, max_samples: int, sample_prob: float, seed: int = 0,
+                   kind: str = "adaptive", ub: int | None = None, **policy):
+    """Training samples logged by a search (fsp_policy_samples).
+
+    Returns (x bf16 [k, 32], target fp32 [k, 2], Result), device tensors."""
+    pol = make_policy(kind, **policy)
+    x = torch.empty((max_samples, 32), dtype=torch.bfloat16, device="cuda")
+    t = torch.empty((max_samples, 2), dtype=torch.float32, device="cuda")
+    nout = ctypes.c_int64()
+    perm = np.zeros(max(inst.n, 1), dtype=np.uint8)
+    res = _Result()
+    res.perm = perm.ctypes.data_as(ctypes.c_void_p).value
+    _check(lib().fsp_policy_samples(inst.handle, ctypes.byref(pol), int(ub) if ub else 0,
+                                    int(max_samples), float(sample_prob), ctypes.c_uint64(seed),
+                                    ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                    ctypes.byref(nout), ctypes.byref(res)),
+           "fsp_policy_samples")
+    k = int(nout.value)
+    return x[:k], t[:k], Result(res, perm[:inst.n].copy())
 
 
 def neh(inst: Instance):

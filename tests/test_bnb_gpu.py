@@ -98,8 +98,11 @@ def test_critical_tree_counts_equal_oracle(fsp, orc, n, m, seed, rule):
     oc, _, ost = orc.bnb(p, opt, 0 if rule == "ge" else 1)
     assert oc == opt and ost.complete == 1
     inst = fsp.Instance(p)
+    model = fsp.Model(2 + 2 * min(m, 15), 2, seed=seed)
     for kind, kw in (("fixed", {"fixed_pool": 1}), ("fixed", {"fixed_pool": 37}),
-                     ("fixed", {"fixed_pool": 100000}), ("adaptive", {})):
+                     ("fixed", {"fixed_pool": 100000}), ("adaptive", {}),
+                     ("autotuned", {"fixed_pool": 64}), ("learned", {"fixed_pool": 5, "model": model}),
+                     ("learned", {"fixed_pool": 3000, "model": model})):
         res = fsp.branch_and_bound(inst, kind, ub=opt, prune_rule=rule, **kw)
         say(f"{n}x{m} {rule} {kind} {kw}: {res.nodes_bounded} vs {ost.nodes_bounded}")
         assert res.makespan == opt and res.found == 0 and res.status == 0
@@ -130,3 +133,64 @@ def test_policy_errors(fsp):
     inst = fsp.Instance(I.instance(8, 4, 3))
     with pytest.raises(fsp.FspError):
         fsp.branch_and_bound(inst, "fixed", fixed_pool=0)
+
+
+@pytest.mark.parametrize("kind", ["autotuned", "learned"])
+def test_graphed_kinds_reach_the_optimum(fsp, orc, kind):
+    for n, m, seed in ((9, 5, 1000), (12, 8, 62), (15, 6, 67), (20, 10, 4052)):
+        p = I.instance(n, m, seed)
+        oc, _, ost = orc.bnb(p)
+        inst = fsp.Instance(p)
+        kw = {}
+        if kind == "learned":
+            kw["model"] = fsp.Model(2 + 2 * min(m, 15), 2, seed=1)
+        for pool in (7, 4096):
+            res = fsp.branch_and_bound(inst, kind, fixed_pool=pool, **kw)
+            say(f"{kind} {n}x{m} pool {pool}: {res.makespan} vs {oc}, {res.nodes_bounded} nodes")
+            assert res.status == 0 and res.makespan == oc
+            check_schedule(orc, p, res)
+
+
+def test_autotuner_picks_a_candidate_and_caches_it(fsp):
+    inst = fsp.Instance(I.instance(20, 10, 4046))
+    pool, rate = fsp.autotune_pool(inst, 0.8)
+    say("autotuned pool", pool, "rate", rate)
+    assert pool >= 1 << 14 and (pool & (pool - 1)) == 0 and rate > 0
+    assert fsp.autotune_pool(inst, 0.8) == (pool, rate)
+
+
+def test_learned_kind_rejects_a_mismatched_model(fsp):
+    inst = fsp.Instance(I.instance(9, 5, 1000))
+    with pytest.raises(fsp.FspError):
+        fsp.branch_and_bound(inst, "learned", fixed_pool=10, model=fsp.Model(22, 2))
+    with pytest.raises(fsp.FspError):
+        fsp.branch_and_bound(inst, "learned", fixed_pool=10)
+
+
+def test_policy_samples(fsp, orc):
+    """Samples logged by a search: the features are the node's depth, bound,
+    prefix completion times and remaining work over the NEH makespan; the
+    first target is the gap of a feasible completion to the bound (>= 0, and
+    not below the best completion), the second says whether the bound
+    reaches the final UB."""
+    n, m = 9, 5
+    p = I.instance(n, m, 1000)
+    inst = fsp.Instance(p)
+    x, t, res = fsp.policy_samples(inst, 500, 0.5, seed=3, kind="fixed", fixed_pool=40)
+    assert res.status == 0 and 0 < x.shape[0] <= 500
+    X = x.float().cpu().numpy()
+    T = t.cpu().numpy()
+    neh_c, _ = orc.neh(p)
+    assert np.all(T[:, 0] >= 0) and set(np.unique(T[:, 1])) <= {0.0, 1.0}
+    tot = p.sum(0)
+    # reconstruct each node from its features: depth and bound are exact
+    for r in range(min(60, len(X))):
+        d = int(round(X[r, 0] * n))
+        lb = X[r, 1] * neh_c  # bf16: about 3 significant digits
+        assert 1 <= d < n
+        # remaining work is the column total minus the prefix (same scale)
+        rem = X[r, 2 + m:2 + 2 * m] * neh_c
+        front = X[r, 2:2 + m] * neh_c
+        assert np.all(rem <= tot * 1.01 + 1) and np.all(np.diff(front) >= -0.01 * neh_c)
+        if abs(lb - res.makespan) > 0.01 * neh_c:
+            assert T[r, 1] == (1.0 if lb >= res.makespan else 0.0)
