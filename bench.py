@@ -81,6 +81,149 @@ def cpu_baseline(p, pool, target_s: float = 10.0) -> dict:
                       f"{dt:.1f} s"}
 
 
+# Held-out 20x10 instances (seeds outside the 4000..4199 training range)
+# whose plain adaptive search proves the optimum within the time limit.
+BNB_SEEDS = []
+BNB_TIME_LIMIT = 20.0
+
+
+def geomean(xs):
+    xs = [max(float(x), 1e-9) for x in xs]
+    return float(np.exp(np.mean(np.log(xs)))) if xs else None
+
+
+def bnb_leg(seeds, time_limit) -> dict:
+    """Time to a proven optimum, plain adaptive (the paper's Algorithm 1,
+    launch by launch) vs batched (graph-replayed iterations, autotuned pool)
+    vs batched + learned ordering, on held-out instances."""
+    from paper_1206_4973_amd import fsp, inputs
+    from paper_1206_4973_amd import train_policy
+    model_path = os.path.join(ROOT, "paper_1206_4973_amd", "policy_20x10.npz")
+    model = train_policy.load(model_path) if os.path.exists(model_path) else None
+    kinds = ["adaptive", "autotuned"] + (["learned"] if model is not None else [])
+    rows = []
+    for s in seeds:
+        inst = fsp.Instance(inputs.instance(20, 10, s))
+        fsp.autotune_pool(inst)  # per-shape tuning, cached; not part of a run
+        row = {"seed": s}
+        for kind in kinds:
+            kw = {"model": model} if kind == "learned" else {}
+            r = fsp.branch_and_bound(inst, kind, time_limit=time_limit, **kw)
+            row[kind] = {"makespan": r.makespan, "proven": r.status == 0,
+                         "t_proof_s": r.t_total_s, "t_found_s": r.t_found_s,
+                         "nodes": r.nodes_bounded, "pool": r.final_pool}
+        inst.close()
+        rows.append(row)
+    out = {"instances": "20x10, seeds " + ",".join(str(s) for s in seeds),
+           "time_limit_s": time_limit, "kinds": kinds}
+    all_proven = all(r[k]["proven"] for r in rows for k in kinds)
+    same_opt = all(len({r[k]["makespan"] for k in kinds}) == 1 for r in rows)
+    out["all_proven"] = all_proven
+    out["same_optimum"] = same_opt
+    for k in kinds:
+        out[k] = {"geomean_t_proof_s": geomean([r[k]["t_proof_s"] for r in rows]),
+                  "geomean_nodes": geomean([r[k]["nodes"] for r in rows])}
+    for k in kinds[1:]:
+        out[f"speedup_{k}_vs_adaptive"] = geomean(
+            [r["adaptive"]["t_proof_s"] / r[k]["t_proof_s"] for r in rows])
+        out[f"node_ratio_{k}_vs_adaptive"] = geomean(
+            [r[k]["nodes"] / r["adaptive"]["nodes"] for r in rows])
+    out["per_instance"] = rows
+    return out
+
+
+def timed(fn, steps, warmup, stream):
+    """Average seconds per call of fn over `steps` calls (HIP events on the
+    launch stream), after `warmup` calls."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def batch_workload(steps, warmup) -> dict:
+    """64 instances (n in {20,50,100} x m in {5,10,20}, times uniform [1,99],
+    seeds 3000+i), each with a pool of 2^e nodes, e uniform in 10..18 (depth
+    uniform 1..n-1): one persistent graph-replayed launch vs 64 launches."""
+    import torch
+    from paper_1206_4973_amd import fsp, inputs
+    shapes = [(n, m) for n in (20, 50, 100) for m in (5, 10, 20)]
+    rng = np.random.default_rng(3000)
+    exps = [int(e) for e in rng.integers(10, 19, size=64)]
+    items, ops, nodes = [], 0, 0
+    for i in range(64):
+        n, m = shapes[i % 9]
+        pool = inputs.random_pool(n, 1 << exps[i], 1, n - 1, 3000 + 500000 + i)
+        items.append((fsp.Instance(inputs.instance(n, m, 3000 + i)),
+                      torch.from_numpy(pool).cuda(), None))
+        ops += algorithmic_ops(pool[:, 0], n, m)
+        nodes += len(pool)
+    stream = torch.cuda.current_stream()
+    b = fsp.Batch(items)
+    t_batch = timed(lambda: b.replay(stream), steps, warmup, stream)
+    outs = [torch.empty(x[1].shape[0], dtype=torch.int32, device="cuda") for x in items]
+
+    def separate():
+        for (inst, nd, _), o in zip(items, outs):
+            inst.bound_pool(nd, o, stream=stream)
+    t_sep = timed(separate, steps, warmup, stream)
+    same = all(torch.equal(a, c) for a, c in zip(b.outs, outs))
+    achieved = ops / t_batch / 1e12
+    return {"workload": "batch: 64 instances, n in {20,50,100} x m in {5,10,20}, "
+                        "pools 2^10..2^18 (seed 3000)",
+            "nodes": nodes, "steps": steps, "warmup": warmup, "batch_info": b.info(),
+            "one_launch": {"ms": t_batch * 1e3, "nodes_per_s": nodes / t_batch,
+                           "achieved_TOPs": achieved, "frac": achieved / INT32_PEAK_TOPS},
+            "separate_launches": {"ms": t_sep * 1e3, "nodes_per_s": nodes / t_sep,
+                                  "frac": ops / t_sep / 1e12 / INT32_PEAK_TOPS},
+            "identical_bounds": bool(same), "peak_TOPs": INT32_PEAK_TOPS}
+
+
+def large_workload(steps, warmup, bnb_time) -> dict:
+    """50x20 (seed 5000) and 200x20 (seed 5001): pools of 2^22 nodes (depth
+    uniform 1..n-1), then time-limited searches (plain adaptive, batched,
+    batched + learned when a 20-machine policy is present) reporting the best
+    UB, the smallest pending bound, the gap and nodes per second."""
+    import torch
+    from paper_1206_4973_amd import fsp, inputs, train_policy
+    out = {"workload": "large: 50x20 and 200x20", "bnb_time_limit_s": bnb_time}
+    model_path = os.path.join(ROOT, "paper_1206_4973_amd", "policy_m20.npz")
+    model = train_policy.load(model_path) if os.path.exists(model_path) else None
+    stream = torch.cuda.current_stream()
+    for n, m, seed in ((50, 20, 5000), (200, 20, 5001)):
+        p = inputs.instance(n, m, seed)
+        inst = fsp.Instance(p)
+        pool = inputs.random_pool(n, 1 << 22, 1, n - 1, seed + 500000)
+        nodes = torch.from_numpy(pool).cuda()
+        lb = torch.empty(len(pool), dtype=torch.int32, device="cuda")
+        t = timed(lambda: inst.bound_pool(nodes, lb, stream=stream), steps, warmup, stream)
+        ops = algorithmic_ops(pool[:, 0], n, m)
+        rec = {"pool_bounding": {"nodes": len(pool), "ms": t * 1e3,
+                                 "nodes_per_s": len(pool) / t,
+                                 "frac": ops / t / 1e12 / INT32_PEAK_TOPS}}
+        del nodes, lb
+        kinds = ["adaptive", "autotuned"] + (["learned"] if model is not None else [])
+        for kind in kinds:
+            kw = {"model": model} if kind == "learned" else {}
+            r = fsp.branch_and_bound(inst, kind, time_limit=bnb_time, **kw)
+            rec[kind] = {"best_ub": r.makespan, "open_lb": r.open_lb,
+                         "gap": (r.makespan - r.open_lb) / r.makespan,
+                         "proven": r.status == 0, "nodes": r.nodes_bounded,
+                         "nodes_per_s": r.nodes_bounded / max(r.t_search_s, 1e-9),
+                         "t_found_s": r.t_found_s, "pool": r.final_pool}
+        out[f"{n}x{m}"] = rec
+        inst.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +231,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2-pool", type=int, default=22)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-bnb", action="store_true", help="skip the B&B time-to-optimum leg")
+    ap.add_argument("--workload", default="pool", choices=["pool", "batch", "large"],
+                    help="pool: the 20x20 line (default); batch: 64 mixed instances in one "
+                         "launch; large: 50x20 and 200x20 pools and time-limited searches")
+    ap.add_argument("--bnb-time", type=float, default=60.0,
+                    help="time limit of each search of the large workload (s)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -109,6 +258,12 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": 1 << 28, "launches": 5}))
+        return 0
+    if args.workload == "batch":
+        print(json.dumps(batch_workload(args.steps, args.warmup)), flush=True)
+        return 0
+    if args.workload == "large":
+        print(json.dumps(large_workload(args.steps, args.warmup, args.bnb_time)), flush=True)
         return 0
     n, m, seed = 20, 20, 2000
     count = 1 << args.log2_pool
@@ -171,6 +326,8 @@ def main() -> int:
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(p, pool)
+    if not args.no_bnb and BNB_SEEDS:
+        res["bnb_time_to_optimum"] = bnb_leg(BNB_SEEDS, BNB_TIME_LIMIT)
     print(json.dumps(res), flush=True)
     return 0
 

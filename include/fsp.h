@@ -209,6 +209,11 @@ typedef struct {
   double t_total_s;   /* wall time of the whole call                        */
   int64_t final_pool; /* pool size in force at the end                      */
   double t_search_s;  /* wall time of the search loop (set-up excluded)     */
+  int32_t open_lb;    /* a lower bound on the optimum: the smallest bound of
+                         the nodes still pending after a time limit (status
+                         1), else the makespan; gap = (makespan - open_lb) /
+                         makespan                                           */
+  int32_t reserved;
 } fsp_result;
 
 /*

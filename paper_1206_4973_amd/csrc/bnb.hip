@@ -237,6 +237,22 @@ __global__ __launch_bounds__(kThreads) void prune_kernel(
   }
 }
 
+// smallest bound among the pending nodes (for the optimality gap after a
+// time limit): an atomic min over every bucket entry
+__global__ void open_lb_kernel(const int32_t *__restrict__ blb,
+                               const int32_t *__restrict__ bcount, int n, int64_t cap,
+                               int32_t *__restrict__ out) {
+  for (int d = 0; d < n; ++d) {
+    const int c = bcount[d];
+    int best = 0x7fffffff;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c;
+         i += (int64_t)gridDim.x * blockDim.x)
+      best = min(best, blb[(int64_t)d * cap + i]);
+    for (int off = 32; off > 0; off >>= 1) best = min(best, __shfl_down(best, off));
+    if ((threadIdx.x & 63) == 0 && best != 0x7fffffff) atomicMin(out, best);
+  }
+}
+
 // seed: place the root in bucket 0 if it can beat UB; count its bound
 __global__ void seed_kernel(BnbDesc *D, const int32_t *root_lb,
                             uint8_t *bnodes, int32_t *blb, int32_t *bcount,
@@ -685,6 +701,22 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
   }
   const double t_loop = elapsed() - t_loop0;
   if (rc == FSP_OK) rc = S.commit();
+  int32_t open_lb = -1;
+  if (rc == FSP_OK && status == 1) {
+    // smallest bound among the pending nodes (pool_lb[0] as the scratch cell)
+    const int32_t big = 0x7fffffff;
+    if (hipMemcpyAsync(S.pool_lb, &big, sizeof(int32_t), hipMemcpyHostToDevice, S.stream) !=
+        hipSuccess)
+      rc = FSP_EDEVICE;
+    if (rc == FSP_OK) {
+      hipLaunchKernelGGL(open_lb_kernel, dim3(S.grid), dim3(256), 0, S.stream, S.blb, S.bcount,
+                         n, S.cap, S.pool_lb);
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(&open_lb, S.pool_lb, sizeof(int32_t), hipMemcpyDeviceToHost,
+                         S.stream) != hipSuccess)
+        rc = FSP_EDEVICE;
+    }
+  }
   if (rc == FSP_OK) rc = S.read_desc();
   if (log) std::fclose(log);
   if (rc == FSP_OK && samples) {
@@ -725,6 +757,11 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
   out->t_total_s = elapsed();
   out->final_pool = target;
   out->t_search_s = t_loop;
+  // lower bound on the optimum: the smallest pending bound, or the UB when
+  // nothing is pending (the tree is exhausted)
+  out->open_lb = status == 1 && open_lb != 0x7fffffff && open_lb >= 0
+                     ? std::min<int32_t>(open_lb, h.ub)
+                     : h.ub;
   S.release();
   return FSP_OK;
 }
