@@ -48,7 +48,8 @@ __global__ void reset_counter(unsigned long long *c) {
 
 template <int M, bool WIDE, bool CHUNKED>
 __device__ __forceinline__ void run_tile(const BatchSeg &S, char *smem,
-                                         int64_t t, bool restage) {
+                                         int64_t t, bool restage,
+                                         char *tile_slots) {
   const InstView I = S.I;
   const LdsView L = carve<WIDE>(smem, I);
   if (restage) {
@@ -56,12 +57,13 @@ __device__ __forceinline__ void run_tile(const BatchSeg &S, char *smem,
     __syncthreads();
   }
   bound_nodes<M, WIDE, CHUNKED>(I, L, S.nodes, S.stride, S.aligned != 0,
-                                (t - S.tile_begin) * kBlock, S.count, S.lb);
+                                (t - S.tile_begin) * kBlock, S.count, S.lb,
+                                tile_slots);
 }
 
 __global__ __launch_bounds__(kBlock, 4) void batch_kernel(
     const BatchSeg *__restrict__ segs, int nsegs, int64_t total_tiles,
-    unsigned long long *counter) {
+    unsigned long long *counter, char *slots, int64_t tile_bytes) {
   extern __shared__ __align__(16) char smem[];
   __shared__ long long s_tile;
   int cur = -1;
@@ -83,16 +85,17 @@ __global__ __launch_bounds__(kBlock, 4) void batch_kernel(
     const BatchSeg &S = segs[lo];
     const bool restage = lo != cur;
     cur = lo;
+    char *ts = slots + t * tile_bytes;  // this tile's job-mask slots
     switch (S.variant) {
-      case V5N: run_tile<5, false, false>(S, smem, t, restage); break;
-      case V5W: run_tile<5, true, false>(S, smem, t, restage); break;
-      case V5C: run_tile<5, true, true>(S, smem, t, restage); break;
-      case V10N: run_tile<10, false, false>(S, smem, t, restage); break;
-      case V10W: run_tile<10, true, false>(S, smem, t, restage); break;
-      case V10C: run_tile<10, true, true>(S, smem, t, restage); break;
-      case V20N: run_tile<20, false, false>(S, smem, t, restage); break;
-      case V20W: run_tile<20, true, false>(S, smem, t, restage); break;
-      case V20C: run_tile<20, true, true>(S, smem, t, restage); break;
+      case V5N: run_tile<5, false, false>(S, smem, t, restage, ts); break;
+      case V5W: run_tile<5, true, false>(S, smem, t, restage, ts); break;
+      case V5C: run_tile<5, true, true>(S, smem, t, restage, ts); break;
+      case V10N: run_tile<10, false, false>(S, smem, t, restage, ts); break;
+      case V10W: run_tile<10, true, false>(S, smem, t, restage, ts); break;
+      case V10C: run_tile<10, true, true>(S, smem, t, restage, ts); break;
+      case V20N: run_tile<20, false, false>(S, smem, t, restage, ts); break;
+      case V20W: run_tile<20, true, false>(S, smem, t, restage, ts); break;
+      case V20C: run_tile<20, true, true>(S, smem, t, restage, ts); break;
       default: break;
     }
   }
@@ -118,6 +121,8 @@ struct fsp_batch {
   int64_t total_tiles = 0;
   BatchSeg *d_segs = nullptr;
   unsigned long long *d_counter = nullptr;
+  char *d_slots = nullptr;  // job-mask scratch of the batch kernel and fallbacks
+  int64_t tile_bytes = 0;   // scratch bytes per tile of the batch kernel
   size_t lds = 0;
   int grid = 0;
   std::vector<fsp_segment> fallback;  // bounded by single-pool launches
@@ -132,12 +137,14 @@ int enqueue(fsp_batch *b, hipStream_t s) {
   if (b->nsegs > 0) {
     hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, b->d_counter);
     hipLaunchKernelGGL(batch_kernel, dim3(b->grid), dim3(kBlock), b->lds, s,
-                       b->d_segs, b->nsegs, b->total_tiles, b->d_counter);
+                       b->d_segs, b->nsegs, b->total_tiles, b->d_counter,
+                       b->d_slots, b->tile_bytes);
     FSP_HIP_TRY(hipGetLastError());
   }
   for (const fsp_segment &f : b->fallback) {
+    // queued after the batch kernel on the same stream: the scratch is free
     const int rc = launch_bound(f.inst, f.data, f.stride, f.count, f.lb_out, s,
-                                nullptr);
+                                nullptr, b->d_slots);
     if (rc != FSP_OK) return rc;
   }
   return FSP_OK;
@@ -149,6 +156,7 @@ void destroy(fsp_batch *b) {
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_segs) (void)hipFree(b->d_segs);
   if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->d_slots) (void)hipFree(b->d_slots);
   delete b;
 }
 
@@ -206,6 +214,11 @@ int fsp_batch_create(const fsp_segment *segs, int32_t nsegs,
   std::vector<BatchSeg> table;
   int64_t tiles = 0;
   size_t lds = 16;
+  int slot_max = 0;
+  for (const Item &it : items) slot_max = std::max(slot_max, it.s.I.slot_bytes);
+  size_t scratch = 0;
+  for (const fsp_segment &f : b->fallback)
+    scratch = std::max(scratch, bound_scratch_bytes(f.inst->n, f.count));
   for (Item &it : items) {
     it.s.tile_begin = tiles;
     tiles += (it.s.count + kBlock - 1) / kBlock;
@@ -216,6 +229,12 @@ int fsp_batch_create(const fsp_segment *segs, int32_t nsegs,
   b->nsegs = (int)table.size();
   b->total_tiles = tiles;
   b->lds = lds;
+  b->tile_bytes = (int64_t)(kBlock / 64) * slot_max;
+  scratch = std::max(scratch, (size_t)(tiles * b->tile_bytes));
+  if (scratch > 0 && hipMalloc(&b->d_slots, scratch) != hipSuccess) {
+    destroy(b);
+    return FSP_ENOMEM;
+  }
   if (b->nsegs > 0) {
     if (hipMalloc(&b->d_segs, table.size() * sizeof(BatchSeg)) != hipSuccess ||
         hipMalloc(&b->d_counter, sizeof(unsigned long long)) != hipSuccess) {

@@ -330,6 +330,8 @@ int BnbState::init(const fsp_instance *inst_, int64_t max_pool, int rule_) {
       hipMalloc(&bcount, (size_t)n * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&pool, (size_t)cap * stride) != hipSuccess ||
       hipMalloc(&pool_lb, (size_t)cap * sizeof(int32_t)) != hipSuccess ||
+      (bound_scratch_bytes(n, cap) > 0 &&
+       hipMalloc(&slots, bound_scratch_bytes(n, cap)) != hipSuccess) ||
       hipMalloc(&desc, sizeof(BnbDesc)) != hipSuccess ||
       hipMalloc(&best_perm, 256) != hipSuccess ||
       hipMalloc(&target_dev, sizeof(int64_t)) != hipSuccess ||
@@ -383,7 +385,7 @@ void BnbState::release() {
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
-  for (void *p : {(void *)bnodes, (void *)blb, (void *)bcount, (void *)pool, (void *)pool_lb,
+  for (void *p : {(void *)bnodes, (void *)blb, (void *)bcount, (void *)pool, (void *)pool_lb, slots,
                   (void *)desc, (void *)best_perm, (void *)target_dev, (void *)bscore,
                   (void *)tnodes, (void *)tlb, (void *)tscore, (void *)hist, X, (void *)Y,
                   (void *)log_nodes, (void *)log_lb})
@@ -405,7 +407,7 @@ int BnbState::start(int32_t ub0, const std::vector<uint8_t> &perm0) {
   FSP_HIP_TRY(hipMemcpyAsync(best_perm, bp.data(), 256, hipMemcpyHostToDevice, stream));
   // bound the root: an all-zero record in the pool buffer
   FSP_HIP_TRY(hipMemsetAsync(pool, 0, stride, stream));
-  int rc = launch_bound(inst, pool, stride, 1, pool_lb, stream, nullptr);
+  int rc = launch_bound(inst, pool, stride, 1, pool_lb, stream, nullptr, slots);
   if (rc != FSP_OK) return rc;
   hipLaunchKernelGGL(seed_kernel, dim3(1), dim3(64), 0, stream, desc, pool_lb,
                      bnodes, blb, bcount, stride, rule);
@@ -430,7 +432,7 @@ int BnbState::enqueue_iteration(hipStream_t s) {
   hipLaunchKernelGGL(branch_kernel, dim3(grid), dim3(kThreads), 0, s, desc,
                      bnodes, blb, pool, n, stride, cap, rule);
   FSP_HIP_TRY(hipGetLastError());
-  rc = launch_bound(inst, pool, stride, cap, pool_lb, s, &desc->children);
+  rc = launch_bound(inst, pool, stride, cap, pool_lb, s, &desc->children, slots);
   if (rc != FSP_OK) return rc;
   hipLaunchKernelGGL(prune_kernel, dim3(grid), dim3(kThreads), 0, s, desc,
                      pool, pool_lb, bnodes, blb, bcount, n, stride, cap, rule, log_cap,

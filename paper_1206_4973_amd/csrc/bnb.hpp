@@ -37,6 +37,7 @@ struct BnbState {
   int32_t *bcount = nullptr;   // [n]
   uint8_t *pool = nullptr;     // [cap][stride]
   int32_t *pool_lb = nullptr;  // [cap]
+  void *slots = nullptr;       // job-mask scratch of the bounding launches
   BnbDesc *desc = nullptr;
   uint8_t *best_perm = nullptr;  // [256]
   int64_t *target_dev = nullptr;

@@ -18,20 +18,38 @@
 // their difference z = tl - tk >= 0:
 //     z' = max(z - a, lag) + b = max(z + (b - a), lag + b),
 // and recovers tl at the end as r[k] + S[k] + z (tk ends at r[k] + S[k]
-// whatever the order).  The same algebra makes an absent job a no-op: with
-// (b - a) and (lag + b) both replaced by 0, z' = max(z, 0) = z.  So every
-// lane walks the same table position in lock-step, the table entry is a
-// wave-uniform LDS broadcast, and the per-lane work is
-//     alpha = bit job of U            (v_bfe_u32)
-//     z     = max(z + alpha*x, alpha*y)   (v_mad_i32_i24, v_mul_u32_u24, v_max_i32)
+// whatever the order).  Every lane walks the same table position in
+// lock-step; the record {x = 256 (b - a), y = 256 (lag + b) + job} is a
+// wave-uniform LDS broadcast, and a lane whose node has the position's job
+// already scheduled must keep its z.  Two forms of that choice:
+//   n <= 32: the node's unscheduled set U is one register, and
+//       alpha = bit job of U;  z = max(z + alpha*x, alpha*y)
+//     (v_bfe_u32, v_mad_i32_i24, v_mul_u32_u24, v_max_i32); alpha = 0 gives
+//     max(z, 0) = z.
+//   n > 32: the set spans several words, so each wave first writes, once per
+//     tile, the 64-bit mask of lanes that still have job j, for every j, into
+//     a scratch slot (one ballot per job), and the walk reads the position's
+//     mask with a scalar load (the job's slot offset comes from a second,
+//     scalar-read table):
+//       t = max(z + x, y);  z = mask[job] ? t : z
+//     (v_add_u32, v_max_i32, v_cndmask_b32 on the SGPR pair).  This replaces
+//     an LDS read and a bit extract per position; for n <= 32 the register
+//     form is faster, as the scalar loads then cost more than the bit extract
+//     they save.
 // z is kept scaled by 256 with the job id riding in the low byte of y (so no
 // extra instruction is needed to split the record): for integers the high
 // part of max(256u + e, 256v + j) with 0 <= e, j < 256 is max(u, v), so
 // z = Z >> 8 exactly.
 //
-// Data layout in LDS (per workgroup): the pair table (whole, or chunk by
-// chunk when it does not fit), the padded p matrix for the prefix recurrence
-// and, for n > 32, one membership byte per (job, lane).
+// Data layout: in LDS (per workgroup) the pair records (whole table, or chunk
+// by chunk when it does not fit), the padded p matrix for the prefix
+// recurrence and, for n > 32, the unscheduled-job words of every lane; in
+// global memory the mask offset of every table position (read by scalar
+// loads) and, for n > 32, the scratch of job-mask slots, one per wave of every
+// tile, each written once per launch.
+#include <algorithm>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "bound_tile.hpp"
@@ -49,6 +67,7 @@ struct BoundParams {
   int stride;
   int aligned;  // records 16-byte aligned: load them as uint4
   int32_t *lb;
+  char *slots;  // bound_scratch_bytes(n, count) bytes of job-mask slots (n > 32)
 };
 
 template <int M, bool WIDE, bool CHUNKED>
@@ -59,12 +78,15 @@ __global__ __launch_bounds__(kBlock, 4) void bound_kernel(const BoundParams a) {
   __syncthreads();
   int64_t count = a.count, ntiles = a.ntiles;
   if (a.count_dev) {
-    count = *a.count_dev;
+    // never more than the capacity that sized the grid and the scratch
+    count = min((int64_t)*a.count_dev, a.count);
     ntiles = (count + kBlock - 1) / kBlock;
   }
+  const size_t tile_bytes = (size_t)(kBlock / 64) * (size_t)a.I.slot_bytes;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
     bound_nodes<M, WIDE, CHUNKED>(a.I, L, a.nodes, a.stride, a.aligned != 0,
-                                  tile * kBlock, count, a.lb);
+                                  tile * kBlock, count, a.lb,
+                                  a.slots + (size_t)tile * tile_bytes);
 }
 
 using BoundFn = void (*)(BoundParams);
@@ -102,7 +124,7 @@ BoundFn kernel_for(int m, bool wide, bool chunked) {
 
 // LDS budget of one workgroup for the pair table: the whole table for
 // n <= 32 (at most 48.6 KB); 32 KB chunks above, so that four workgroups fit
-// on a compute unit.
+// on a compute unit next to the job words.
 constexpr size_t kTableBudgetNarrow = 64 * 1024;
 constexpr size_t kTableBudgetWide = 32 * 1024;
 
@@ -117,12 +139,13 @@ InstView inst_view(const fsp_instance *inst, size_t table_budget) {
   v.Qp = inst->d_Qp;
   v.tot = inst->d_tot;
   v.rec = inst->d_rec;
+  v.joff = inst->d_joff;
+  v.slot_bytes = inst->wide ? mask_slot_bytes(inst->n) : 0;
   v.n = inst->n;
   v.mp = inst->mp;
   v.npad = inst->npad;
   v.P = inst->P;
-  const size_t rsz = inst->wide ? sizeof(WideRec) : sizeof(NarrowRec);
-  const size_t per_pair = (size_t)inst->npad * rsz;
+  const size_t per_pair = (size_t)inst->npad * sizeof(Rec);
   int ppc = (int)(table_budget / per_pair);
   if (ppc < 1) ppc = 1;
   if (ppc > inst->P) ppc = inst->P;
@@ -131,12 +154,62 @@ InstView inst_view(const fsp_instance *inst, size_t table_budget) {
   return v;
 }
 
+int stream_scratch(hipStream_t stream, size_t bytes, void **out) {
+  // one workspace per (device, stream); the per-thread default stream is a
+  // different stream in every host thread, so it is also keyed by thread
+  struct Ws {
+    int dev;
+    hipStream_t stream;
+    std::thread::id thread;
+    void *ptr;
+    size_t bytes;
+  };
+  static std::mutex mu;
+  static std::vector<Ws> spaces;
+  int dev = 0;
+  FSP_HIP_TRY(hipGetDevice(&dev));
+  const std::thread::id tid = stream == hipStreamPerThread
+                                  ? std::this_thread::get_id()
+                                  : std::thread::id();
+  std::lock_guard<std::mutex> lock(mu);
+  Ws *w = nullptr;
+  for (Ws &s : spaces)
+    if (s.dev == dev && s.stream == stream && s.thread == tid) w = &s;
+  if (!w) {
+    spaces.push_back({dev, stream, tid, nullptr, 0});
+    w = &spaces.back();
+  }
+  if (w->bytes < bytes) {
+    // the old workspace may still be in use by work queued on the stream
+    if (w->ptr) {
+      FSP_HIP_TRY(hipStreamSynchronize(stream));
+      (void)hipFree(w->ptr);
+      w->ptr = nullptr;
+      w->bytes = 0;
+    }
+    const size_t grow = std::max(bytes, (size_t)1 << 20);
+    if (hipMalloc(&w->ptr, grow) != hipSuccess) {
+      w->ptr = nullptr;
+      return FSP_ENOMEM;
+    }
+    w->bytes = grow;
+  }
+  *out = w->ptr;
+  return FSP_OK;
+}
+
 int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
                  int64_t count, int32_t *lb_out, hipStream_t stream,
-                 const int32_t *count_dev) {
+                 const int32_t *count_dev, void *scratch) {
   if (count == 0) return FSP_OK;
   const bool wide = inst->wide != 0;
+  const size_t need = bound_scratch_bytes(inst->n, count);
+  if (!scratch && need > 0) {
+    const int rc = stream_scratch(stream, need, &scratch);
+    if (rc != FSP_OK) return rc;
+  }
   BoundParams a{};
+  a.slots = static_cast<char *>(scratch);
   a.nodes = nodes;
   a.count = count;
   a.ntiles = (count + kBlock - 1) / kBlock;
@@ -198,5 +271,5 @@ extern "C" int fsp_bound_pool(const fsp_nodes *nodes, int64_t count,
   if (nodes->stride < nodes->inst->n + 1) return FSP_EINVAL;
   return fspi::launch_bound(nodes->inst, nodes->data, nodes->stride, count,
                             lb_out, reinterpret_cast<hipStream_t>(stream),
-                            nullptr);
+                            nullptr, nullptr);
 }

@@ -14,10 +14,12 @@ struct InstView {
   const uint32_t *__restrict__ Hp;  // [n][mp/2] head sums, packed 16-bit pairs
   const uint32_t *__restrict__ Qp;  // [n][mp/2] tail sums, packed 16-bit pairs
   const int32_t *__restrict__ tot;  // [mp]
-  const void *__restrict__ rec;     // [P][npad]
+  const Rec *__restrict__ rec;       // [P][npad] {x, y} per table position
+  const uint32_t *__restrict__ joff; // [P][npad] 8 * job id per position
   int n, mp, npad, P;
-  int ppc;      // pairs per LDS chunk
-  int nchunks;  // chunks of the pair table
+  int ppc;         // pairs per LDS chunk
+  int nchunks;     // chunks of the pair table
+  int slot_bytes;  // bytes of one wave's mask slot (mask_slot_bytes(n))
 };
 
 // LDS of one workgroup for one instance: the table chunk, then (n <= 32)
@@ -31,6 +33,14 @@ struct LdsView {
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
+// Read-only views through the constant address space: loads from these with
+// a wave-uniform address are scalar loads whose result lands in SGPRs.
+typedef const __attribute__((address_space(4))) char kchar;
+typedef const __attribute__((address_space(4))) uint32_t ku32;
+typedef const __attribute__((address_space(4))) uint64_t ku64;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) u32x4 ku128;
+
 template <int M>
 __host__ __device__ constexpr int pair_index(int k, int l) {
   return k * (2 * M - k - 1) / 2 + (l - k - 1);
@@ -38,8 +48,7 @@ __host__ __device__ constexpr int pair_index(int k, int l) {
 
 __host__ __device__ inline size_t lds_bytes(int n, int mp, int npad, int ppc,
                                             bool wide) {
-  const size_t rsz = wide ? sizeof(WideRec) : sizeof(NarrowRec);
-  size_t b = (size_t)ppc * npad * rsz;
+  size_t b = (size_t)ppc * npad * sizeof(Rec);
   if (wide)
     b += (size_t)((n + 31) / 32) * kBlock * 4;
   else
@@ -49,7 +58,6 @@ __host__ __device__ inline size_t lds_bytes(int n, int mp, int npad, int ppc,
 
 template <bool WIDE>
 __device__ __forceinline__ LdsView carve(char *smem, const InstView I) {
-  using Rec = typename std::conditional<WIDE, WideRec, NarrowRec>::type;
   LdsView L;
   L.s_rec = smem;
   char *after = smem + (size_t)I.ppc * I.npad * sizeof(Rec);
@@ -58,14 +66,12 @@ __device__ __forceinline__ LdsView carve(char *smem, const InstView I) {
   return L;
 }
 
-template <bool WIDE>
 __device__ __forceinline__ void stage_chunk(const InstView I, char *s_rec,
                                             int chunk) {
-  using Rec = typename std::conditional<WIDE, WideRec, NarrowRec>::type;
   const int lo = chunk * I.ppc;
   const int hi = min(I.P, lo + I.ppc);
   const int total = (hi - lo) * I.npad;
-  const Rec *src = reinterpret_cast<const Rec *>(I.rec) + (size_t)lo * I.npad;
+  const Rec *src = I.rec + (size_t)lo * I.npad;
   Rec *dst = reinterpret_cast<Rec *>(s_rec);
   for (int i = threadIdx.x; i < total; i += kBlock) dst[i] = src[i];
 }
@@ -77,108 +83,166 @@ __device__ __forceinline__ void stage_instance(const InstView I,
                                                const LdsView &L) {
   if (!WIDE)
     for (int i = threadIdx.x; i < I.n * I.mp; i += kBlock) L.s_p[i] = I.p[i];
-  if (I.nchunks == 1) stage_chunk<WIDE>(I, L.s_rec, 0);
+  if (I.nchunks == 1) stage_chunk(I, L.s_rec, 0);
 }
 
-// One step of the two-machine walk (see the header comment):
+// Write the wave's job masks: entry j of the slot is the 64-bit set of lanes
+// whose node still has job j unscheduled; entries n .. end of slot are zero
+// (the padding positions of the table point at entry n).  One ballot per job
+// transposes the lanes' job sets; lane t then stores the mask of job 64c + t.
+// Every lane of the wave calls it.
+template <bool WIDE>
+__device__ __forceinline__ void write_masks(uint64_t *slot, int n,
+                                            int slot_bytes, uint32_t U,
+                                            const uint32_t *words_lane) {
+  const int lane = (int)__lane_id();
+  const int entries = slot_bytes / 8;
+  for (int c = 0; c * 64 < entries; ++c) {
+    uint64_t mine = 0;
+    const int jend = min(n, c * 64 + 64);
+    for (int j = c * 64; j < jend; ++j) {
+      uint32_t bit;
+      if constexpr (WIDE)
+        bit = (words_lane[(j >> 5) * kBlock] >> (j & 31)) & 1u;
+      else
+        bit = (U >> j) & 1u;
+      const uint64_t mk = __ballot(bit);
+      if (lane == j - c * 64) mine = mk;
+    }
+    if (c * 64 + lane < entries) slot[c * 64 + lane] = mine;
+  }
+}
+
+// ---- n <= 32: the node's unscheduled jobs are one 32-bit register ----
+// One position: alpha = bit `job` of U (job = low 5 bits of y), then
 //   z = max(z + alpha*x, alpha*y)
-__device__ __forceinline__ int step(uint32_t al, int x, int y, int Z) {
+// which leaves z unchanged for alpha = 0 because z >= 0.
+__device__ __forceinline__ int step_u(uint32_t U, int x, int y, int Z) {
+  const uint32_t al = __builtin_amdgcn_ubfe(U, (uint32_t)y, 1u);
   const int up = __mul24((int)al, x) + Z;
   const int lo = (int)__umul24(al, (uint32_t)y);
   return max(up, lo);
 }
 
-// Membership bit of the record's job in this lane's unscheduled set.  The
-// low 5 bits of y are the job's bit within its 32-job word; wide records
-// carry the byte offset of the word (in the [word][lane] LDS layout).
-template <bool WIDE>
-__device__ __forceinline__ uint32_t member(uint32_t U, const char *words_lane,
-                                           int y, int woff) {
-  if constexpr (WIDE) {
-    const uint32_t w = *reinterpret_cast<const uint32_t *>(words_lane + woff);
-    return __builtin_amdgcn_ubfe(w, (uint32_t)y, 1u);
-  } else {
-    return __builtin_amdgcn_ubfe(U, (uint32_t)y, 1u);  // job = y & 31
+__device__ __forceinline__ int walk1_u(const char *rp_raw, int npad, uint32_t U,
+                                       int Z) {
+  const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);  // 2 records
+  for (int i = 0; i < npad / 4; ++i) {
+    const int4 r0 = rp[2 * i], r1 = rp[2 * i + 1];
+    Z = step_u(U, r0.x, r0.y, Z);
+    Z = step_u(U, r0.z, r0.w, Z);
+    Z = step_u(U, r1.x, r1.y, Z);
+    Z = step_u(U, r1.z, r1.w, Z);
+  }
+  return Z;
+}
+
+__device__ __forceinline__ void walk2_u(const char *ra_raw, const char *rb_raw,
+                                        int npad, uint32_t U, int &ZA,
+                                        int &ZB) {
+  const int4 *ra = reinterpret_cast<const int4 *>(ra_raw);
+  const int4 *rb = reinterpret_cast<const int4 *>(rb_raw);
+  for (int i = 0; i < npad / 4; ++i) {
+    const int4 a0 = ra[2 * i], a1 = ra[2 * i + 1];
+    const int4 b0 = rb[2 * i], b1 = rb[2 * i + 1];
+    ZA = step_u(U, a0.x, a0.y, ZA);
+    ZB = step_u(U, b0.x, b0.y, ZB);
+    ZA = step_u(U, a0.z, a0.w, ZA);
+    ZB = step_u(U, b0.z, b0.w, ZB);
+    ZA = step_u(U, a1.x, a1.y, ZA);
+    ZB = step_u(U, b1.x, b1.y, ZB);
+    ZA = step_u(U, a1.z, a1.w, ZA);
+    ZB = step_u(U, b1.z, b1.w, ZB);
   }
 }
 
-// Walk of one pair over its Johnson order (npad records in LDS at rp).
-template <bool WIDE>
-__device__ __forceinline__ int walk1(const char *rp_raw, int npad, uint32_t U,
-                                     const char *alpha_lane, int Z) {
-  if constexpr (!WIDE) {
-    const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);  // 2 records
-    for (int i = 0; i < npad / 2; i += 2) {
-      const int4 r0 = rp[i], r1 = rp[i + 1];
-      Z = step(member<false>(U, nullptr, r0.y, 0), r0.x, r0.y, Z);
-      Z = step(member<false>(U, nullptr, r0.w, 0), r0.z, r0.w, Z);
-      Z = step(member<false>(U, nullptr, r1.y, 0), r1.x, r1.y, Z);
-      Z = step(member<false>(U, nullptr, r1.w, 0), r1.z, r1.w, Z);
-    }
-  } else {
-    const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);
-    for (int i = 0; i < npad; i += 2) {
-      const int4 r0 = rp[i], r1 = rp[i + 1];
-      Z = step(member<true>(0, alpha_lane, r0.y, r0.z), r0.x, r0.y, Z);
-      Z = step(member<true>(0, alpha_lane, r1.y, r1.z), r1.x, r1.y, Z);
-    }
+// ---- n > 32: the wave's job masks, read back as SGPR pairs ----
+// One position of the two-machine walk (see the header comment of bound.hip):
+// z = max(z + x, y) in the lanes whose node has the position's job
+// unscheduled, z unchanged in the others.  off is the byte offset of the
+// job's mask in the wave's slot; the mask comes from a scalar load, so the
+// lane select is one v_cndmask on an SGPR pair.
+__device__ __forceinline__ int step(kchar *ms, uint32_t off, int x, int y,
+                                    int Z) {
+  const uint64_t mk = *reinterpret_cast<ku64 *>(ms + off);
+  const int up = max(Z + x, y);
+  return __builtin_amdgcn_inverse_ballot_w64(mk) ? up : Z;
+}
+
+// Walk of one pair over its Johnson order: npad records in LDS at rp_raw,
+// npad mask offsets at jp (npad is a multiple of 4).  The offsets of the next
+// four positions are requested before the masks of the current four, so both
+// scalar round trips overlap in one wait (the offset table is padded so that
+// the request past the last pair stays inside it).
+__device__ __forceinline__ int walk1(const char *rp_raw, kchar *jp, kchar *ms,
+                                     int npad, int Z) {
+  const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);  // 2 records
+  ku128 *jw = reinterpret_cast<ku128 *>(jp);                // 4 offsets
+  u32x4 o = jw[0];
+  asm volatile("" : "+s"(o));  // loaded before the loop, not waited for in it
+  for (int i = 0; i < npad / 4; ++i) {
+    const u32x4 nx = jw[i + 1];
+    const int4 r0 = rp[2 * i], r1 = rp[2 * i + 1];
+    Z = step(ms, o.x, r0.x, r0.y, Z);
+    Z = step(ms, o.y, r0.z, r0.w, Z);
+    Z = step(ms, o.z, r1.x, r1.y, Z);
+    Z = step(ms, o.w, r1.z, r1.w, Z);
+    // carried through an opaque copy: otherwise the two loads feeding the
+    // loop-carried value are merged back into one load at the loop top
+    o = nx;
+    asm volatile("" : "+s"(o));
   }
   return Z;
 }
 
 // Two pairs walked together: two independent dependency chains per lane.
-template <bool WIDE>
 __device__ __forceinline__ void walk2(const char *ra_raw, const char *rb_raw,
-                                      int npad, uint32_t U,
-                                      const char *alpha_lane, int &ZA,
-                                      int &ZB) {
-  if constexpr (!WIDE) {
-    const int4 *ra = reinterpret_cast<const int4 *>(ra_raw);
-    const int4 *rb = reinterpret_cast<const int4 *>(rb_raw);
-    for (int i = 0; i < npad / 2; i += 2) {
-      const int4 a0 = ra[i], a1 = ra[i + 1];
-      const int4 b0 = rb[i], b1 = rb[i + 1];
-      ZA = step(member<false>(U, nullptr, a0.y, 0), a0.x, a0.y, ZA);
-      ZB = step(member<false>(U, nullptr, b0.y, 0), b0.x, b0.y, ZB);
-      ZA = step(member<false>(U, nullptr, a0.w, 0), a0.z, a0.w, ZA);
-      ZB = step(member<false>(U, nullptr, b0.w, 0), b0.z, b0.w, ZB);
-      ZA = step(member<false>(U, nullptr, a1.y, 0), a1.x, a1.y, ZA);
-      ZB = step(member<false>(U, nullptr, b1.y, 0), b1.x, b1.y, ZB);
-      ZA = step(member<false>(U, nullptr, a1.w, 0), a1.z, a1.w, ZA);
-      ZB = step(member<false>(U, nullptr, b1.w, 0), b1.z, b1.w, ZB);
-    }
-  } else {
-    const int4 *ra = reinterpret_cast<const int4 *>(ra_raw);
-    const int4 *rb = reinterpret_cast<const int4 *>(rb_raw);
-    for (int i = 0; i < npad; i += 2) {
-      const int4 a0 = ra[i], a1 = ra[i + 1];
-      const int4 b0 = rb[i], b1 = rb[i + 1];
-      ZA = step(member<true>(0, alpha_lane, a0.y, a0.z), a0.x, a0.y, ZA);
-      ZB = step(member<true>(0, alpha_lane, b0.y, b0.z), b0.x, b0.y, ZB);
-      ZA = step(member<true>(0, alpha_lane, a1.y, a1.z), a1.x, a1.y, ZA);
-      ZB = step(member<true>(0, alpha_lane, b1.y, b1.z), b1.x, b1.y, ZB);
-    }
+                                      kchar *ja, kchar *jb, kchar *ms,
+                                      int npad, int &ZA, int &ZB) {
+  const int4 *ra = reinterpret_cast<const int4 *>(ra_raw);
+  const int4 *rb = reinterpret_cast<const int4 *>(rb_raw);
+  ku128 *wa = reinterpret_cast<ku128 *>(ja);
+  ku128 *wb = reinterpret_cast<ku128 *>(jb);
+  u32x4 oa = wa[0], ob = wb[0];
+  asm volatile("" : "+s"(oa), "+s"(ob));  // loaded before the loop
+  for (int i = 0; i < npad / 4; ++i) {
+    const u32x4 na = wa[i + 1], nb = wb[i + 1];
+    const int4 a0 = ra[2 * i], a1 = ra[2 * i + 1];
+    const int4 b0 = rb[2 * i], b1 = rb[2 * i + 1];
+    ZA = step(ms, oa.x, a0.x, a0.y, ZA);
+    ZB = step(ms, ob.x, b0.x, b0.y, ZB);
+    ZA = step(ms, oa.y, a0.z, a0.w, ZA);
+    ZB = step(ms, ob.y, b0.z, b0.w, ZB);
+    ZA = step(ms, oa.z, a1.x, a1.y, ZA);
+    ZB = step(ms, ob.z, b1.x, b1.y, ZB);
+    ZA = step(ms, oa.w, a1.z, a1.w, ZA);
+    ZB = step(ms, ob.w, b1.z, b1.w, ZB);
+    oa = na;
+    ob = nb;
+    asm volatile("" : "+s"(oa), "+s"(ob));
   }
 }
 
 // Every pair whose index lies in [lo, hi): pairs (k,l) and (k,l+1) are walked
-// together.  Returns the max over those pairs of 256*(pair bound) + junk.
-// The record pointer advances pair by pair (pair index order = table order)
-// so that no per-pair address stays live.
+// together.  s_rec holds the records of pairs lo.. (LDS), jt the mask offsets
+// of pair lo.  Returns the max over those pairs of 256*(pair bound) + junk.
+// The record and job pointers advance pair by pair (pair index order = table
+// order) so that no per-pair address stays live.
 template <int M, bool WIDE>
-__device__ __forceinline__ int pair_sweep(const char *s_rec, int lo, int hi,
-                                          int npad, uint32_t U,
-                                          const char *alpha_lane,
-                                          const int (&R256)[M],
+__device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
+                                          int hi, int npad, uint32_t U,
+                                          kchar *ms, const int (&R256)[M],
                                           const int (&T256)[M],
                                           const int (&Q256)[M], int LB256) {
-  using Rec = typename std::conditional<WIDE, WideRec, NarrowRec>::type;
   int pb = npad * (int)sizeof(Rec);
+  int jb = npad * (int)sizeof(uint32_t);
   // Opaque per call: otherwise every per-pair offset is loop-invariant in the
   // tile loop and gets hoisted, one scalar register per pair.
-  asm volatile("" : "+s"(pb));
-  uint32_t off = 0;  // byte offset of pair index `pa - lo` (wraps below lo)
-  off -= (uint32_t)(lo * pb);
+  asm volatile("" : "+s"(pb), "+s"(jb));
+  // Byte offsets of pair index `pa - lo`, negative below lo.  Every offset is
+  // formed in full before it is added to a pointer: the job table is a 64-bit
+  // address, so a pointer stepped below its base and back would not wrap.
+  int off = -lo * pb, joff = -lo * jb;
 #pragma unroll
   for (int k = 0; k < M - 1; ++k) {
 #pragma unroll
@@ -186,12 +250,14 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, int lo, int hi,
       const int pa = pair_index<M>(k, l);
       if (l + 1 < M) {
         const bool ina = pa >= lo && pa < hi, inb = pa + 1 >= lo && pa + 1 < hi;
-        // wide tables: one chain per pair (the membership bytes come from LDS
-        // and two chains would not fit the register budget)
-        if (!WIDE && ina && inb) {
+        const int offb = off + pb, joffb = joff + jb;
+        if (ina && inb) {
           int ZA = R256[l] - R256[k], ZB = R256[l + 1] - R256[k];
-          walk2<WIDE>(s_rec + off, s_rec + off + pb, npad, U, alpha_lane, ZA,
-                      ZB);
+          if constexpr (WIDE)
+            walk2(s_rec + off, s_rec + offb, jt + joff, jt + joffb, ms, npad,
+                  ZA, ZB);
+          else
+            walk2_u(s_rec + off, s_rec + offb, npad, U, ZA, ZB);
           LB256 = max(LB256, max(T256[k] + Q256[l] + ZA,
                                  T256[k] + Q256[l + 1] + ZB));
           // keep the max chain sequential (a reassociated max tree would hold
@@ -199,27 +265,32 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, int lo, int hi,
           asm volatile("" : "+v"(LB256));
         } else {
           if (ina) {
-            int Z = walk1<WIDE>(s_rec + off, npad, U, alpha_lane,
-                                R256[l] - R256[k]);
+            int Z = WIDE ? walk1(s_rec + off, jt + joff, ms, npad,
+                                 R256[l] - R256[k])
+                         : walk1_u(s_rec + off, npad, U, R256[l] - R256[k]);
             LB256 = max(LB256, T256[k] + Q256[l] + Z);
             asm volatile("" : "+v"(LB256));
           }
           if (inb) {
-            int Z = walk1<WIDE>(s_rec + off + pb, npad, U, alpha_lane,
-                                R256[l + 1] - R256[k]);
+            int Z = WIDE ? walk1(s_rec + offb, jt + joffb, ms, npad,
+                                 R256[l + 1] - R256[k])
+                         : walk1_u(s_rec + offb, npad, U, R256[l + 1] - R256[k]);
             LB256 = max(LB256, T256[k] + Q256[l + 1] + Z);
             asm volatile("" : "+v"(LB256));
           }
         }
         off += 2 * pb;
+        joff += 2 * jb;
       } else {
         if (pa >= lo && pa < hi) {
-          int Z = walk1<WIDE>(s_rec + off, npad, U, alpha_lane,
-                              R256[l] - R256[k]);
+          int Z = WIDE ? walk1(s_rec + off, jt + joff, ms, npad,
+                               R256[l] - R256[k])
+                       : walk1_u(s_rec + off, npad, U, R256[l] - R256[k]);
           LB256 = max(LB256, T256[k] + Q256[l] + Z);
           asm volatile("" : "+v"(LB256));
         }
         off += pb;
+        joff += jb;
       }
     }
   }
@@ -227,24 +298,24 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, int lo, int hi,
 }
 
 // Bound the 256 nodes [base, base + 256) of a pool (one per lane), writing
-// lb_out[idx] for idx < count.  Every lane of the workgroup must call it (the
-// chunked form synchronises the workgroup).
+// lb_out[idx] for idx < count.  For n > 32, tile_slots is this tile's part of
+// the mask scratch: kBlock / 64 slots of I.slot_bytes, never used by another
+// tile of the same launch (unused, may be null, for n <= 32).  Every lane of the workgroup must call it (the chunked form
+// synchronises the workgroup).
 template <int M, bool WIDE, bool CHUNKED>
 __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
                                             const uint8_t *nodes, int stride,
                                             bool aligned, int64_t base,
-                                            int64_t count, int32_t *lb_out) {
-  using Rec = typename std::conditional<WIDE, WideRec, NarrowRec>::type;
+                                            int64_t count, int32_t *lb_out,
+                                            char *tile_slots) {
   const int tid = threadIdx.x;
   const int n = I.n, mp = I.mp, npad = I.npad;
   char *s_rec = L.s_rec;
   const int32_t *s_p = L.s_p;
   uint32_t *words_lane = WIDE ? L.s_words + tid : nullptr;
-  const char *alpha_lane = reinterpret_cast<const char *>(words_lane);
   const uint32_t full = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
   const int64_t idx = base + tid;
   const bool live = idx < count;
-  (void)sizeof(Rec);
 
   // ---- 1. decode the prefix, front recurrence, prefix column sums ----
   int F[M], Pk[M];
@@ -355,19 +426,40 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
     }
   }
   const int last = F[M - 1];
+  const int u_left = WIDE ? n - d : __builtin_popcount(U);
 
-  // ---- 3. every machine pair ----
+  // ---- 3. (n > 32) the wave's job masks, then every machine pair.  The
+  //         slot is written with vector stores and read back with scalar
+  //         loads.  The vector L1 writes through, so once the wave's stores
+  //         have completed (vmcnt 0) they are in the L2 that the scalar cache
+  //         fills from; the slot address is fresh in this launch (the scalar
+  //         cache starts every dispatch invalidated), so no scalar cache line
+  //         can hold an older copy of it. ----
+  kchar *ms = nullptr, *jt = nullptr;
+  if constexpr (WIDE) {
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    uint64_t *slot = reinterpret_cast<uint64_t *>(
+        tile_slots + (size_t)wave * (size_t)I.slot_bytes);
+    write_masks<WIDE>(slot, n, I.slot_bytes, U, words_lane);
+    uint64_t slot_addr = reinterpret_cast<uint64_t>(slot);
+    // wait for the stores; the address passes through the same statement so
+    // that no load from the slot can be scheduled above the wait
+    asm volatile("s_waitcnt vmcnt(0)" : "+s"(slot_addr)::"memory");
+    ms = reinterpret_cast<kchar *>(slot_addr);
+    jt = reinterpret_cast<kchar *>(reinterpret_cast<uint64_t>(I.joff));
+  }
+
   int LB256 = 0;
   if constexpr (!CHUNKED) {
 #pragma unroll
     for (int k = 0; k < M; ++k)
       asm volatile("" : "+v"(R256[k]), "+v"(T256[k]), "+v"(Q256[k]));
-    LB256 = pair_sweep<M, WIDE>(s_rec, 0, M * (M - 1) / 2, npad, U,
-                                alpha_lane, R256, T256, Q256, LB256);
+    LB256 = pair_sweep<M, WIDE>(s_rec, jt, 0, M * (M - 1) / 2, npad, U, ms,
+                                R256, T256, Q256, LB256);
   } else {
     for (int chunk = 0; chunk < I.nchunks; ++chunk) {
       __syncthreads();
-      stage_chunk<WIDE>(I, s_rec, chunk);
+      stage_chunk(I, s_rec, chunk);
       __syncthreads();
       // keep the per-node values from being re-derived per pair outside
       // the chunk loop (which would cost a register per pair)
@@ -376,18 +468,12 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
         asm volatile("" : "+v"(R256[k]), "+v"(T256[k]), "+v"(Q256[k]));
       int lo = chunk * I.ppc, hi = lo + I.ppc;
       asm volatile("" : "+s"(lo), "+s"(hi));
-      LB256 = pair_sweep<M, WIDE>(s_rec, lo, hi, npad, U, alpha_lane, R256,
-                                  T256, Q256, LB256);
+      LB256 = pair_sweep<M, WIDE>(s_rec, jt + (size_t)lo * npad * 4, lo, hi,
+                                  npad, U, ms, R256, T256, Q256, LB256);
     }
   }
 
   // ---- 4. result ----
-  int u_left;
-  if constexpr (WIDE) {
-    u_left = n - d;
-  } else {
-    u_left = __builtin_popcount(U);
-  }
   int lb = u_left == 0 ? last : (LB256 >> 8);
   if (bad) lb = FSP_LB_INVALID;
   if (live) lb_out[idx] = lb;

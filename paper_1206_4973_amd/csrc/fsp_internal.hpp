@@ -25,29 +25,39 @@ constexpr int kMaxMachines = 20;  // largest instantiated machine count
 constexpr int kBlock = 256;       // threads per workgroup of the pool kernels
 constexpr int kLogBlock = 8;
 
-// Narrow records (n <= 32: one 32-bit job mask per node):
+// Table records, one per (machine pair, position in the pair's Johnson order):
 //   x = 256 * (b - a)            (signed, |.| < 2^23)
-//   y = ((lag + b) << 8) | job   (unsigned, < 2^24)
-// Wide records (n > 32) add the byte offset, in the kernels' [word][lane]
-// LDS layout of the unscheduled-job masks, of the job's 32-job word:
-//   {x, y, (job / 32) * 256 lanes * 4 bytes, 0}
-// with a = p[job][k], b = p[job][l], lag = sum_{k<h<l} p[job][h].
-using NarrowRec = int2;
-using WideRec = int4;
+//   y = ((lag + b) << 8) | job   (unsigned, < 2^24; job < 256)
+// with a = p[job][k], b = p[job][l], lag = sum_{k<h<l} p[job][h].  A second
+// table [P][npad] holds 8 * job of every position (the byte offset of the
+// job's mask in a wave's mask slot); padding positions have x = y = 0 and
+// offset 8 * n.
+using Rec = int2;
+
+// Bytes of one wave's job-mask slot in the bounding scratch (n > 32): one
+// 64-bit lane mask per job id 0..n (n = the padding id), rounded up to 256
+// bytes so that no two slots share a cache line.
+inline int mask_slot_bytes(int n) { return ((n + 1) * 8 + 255) / 256 * 256; }
 
 inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
+
+// Bytes of the mask-offset table: [P][npad] plus one group of four entries
+// that the walk may request (and not use) past the last pair.
+inline size_t joff_bytes(int P, int npad) {
+  return ((size_t)P * npad + 4) * sizeof(uint32_t);
+}
 inline int npairs(int m) { return m * (m - 1) / 2; }
 
 }  // namespace fspi
 
 struct fsp_instance {
   int n = 0, m = 0, mp = 0, P = 0, npad = 0;
-  int wide = 0;    // 1 when n > 32 (records carry the job id separately)
+  int wide = 0;    // 1 when n > 32 (job sets of more than one word)
   int device = 0;
   int32_t *d_p = nullptr, *d_H = nullptr, *d_Q = nullptr, *d_tot = nullptr;
   uint32_t *d_Hp = nullptr, *d_Qp = nullptr;  // H, Q as packed 16-bit pairs
-  void *d_rec = nullptr;    // NarrowRec or WideRec [P][npad]
-  size_t rec_bytes = 0;
+  fspi::Rec *d_rec = nullptr;  // [P][npad]
+  uint32_t *d_joff = nullptr;  // [P][npad] 8 * job id per table position
   std::vector<int32_t> p_host;  // [n][m], for host-side set-up work (NEH)
 };
 
@@ -59,11 +69,26 @@ struct fsp_instance {
   } while (0)
 
 namespace fspi {
+// Device scratch that one bounding launch of `count` nodes of an n-job
+// instance needs: for n > 32, one mask slot per wave of every tile; none for
+// n <= 32 (the job set of a node is a register there).
+inline size_t bound_scratch_bytes(int n, int64_t count) {
+  if (n <= 32) return 0;
+  const int64_t tiles = (count + kBlock - 1) / kBlock;
+  return (size_t)tiles * (kBlock / 64) * (size_t)mask_slot_bytes(n);
+}
+
 // Launches the pool-bounding kernel (bound.hip).  Validates nothing: the
 // caller has checked every argument.  With count_dev set, the kernel reads
 // the node count from device memory when it starts (at most `count`, which
-// sizes the grid).
+// sizes the grid).  scratch holds at least bound_scratch_bytes(n, count)
+// bytes and is used by no other work running at the same time; null takes
+// the workspace that the library keeps for the stream (allocated or grown on
+// first need, which synchronises the stream).
 int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
                  int64_t count, int32_t *lb_out, hipStream_t stream,
-                 const int32_t *count_dev);
+                 const int32_t *count_dev, void *scratch);
+
+// The library's per-stream bounding workspace of at least `bytes` bytes.
+int stream_scratch(hipStream_t stream, size_t bytes, void **out);
 }  // namespace fspi

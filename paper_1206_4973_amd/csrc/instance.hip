@@ -56,8 +56,8 @@ __global__ void stage_totals(const int32_t *__restrict__ p, int n, int mp,
 }
 
 __global__ __launch_bounds__(256) void stage_pairs(
-    const int32_t *__restrict__ p, int n, int m, int mp, int npad, int wide,
-    void *__restrict__ rec_out) {
+    const int32_t *__restrict__ p, int n, int m, int mp, int npad,
+    Rec *__restrict__ rec_out, uint32_t *__restrict__ joff_out) {
   __shared__ int sA[256], sB[256];
   const int pi = blockIdx.x;
   // (k,l) of pair pi in lexicographic order
@@ -97,19 +97,16 @@ __global__ __launch_bounds__(256) void stage_pairs(
     pos = rank;
   }
   if (j >= npad) return;
-  // Padding records are all-zero: x = 0 and y = 0 leave the pair state
-  // unchanged (see the step in bound.hip).
-  int x = 0, y = 0, woff = 0;
+  // Padding records are all-zero and point at job n's mask, which is empty:
+  // the walk leaves the pair state unchanged there (see bound.hip).
+  int x = 0, y = 0;
   if (j < n) {
     x = 256 * (b - a);
     y = ((lag + b) << 8) | j;
-    woff = (j >> 5) * kBlock * 4;
   }
   const size_t slot = (size_t)pi * npad + pos;
-  if (wide)
-    reinterpret_cast<WideRec *>(rec_out)[slot] = make_int4(x, y, woff, 0);
-  else
-    reinterpret_cast<NarrowRec *>(rec_out)[slot] = make_int2(x, y);
+  rec_out[slot] = make_int2(x, y);
+  joff_out[slot] = 8u * (uint32_t)(j < n ? j : n);
 }
 
 void free_device(fsp_instance *in) {
@@ -118,11 +115,13 @@ void free_device(fsp_instance *in) {
   if (in->d_Q) (void)hipFree(in->d_Q);
   if (in->d_tot) (void)hipFree(in->d_tot);
   if (in->d_rec) (void)hipFree(in->d_rec);
+  if (in->d_joff) (void)hipFree(in->d_joff);
   if (in->d_Hp) (void)hipFree(in->d_Hp);
   if (in->d_Qp) (void)hipFree(in->d_Qp);
   in->d_Hp = in->d_Qp = nullptr;
   in->d_p = in->d_H = in->d_Q = in->d_tot = nullptr;
   in->d_rec = nullptr;
+  in->d_joff = nullptr;
 }
 
 int build_tables(fsp_instance *in, const int32_t *p_host) {
@@ -132,7 +131,8 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
       hipMalloc(&in->d_H, mat) != hipSuccess ||
       hipMalloc(&in->d_Q, mat) != hipSuccess ||
       hipMalloc(&in->d_tot, mp * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&in->d_rec, in->rec_bytes) != hipSuccess ||
+      hipMalloc(&in->d_rec, (size_t)in->P * in->npad * sizeof(Rec)) != hipSuccess ||
+      hipMalloc(&in->d_joff, joff_bytes(in->P, in->npad)) != hipSuccess ||
       hipMalloc(&in->d_Hp, mat / 2) != hipSuccess ||
       hipMalloc(&in->d_Qp, mat / 2) != hipSuccess)
     return FSP_ENOMEM;
@@ -144,13 +144,17 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
   if (hipMemcpy(d_in, p_host, (size_t)n * m * sizeof(int32_t),
                 hipMemcpyHostToDevice) != hipSuccess)
     rc = FSP_EDEVICE;
+  // the offset table's tail group past the last pair is read, never used
+  if (rc == FSP_OK &&
+      hipMemset(in->d_joff, 0, joff_bytes(in->P, in->npad)) != hipSuccess)
+    rc = FSP_EDEVICE;
   if (rc == FSP_OK) {
     hipLaunchKernelGGL(stage_rows, dim3((n + 63) / 64), dim3(64), 0, s, d_in,
                        n, m, mp, in->d_p, in->d_H, in->d_Q, in->d_Hp, in->d_Qp);
     hipLaunchKernelGGL(stage_totals, dim3(1), dim3(64), 0, s, in->d_p, n, mp,
                        in->d_tot);
     hipLaunchKernelGGL(stage_pairs, dim3(in->P), dim3(256), 0, s, in->d_p, n,
-                       m, mp, in->npad, in->wide, in->d_rec);
+                       m, mp, in->npad, in->d_rec, in->d_joff);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
       rc = FSP_EDEVICE;
   }
@@ -201,8 +205,6 @@ int fsp_load_instance(const int32_t *p_host, int32_t n, int32_t m,
   in->P = npairs(m);
   in->npad = round_up(n, 4);
   in->wide = n > 32 ? 1 : 0;
-  in->rec_bytes = (size_t)in->P * in->npad *
-                  (in->wide ? sizeof(WideRec) : sizeof(NarrowRec));
   in->p_host.assign(p_host, p_host + (size_t)n * m);
   if (hipGetDevice(&in->device) != hipSuccess) {
     delete in;
