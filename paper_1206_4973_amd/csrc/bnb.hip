@@ -21,6 +21,8 @@
 //           longer beat UB is eliminated (lazy re-check, Sec. II.A); the others
 //           append their unscheduled jobs in ascending id (Sec. II.B: one son
 //           per unscheduled job); children are compacted with a wave ballot;
+//           a record's bytes past its prefix are never read, so only the
+//           16-byte chunks up to the prefix are moved;
 //   bound   the pool-bounding kernel, count read from the descriptor;
 //   prune   one lane per child: leaves propose themselves as the new best
 //           (64-bit atomic min of (makespan, index)); other children that can
@@ -47,30 +49,6 @@ constexpr int kThreads = 256;
 
 __device__ __forceinline__ bool keeps(int rule, int lb, int ub) {
   return rule == FSP_PRUNE_GT ? lb <= ub : lb < ub;
-}
-
-// Wave-level compaction: returns this lane's slot in an array whose length
-// counter is *counter (one atomic per wave).  Only lanes with pred get a slot.
-__device__ __forceinline__ int wave_slot(bool pred, int32_t *counter) {
-  const uint64_t mask = __ballot(pred);
-  const int lane = __lane_id();
-  const uint64_t below = lane == 0 ? 0ull : (mask & ((~0ull) >> (64 - lane)));
-  const int rank = __popcll(below);
-  const uint64_t act = __ballot(1);
-  const int leader = __ffsll((unsigned long long)act) - 1;
-  int base = 0;
-  if (lane == leader && mask) base = atomicAdd(counter, __popcll(mask));
-  base = __shfl(base, leader);
-  return base + rank;
-}
-
-__device__ __forceinline__ void wave_add(int64_t *counter, bool pred) {
-  const uint64_t mask = __ballot(pred);
-  const uint64_t act = __ballot(1);
-  const int leader = __ffsll((unsigned long long)act) - 1;
-  if (__lane_id() == leader && mask)
-    atomicAdd(reinterpret_cast<unsigned long long *>(counter),
-              (unsigned long long)__popcll(mask));
 }
 
 // ---- plan ------------------------------------------------------------------
@@ -118,6 +96,10 @@ __global__ void plan_kernel(BnbDesc *D, int32_t *bcount, const uint8_t *pool,
 }
 
 // ---- branch ----------------------------------------------------------------
+// The parent record is read as 16-byte chunks (records are 16-byte aligned):
+// the chunks up to the one holding byte 1 + d are decoded for the scheduled
+// set and written back, patched, as the child; later bytes of a record are
+// never read at depth d + 1.
 __global__ __launch_bounds__(kThreads) void branch_kernel(
     BnbDesc *D, const uint8_t *__restrict__ bnodes,
     const int32_t *__restrict__ blb, uint8_t *__restrict__ pool, int n,
@@ -125,53 +107,105 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
   if (!D->active) return;
   const int d = D->depth, u = n - d, K = D->parents, base = D->parent_base;
   const int ub = D->ub;
-  const int64_t total = (int64_t)K * u;
-  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+  const int total = K * u;  // K <= cap and u <= 255: fits 32 bits
+  const int gsz = gridDim.x * blockDim.x;
+  const int last_chunk = (1 + d) >> 4;  // chunk holding the new job's byte
+  int branched = 0, pruned = 0;
   // iterate so that every wave of the grid takes part in each round
-  for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < total; r0 += gsz) {
-    const int64_t slot = r0 + threadIdx.x;
+  for (int r0 = blockIdx.x * blockDim.x; r0 < total; r0 += gsz) {
+    const int slot = r0 + threadIdx.x;
     const bool in = slot < total;
     int p = 0, c = 0;
     bool live = false;
-    const uint8_t *prec = nullptr;
     if (in) {
-      p = base + (int)(slot / u);
-      c = (int)(slot % u);
-      const int64_t at = (int64_t)d * cap + p;
-      prec = bnodes + at * stride;
-      live = keeps(rule, blb[at], ub);
-    }
-    wave_add(&D->nodes_branched, in && c == 0 && live);
-    wave_add(&D->nodes_pruned, in && c == 0 && !live);
-    const int pos = wave_slot(live, &D->children);
-    if (!live) continue;
-    // c-th unscheduled job of the parent, in ascending id
-    uint32_t used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = 0; i < d; ++i) {
-      const int j = prec[1 + i];
-      used[j >> 5] |= 1u << (j & 31);
-    }
-    int job = -1, left = c;
-    for (int w = 0; w < 8 && job < 0; ++w) {
-      const int lo = w * 32;
-      if (lo >= n) break;
-      uint32_t freew = ~used[w];
-      if (n - lo < 32) freew &= (1u << (n - lo)) - 1u;
-      const int cnt = __popc(freew);
-      if (left < cnt) {
-        for (int t = 0; t < left; ++t) freew &= freew - 1u;
-        job = lo + __ffs(freew) - 1;
-      } else {
-        left -= cnt;
+      const int q = slot / u;
+      c = slot - q * u;
+      p = base + q;
+      live = keeps(rule, blb[(int64_t)d * cap + p], ub);
+      if (c == 0) {
+        branched += live ? 1 : 0;
+        pruned += live ? 0 : 1;
       }
     }
-    uint8_t *crec = pool + (size_t)pos * stride;
-    const uint4 *src = reinterpret_cast<const uint4 *>(prec);
-    uint4 *dst = reinterpret_cast<uint4 *>(crec);
-    for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
-    crec[0] = (uint8_t)(d + 1);
-    crec[1 + d] = (uint8_t)job;
+    const int pos = wave_slot(live, &D->children);
+    if (!live) continue;
+    // opaque per round: otherwise the per-byte tests against d below are
+    // hoisted out of the loop, one scalar register pair each
+    int dd = d, lc = last_chunk;
+    asm volatile("" : "+s"(dd), "+s"(lc));
+    const uint4 *src = reinterpret_cast<const uint4 *>(
+        bnodes + ((int64_t)d * cap + p) * stride);
+    uint4 *dst = reinterpret_cast<uint4 *>(pool + (size_t)pos * stride);
+    if (n <= 32) {
+      // scheduled set in one register; byte 1 + d <= 32 lies in chunk 0..2
+      uint32_t used = 0;
+      uint4 ch[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k > lc) break;
+        const uint4 v = src[k];
+        ch[k] = v;
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+          const int at = 16 * k + b;
+          if (at >= 1 && at <= dd) used |= 1u << ((w[b >> 2] >> (8 * (b & 3))) & 31u);
+        }
+      }
+      // c-th unscheduled job in ascending id
+      uint32_t freew = ~used & (n == 32 ? 0xffffffffu : ((1u << n) - 1u));
+      for (int t = 0; t < c; ++t) freew &= freew - 1u;
+      const uint32_t job = (uint32_t)(__ffs(freew) - 1);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k > lc) break;
+        const uint4 v = ch[k];
+        uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        if (k == 0) w[0] = (w[0] & ~0xffu) | (uint32_t)(d + 1);
+        if (k == lc) {
+          const int b = (1 + d) & 15, sh = 8 * (b & 3);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (q == (b >> 2)) w[q] = (w[q] & ~(0xffu << sh)) | (job << sh);
+        }
+        dst[k] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    } else {
+      uint32_t used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int k = 0; 16 * k <= dd; ++k) {
+        const uint4 v = src[k];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+          const int at = 16 * k + b;
+          if (at >= 1 && at <= dd) {
+            const uint32_t j = (w[b >> 2] >> (8 * (b & 3))) & 0xffu;
+            used[j >> 5] |= 1u << (j & 31u);
+          }
+        }
+      }
+      int job = -1, left = c;
+      for (int w = 0; w < 8 && job < 0; ++w) {
+        const int lo = w * 32;
+        if (lo >= n) break;
+        uint32_t freew = ~used[w];
+        if (n - lo < 32) freew &= (1u << (n - lo)) - 1u;
+        const int cnt = __popc(freew);
+        if (left < cnt) {
+          for (int t = 0; t < left; ++t) freew &= freew - 1u;
+          job = lo + __ffs(freew) - 1;
+        } else {
+          left -= cnt;
+        }
+      }
+      for (int k = 0; k <= lc; ++k) dst[k] = src[k];
+      uint8_t *crec = reinterpret_cast<uint8_t *>(dst);
+      crec[0] = (uint8_t)(d + 1);
+      crec[1 + d] = (uint8_t)job;
+    }
   }
+  wave_total(&D->nodes_branched, branched);
+  wave_total(&D->nodes_pruned, pruned);
 }
 
 // ---- prune + compaction ----------------------------------------------------
@@ -198,15 +232,16 @@ __global__ __launch_bounds__(kThreads) void prune_kernel(
   if (blockIdx.x == 0 && threadIdx.x == 0)
     atomicAdd(reinterpret_cast<unsigned long long *>(&D->nodes_bounded),
               (unsigned long long)total);
-  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < total; r0 += gsz) {
-    const int64_t i = r0 + threadIdx.x;
+  const int gsz = gridDim.x * blockDim.x;
+  int leaves = 0, pruned = 0;
+  for (int r0 = blockIdx.x * blockDim.x; r0 < total; r0 += gsz) {
+    const int i = r0 + threadIdx.x;
     const bool in = i < total;
     const int lb = in ? pool_lb[i] : 0;
     const bool leaf = in && d1 == n;
     const bool keep = in && !leaf && keeps(rule, lb, ub);
-    wave_add(&D->leaves, leaf);
-    wave_add(&D->nodes_pruned, in && !keep && !(leaf && lb < ub));
+    leaves += leaf ? 1 : 0;
+    pruned += (in && !keep && !(leaf && lb < ub)) ? 1 : 0;
     if (leaf && lb < ub) {
       const uint64_t key = ((uint64_t)(uint32_t)lb << 32) | (uint64_t)i;
       atomicMin(reinterpret_cast<unsigned long long *>(&D->best_key),
@@ -232,9 +267,12 @@ __global__ __launch_bounds__(kThreads) void prune_kernel(
     const int64_t at = (int64_t)d1 * cap + pos;
     const uint4 *src = reinterpret_cast<const uint4 *>(pool + (size_t)i * stride);
     uint4 *dst = reinterpret_cast<uint4 *>(bnodes + at * stride);
-    for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
+    // bytes past the prefix are never read
+    for (int q = 0; q <= (d1 >> 4); ++q) dst[q] = src[q];
     blb[at] = lb;
   }
+  wave_total(&D->leaves, leaves);
+  wave_total(&D->nodes_pruned, pruned);
 }
 
 // smallest bound among the pending nodes (for the optimality gap after a

@@ -6,6 +6,32 @@
 
 namespace fspi {
 
+// Wave-level compaction: returns this lane's slot in an array whose length
+// counter is *counter (one atomic per wave).  Only lanes with pred get a slot.
+// Every lane of the wave must call it.
+__device__ __forceinline__ int wave_slot(bool pred, int32_t *counter) {
+  const uint64_t mask = __ballot(pred);
+  const int lane = __lane_id();
+  const uint64_t below = lane == 0 ? 0ull : (mask & ((~0ull) >> (64 - lane)));
+  const int rank = __popcll(below);
+  const uint64_t act = __ballot(1);
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  int base = 0;
+  if (lane == leader && mask) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  return base + rank;
+}
+
+// Adds the wave's sum of v to *counter (one atomic per wave).  Every active
+// lane of the wave must call it.
+__device__ __forceinline__ void wave_total(int64_t *counter, int v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const uint64_t act = __ballot(1);
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  if (__lane_id() == leader && v)
+    atomicAdd(reinterpret_cast<unsigned long long *>(counter), (unsigned long long)v);
+}
+
 // Iteration descriptor and counters, in device memory; the host reads a copy
 // once per batch of pools.
 struct BnbDesc {

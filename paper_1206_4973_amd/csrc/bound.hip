@@ -73,15 +73,17 @@ struct BoundParams {
 template <int M, bool WIDE, bool CHUNKED>
 __global__ __launch_bounds__(kBlock, 4) void bound_kernel(const BoundParams a) {
   extern __shared__ __align__(16) char smem[];
-  const LdsView L = carve<WIDE>(smem, a.I);
-  stage_instance<WIDE>(a.I, L);
-  __syncthreads();
   int64_t count = a.count, ntiles = a.ntiles;
   if (a.count_dev) {
     // never more than the capacity that sized the grid and the scratch
     count = min((int64_t)*a.count_dev, a.count);
     ntiles = (count + kBlock - 1) / kBlock;
   }
+  // a workgroup without a tile leaves before staging the tables
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  const LdsView L = carve<WIDE>(smem, a.I);
+  stage_instance<WIDE>(a.I, L);
+  __syncthreads();
   const size_t tile_bytes = (size_t)(kBlock / 64) * (size_t)a.I.slot_bytes;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
     bound_nodes<M, WIDE, CHUNKED>(a.I, L, a.nodes, a.stride, a.aligned != 0,

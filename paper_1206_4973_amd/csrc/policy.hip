@@ -23,6 +23,8 @@
 //              from whether its bound reaches the final UB (y1 target).
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "bnb.hpp"
 #include "fsp_internal.hpp"
 
@@ -39,50 +41,111 @@ __device__ __forceinline__ int feat_machine(int t, int m, int mm) {
 
 }  // namespace
 
-// ---- features of the nodes of bucket `depth + 1` --------------------------
-__global__ void features_kernel(BnbDesc *D, const int32_t *__restrict__ bcount,
-                                const uint8_t *__restrict__ bnodes,
-                                const int32_t *__restrict__ blb, int64_t cap,
-                                int stride, const int32_t *__restrict__ p,
-                                const int32_t *__restrict__ tot, int n, int m, int mp,
-                                float inv_scale, __bf16 *__restrict__ X) {
+// ---- features --------------------------------------------------------------
+// Features of one node record (16-byte aligned, prefix of depth d), written
+// as 32 bf16 values.  M (the machine count) is a template parameter so that
+// the per-machine values stay in registers.
+template <int M>
+__device__ __forceinline__ void node_features(const uint8_t *rec, int lb,
+                                              const int32_t *__restrict__ p,
+                                              const int32_t *__restrict__ tot, int n,
+                                              int mp, float inv_scale, __bf16 *x) {
+  constexpr int mm = M < kMaxFeatMachines ? M : kMaxFeatMachines;
+  int F[M], S[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    F[k] = 0;
+    S[k] = tot[k];
+  }
+  const uint4 *rc = reinterpret_cast<const uint4 *>(rec);
+  const int d = rec[0];
+  for (int c = 0; 16 * c <= d; ++c) {
+    const uint4 v = rc[c];
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      const int at = 16 * c + b;
+      if (at >= 1 && at <= d) {
+        const int j = (int)((w[b >> 2] >> (8 * (b & 3))) & 0xffu);
+        const int32_t *row = p + j * mp;
+        F[0] += row[0];
+        S[0] -= row[0];
+#pragma unroll
+        for (int k = 1; k < M; ++k) {
+          F[k] = max(F[k], F[k - 1]) + row[k];
+          S[k] -= row[k];
+        }
+      }
+    }
+  }
+  float f[kFeat];
+#pragma unroll
+  for (int t = 0; t < kFeat; ++t) f[t] = 0.f;
+  f[0] = (float)d / (float)n;
+  f[1] = (float)lb * inv_scale;
+#pragma unroll
+  for (int t = 0; t < mm; ++t) {
+    const int k = feat_machine(t, M, mm);
+    f[2 + t] = (float)F[k] * inv_scale;
+    f[2 + mm + t] = (float)S[k] * inv_scale;
+  }
+  uint4 *xo = reinterpret_cast<uint4 *>(x);
+#pragma unroll
+  for (int q = 0; q < kFeat / 8; ++q) {
+    uint32_t h[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const __bf16 lo = (__bf16)f[8 * q + 2 * e], hi = (__bf16)f[8 * q + 2 * e + 1];
+      h[e] = (uint32_t)__builtin_bit_cast(uint16_t, lo) |
+             ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+    }
+    xo[q] = make_uint4(h[0], h[1], h[2], h[3]);
+  }
+}
+
+// features of the nodes of bucket `depth + 1`
+template <int M>
+__global__ __launch_bounds__(256) void features_kernel(
+    BnbDesc *D, const int32_t *__restrict__ bcount, const uint8_t *__restrict__ bnodes,
+    const int32_t *__restrict__ blb, int64_t cap, int stride,
+    const int32_t *__restrict__ p, const int32_t *__restrict__ tot, int n, int mp,
+    float inv_scale, __bf16 *__restrict__ X) {
   const bool act = D->active && D->depth + 1 < n;
   const int d1 = D->depth + 1;
   const int count = act ? bcount[d1] : 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) D->feat_count = count;
-  const int mm = m < kMaxFeatMachines ? m : kMaxFeatMachines;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += gridDim.x * blockDim.x) {
     const int64_t at = (int64_t)d1 * cap + i;
-    const uint8_t *rec = bnodes + at * stride;
-    int F[kMaxMachines], S[kMaxMachines];
-    for (int k = 0; k < m; ++k) {
-      F[k] = 0;
-      S[k] = tot[k];
-    }
-    const int d = rec[0];
-    for (int q = 0; q < d; ++q) {
-      const int j = rec[1 + q];
-      const int32_t *row = p + j * mp;
-      F[0] += row[0];
-      S[0] -= row[0];
-      for (int k = 1; k < m; ++k) {
-        F[k] = max(F[k], F[k - 1]) + row[k];
-        S[k] -= row[k];
-      }
-    }
-    __bf16 *x = X + i * kFeat;
-    float f[kFeat];
-    for (int t = 0; t < kFeat; ++t) f[t] = 0.f;
-    f[0] = (float)d / (float)n;
-    f[1] = (float)blb[at] * inv_scale;
-    for (int t = 0; t < mm; ++t) {
-      const int k = feat_machine(t, m, mm);
-      f[2 + t] = (float)F[k] * inv_scale;
-      f[2 + mm + t] = (float)S[k] * inv_scale;
-    }
-    for (int t = 0; t < kFeat; ++t) x[t] = (__bf16)f[t];
+    node_features<M>(bnodes + at * stride, blb[at], p, tot, n, mp, inv_scale,
+                     X + (int64_t)i * kFeat);
   }
+}
+
+// features of an explicit list of nodes (training samples)
+template <int M>
+__global__ __launch_bounds__(256) void features_list_kernel(
+    const uint8_t *__restrict__ nodes, const int32_t *__restrict__ lbs, int64_t count,
+    int stride, const int32_t *__restrict__ p, const int32_t *__restrict__ tot, int n,
+    int mp, float inv_scale, __bf16 *__restrict__ X) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    node_features<M>(nodes + i * stride, lbs[i], p, tot, n, mp, inv_scale, X + i * kFeat);
+}
+
+using FeatBucketFn = decltype(&features_kernel<2>);
+using FeatListFn = decltype(&features_list_kernel<2>);
+
+template <int... Ks>
+FeatBucketFn bucket_fn(int m, std::integer_sequence<int, Ks...>) {
+  constexpr FeatBucketFn table[] = {features_kernel<Ks + 2>...};
+  return table[m - 2];
+}
+
+template <int... Ks>
+FeatListFn list_fn(int m, std::integer_sequence<int, Ks...>) {
+  constexpr FeatListFn table[] = {features_list_kernel<Ks + 2>...};
+  return table[m - 2];
 }
 
 __global__ void score_kernel(BnbDesc *D, const int32_t *__restrict__ blb,
@@ -110,14 +173,28 @@ __device__ __forceinline__ bool sel_needed(const BnbDesc *D) {
   return D->active && D->parents < D->sel_count;
 }
 
-__global__ void sel_hist_kernel(const BnbDesc *D, const float *__restrict__ bscore,
-                                int64_t cap, int32_t *__restrict__ hist) {
+// Histogram of est over the bucket: each workgroup counts a block of at
+// least kHistPerBlock entries in LDS, then adds its non-empty bins to the
+// global histogram (scores crowd into few bins, which would serialise
+// per-entry global atomics).
+constexpr int kHistPerBlock = 4096;
+
+__global__ __launch_bounds__(256) void sel_hist_kernel(const BnbDesc *D,
+                                                       const float *__restrict__ bscore,
+                                                       int64_t cap, int32_t *__restrict__ hist) {
   if (!sel_needed(D)) return;
   const int count = D->sel_count;
+  const int nblk = min((int)gridDim.x, (count + kHistPerBlock - 1) / kHistPerBlock);
+  if ((int)blockIdx.x >= nblk) return;
+  __shared__ int sh[kBins];
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) sh[b] = 0;
+  __syncthreads();
   const int64_t base = (int64_t)D->depth * cap;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&hist[est_bin(bscore[base + i])], 1);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += nblk * blockDim.x)
+    atomicAdd(&sh[est_bin(bscore[base + i])], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x)
+    if (sh[b]) atomicAdd(&hist[b], sh[b]);
 }
 
 // one workgroup of 256 threads; clears the histogram for its next use
@@ -168,13 +245,19 @@ __global__ void sel_partition_kernel(BnbDesc *D, const uint8_t *__restrict__ bno
   if (!sel_needed(D)) return;
   const int count = D->sel_count, K = D->parents, T = D->sel_T, need = D->sel_need;
   const int64_t base = (int64_t)D->depth * cap;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float e = bscore[base + i];
+  // uniform rounds: every lane of a wave takes part in the wave-level slots
+  for (int r0 = blockIdx.x * blockDim.x; r0 < count; r0 += gridDim.x * blockDim.x) {
+    const int i = r0 + threadIdx.x;
+    const bool in = i < count;
+    const float e = in ? bscore[base + i] : 0.f;
     const int b = est_bin(e);
-    bool take = b < T;
-    if (b == T) take = atomicAdd(&D->sel_tie, 1) < need;
-    const int pos = take ? count - K + atomicAdd(&D->sel_hi, 1) : atomicAdd(&D->sel_lo, 1);
+    const bool tie = in && b == T;
+    const int trank = wave_slot(tie, &D->sel_tie);
+    const bool take = in && (b < T || (tie && trank < need));
+    const int hi = wave_slot(take, &D->sel_hi);
+    const int lo = wave_slot(in && !take, &D->sel_lo);
+    if (!in) continue;
+    const int pos = take ? count - K + hi : lo;
     const uint4 *src = reinterpret_cast<const uint4 *>(bnodes + (base + i) * stride);
     uint4 *dst = reinterpret_cast<uint4 *>(tnodes + (int64_t)pos * stride);
     for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
@@ -292,9 +375,10 @@ int policy_enqueue_select(BnbState &S, hipStream_t s, int grid) {
 
 int policy_enqueue_score(BnbState &S, hipStream_t s, int grid) {
   const fsp_instance *in = S.inst;
-  hipLaunchKernelGGL(features_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.bcount, S.bnodes,
-                     S.blb, S.cap, S.stride, in->d_p, in->d_tot, in->n, in->m, in->mp,
-                     S.inv_scale, reinterpret_cast<__bf16 *>(S.X));
+  FeatBucketFn fn = bucket_fn(in->m, std::make_integer_sequence<int, kMaxMachines - 1>());
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, S.desc, S.bcount, S.bnodes, S.blb, S.cap,
+                     S.stride, in->d_p, in->d_tot, in->n, in->mp, S.inv_scale,
+                     reinterpret_cast<__bf16 *>(S.X));
   FSP_HIP_TRY(hipGetLastError());
   int rc = model_forward_dev(S.model, S.X, &S.desc->feat_count, S.cap, S.Y, s);
   if (rc != FSP_OK) return rc;
@@ -318,54 +402,13 @@ int policy_label(const fsp_instance *in, const uint8_t *nodes, const int32_t *lb
   return FSP_OK;
 }
 
-// features of an explicit list of nodes (training samples): reuse the bucket
-// kernel through a one-bucket view
-namespace {
-__global__ void features_list_kernel(const uint8_t *__restrict__ nodes,
-                                     const int32_t *__restrict__ lbs, int64_t count,
-                                     int stride, const int32_t *__restrict__ p,
-                                     const int32_t *__restrict__ tot, int n, int m, int mp,
-                                     float inv_scale, __bf16 *__restrict__ X) {
-  const int mm = m < kMaxFeatMachines ? m : kMaxFeatMachines;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint8_t *rec = nodes + i * stride;
-    int F[kMaxMachines], S[kMaxMachines];
-    for (int k = 0; k < m; ++k) {
-      F[k] = 0;
-      S[k] = tot[k];
-    }
-    const int d = rec[0];
-    for (int q = 0; q < d; ++q) {
-      const int j = rec[1 + q];
-      const int32_t *row = p + j * mp;
-      F[0] += row[0];
-      S[0] -= row[0];
-      for (int k = 1; k < m; ++k) {
-        F[k] = max(F[k], F[k - 1]) + row[k];
-        S[k] -= row[k];
-      }
-    }
-    float f[kFeat];
-    for (int t = 0; t < kFeat; ++t) f[t] = 0.f;
-    f[0] = (float)d / (float)n;
-    f[1] = (float)lbs[i] * inv_scale;
-    for (int t = 0; t < mm; ++t) {
-      const int k = feat_machine(t, m, mm);
-      f[2 + t] = (float)F[k] * inv_scale;
-      f[2 + mm + t] = (float)S[k] * inv_scale;
-    }
-    for (int t = 0; t < kFeat; ++t) X[i * kFeat + t] = (__bf16)f[t];
-  }
-}
-}  // namespace
-
 int policy_features(const fsp_instance *in, const uint8_t *nodes, const int32_t *lbs,
                     int64_t count, int stride, float inv_scale, void *X, hipStream_t s) {
   if (count == 0) return FSP_OK;
-  hipLaunchKernelGGL(features_list_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
-                     s, nodes, lbs, count, stride, in->d_p, in->d_tot, in->n, in->m, in->mp,
-                     inv_scale, reinterpret_cast<__bf16 *>(X));
+  FeatListFn fn = list_fn(in->m, std::make_integer_sequence<int, kMaxMachines - 1>());
+  hipLaunchKernelGGL(fn, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, nodes, lbs,
+                     count, stride, in->d_p, in->d_tot, in->n, in->mp, inv_scale,
+                     reinterpret_cast<__bf16 *>(X));
   FSP_HIP_TRY(hipGetLastError());
   return FSP_OK;
 }
