@@ -89,6 +89,11 @@ BNB_SEEDS = [4504, 4507, 4511, 4512, 4514, 4519]
 BNB_TIME_LIMIT = 20.0
 
 
+def progress(msg: str) -> None:
+    """One line per finished step on stderr (the JSON result goes to stdout)."""
+    print(msg, file=sys.stderr, flush=True)
+
+
 def geomean(xs):
     xs = [max(float(x), 1e-9) for x in xs]
     return float(np.exp(np.mean(np.log(xs)))) if xs else None
@@ -111,6 +116,7 @@ def bnb_leg(seeds, time_limit) -> dict:
         for kind in kinds:
             kw = {"model": model} if kind == "learned" else {}
             r = fsp.branch_and_bound(inst, kind, time_limit=time_limit, **kw)
+            progress(f"bnb seed {s} {kind}: {r.makespan} in {r.t_total_s:.3f} s")
             row[kind] = {"makespan": r.makespan, "proven": r.status == 0,
                          "t_proof_s": r.t_total_s, "t_found_s": r.t_found_s,
                          "nodes": r.nodes_bounded, "pool": r.final_pool}
@@ -207,6 +213,7 @@ def large_workload(steps, warmup, bnb_time) -> dict:
         nodes = torch.from_numpy(pool).cuda()
         lb = torch.empty(len(pool), dtype=torch.int32, device="cuda")
         t = timed(lambda: inst.bound_pool(nodes, lb, stream=stream), steps, warmup, stream)
+        progress(f"large {n}x{m}: pool of {len(pool)} nodes bounded in {t * 1e3:.3f} ms")
         ops = algorithmic_ops(pool[:, 0], n, m)
         rec = {"pool_bounding": {"nodes": len(pool), "ms": t * 1e3,
                                  "nodes_per_s": len(pool) / t,
@@ -216,6 +223,8 @@ def large_workload(steps, warmup, bnb_time) -> dict:
         for kind in kinds:
             kw = {"model": model} if kind == "learned" else {}
             r = fsp.branch_and_bound(inst, kind, time_limit=bnb_time, **kw)
+            progress(f"large {n}x{m} {kind}: UB {r.makespan}, open bound {r.open_lb}, "
+                     f"{r.nodes_bounded} nodes in {r.t_total_s:.1f} s")
             rec[kind] = {"best_ub": r.makespan, "open_lb": r.open_lb,
                          "gap": (r.makespan - r.open_lb) / r.makespan,
                          "proven": r.status == 0, "nodes": r.nodes_bounded,
