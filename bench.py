@@ -330,7 +330,9 @@ def main() -> int:
             "unit": "TOP/s",
             "frac": achieved / INT32_PEAK_TOPS,
             "traffic": measured_traffic(),
-            "kernel": "bound_kernel<20,narrow>",
+            "kernel": {"packed": f"bound_kernel_p16<{m}> (two nodes per lane, 16-bit)",
+                       "register": f"bound_kernel<{m}> (one node per lane)",
+                       "masks": f"bound_kernel<{m}> (job masks)"}[inst.bound_path],
             "kernel_ms": kernel_s * 1e3,
             "algorithmic_ops_per_launch": ops,
         },

@@ -50,6 +50,7 @@
 #include <algorithm>
 #include <mutex>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "bound_tile.hpp"
@@ -91,7 +92,34 @@ __global__ __launch_bounds__(kBlock, 4) void bound_kernel(const BoundParams a) {
                                   a.slots + (size_t)tile * tile_bytes);
 }
 
+// Two nodes per lane in packed 16-bit arithmetic (n <= 32, total work <=
+// 32767): tiles of 2 * kBlock nodes.  Setting up the second node while the
+// first one's packed state is live needs more than 128 VGPRs at 16+
+// machines, so the bound is three workgroups per CU (up to 168 VGPRs).
+template <int M>
+__global__ __launch_bounds__(kBlock, 3) void bound_kernel_p16(const BoundParams a) {
+  extern __shared__ __align__(16) char smem[];
+  int64_t count = a.count, ntiles = a.ntiles;
+  if (a.count_dev) {
+    count = min((int64_t)*a.count_dev, a.count);
+    ntiles = (count + 2 * kBlock - 1) / (2 * kBlock);
+  }
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  const LdsView L = carve<false>(smem, a.I);
+  stage_instance<false>(a.I, L);
+  __syncthreads();
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    bound_nodes_p16<M>(a.I, L, a.nodes, a.stride, a.aligned != 0,
+                       tile * 2 * kBlock, count, a.lb);
+}
+
 using BoundFn = void (*)(BoundParams);
+
+template <int... Ks>
+BoundFn p16_kernel(int m, std::integer_sequence<int, Ks...>) {
+  constexpr BoundFn table[] = {bound_kernel_p16<Ks + 2>...};
+  return table[m - 2];
+}
 
 template <int M>
 BoundFn pick(bool wide, bool chunked) {
@@ -210,11 +238,13 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
     const int rc = stream_scratch(stream, need, &scratch);
     if (rc != FSP_OK) return rc;
   }
+  const bool p16 = inst->p16 != 0;
+  const int64_t tile_nodes = p16 ? 2 * kBlock : kBlock;
   BoundParams a{};
   a.slots = static_cast<char *>(scratch);
   a.nodes = nodes;
   a.count = count;
-  a.ntiles = (count + kBlock - 1) / kBlock;
+  a.ntiles = (count + tile_nodes - 1) / tile_nodes;
   a.count_dev = count_dev;
   a.stride = stride;
   a.aligned = ((reinterpret_cast<uintptr_t>(nodes) & 15) == 0 &&
@@ -223,7 +253,15 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
                   : 0;
   a.lb = lb_out;
   a.I = inst_view(inst, wide ? kTableBudgetWide : kTableBudgetNarrow);
-  BoundFn fn = kernel_for(inst->m, wide, a.I.nchunks > 1);
+  BoundFn fn;
+  if (p16) {
+    a.I.rec = inst->d_rec16;  // same size and LDS layout as the 32-bit table
+    fn = inst->m >= 2 && inst->m <= kMaxMachines
+             ? p16_kernel(inst->m, std::make_integer_sequence<int, kMaxMachines - 1>())
+             : nullptr;
+  } else {
+    fn = kernel_for(inst->m, wide, a.I.nchunks > 1);
+  }
   if (!fn) return FSP_EUNSUPPORTED;
   const size_t lds = lds_bytes(a.I.n, a.I.mp, a.I.npad, a.I.ppc, wide);
 

@@ -297,37 +297,31 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
   return LB256;
 }
 
-// Bound the 256 nodes [base, base + 256) of a pool (one per lane), writing
-// lb_out[idx] for idx < count.  For n > 32, tile_slots is this tile's part of
-// the mask scratch: kBlock / 64 slots of I.slot_bytes, never used by another
-// tile of the same launch (unused, may be null, for n <= 32).  Every lane of the workgroup must call it (the chunked form
-// synchronises the workgroup).
-template <int M, bool WIDE, bool CHUNKED>
-__device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
-                                            const uint8_t *nodes, int stride,
-                                            bool aligned, int64_t base,
-                                            int64_t count, int32_t *lb_out,
-                                            char *tile_slots) {
-  const int tid = threadIdx.x;
-  const int n = I.n, mp = I.mp, npad = I.npad;
-  char *s_rec = L.s_rec;
-  const int32_t *s_p = L.s_p;
-  uint32_t *words_lane = WIDE ? L.s_words + tid : nullptr;
+// Steps 1 and 2 for the node at idx (one per lane): decode the prefix (U,
+// the front F, the prefix column sums), then heads r[k], tails q[k] and
+// r[k] + S[k] (S = remaining work), each shifted left by SH into R, T, Q.
+// last = F[m-1], the makespan of the prefix.
+template <int M, bool WIDE, int SH>
+__device__ __forceinline__ void node_state(const InstView I, const int32_t *s_p,
+                                           uint32_t *words_lane,
+                                           const uint8_t *nodes, int stride,
+                                           bool aligned, int64_t idx, bool live,
+                                           uint32_t &U, int &d, bool &bad,
+                                           int &last, int (&R)[M], int (&T)[M],
+                                           int (&Q)[M]) {
+  const int n = I.n, mp = I.mp;
   const uint32_t full = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
-  const int64_t idx = base + tid;
-  const bool live = idx < count;
-
   // ---- 1. decode the prefix, front recurrence, prefix column sums ----
   int F[M], Pk[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) F[k] = Pk[k] = 0;
-  uint32_t U = full;
+  U = full;
   if constexpr (WIDE)
     for (int w = 0; w * 32 < n; ++w)
       words_lane[w * kBlock] = n - w * 32 >= 32 ? 0xffffffffu
                                                  : ((1u << (n - w * 32)) - 1u);
-  bool bad = false;
-  int d = 0;
+  bad = false;
+  d = 0;
   if (live) {
     const uint8_t *rp = nodes + idx * (int64_t)stride;
     d = rp[0];
@@ -389,7 +383,6 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   //         run on packed 16-bit pairs of machines: a scheduled job's pair is
   //         forced to 0xffff by an unsigned max with its all-ones sign mask,
   //         then one unsigned min per pair of machines. ----
-  int T256[M], R256[M], Q256[M];
   {
     constexpr int M2 = (M + 1) / 2;
     u16x2 hm2[M2], qm2[M2];
@@ -420,12 +413,39 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
       const int hmk = (k & 1) ? hm2[k >> 1].y : hm2[k >> 1].x;
       const int qmk = (k & 1) ? qm2[k >> 1].y : qm2[k >> 1].x;
       const int r = max(F[k], F[0] + hmk);
-      R256[k] = r << 8;
-      T256[k] = (r + I.tot[k] - Pk[k]) << 8;
-      Q256[k] = qmk << 8;
+      R[k] = r << SH;
+      T[k] = (r + I.tot[k] - Pk[k]) << SH;
+      Q[k] = qmk << SH;
     }
   }
-  const int last = F[M - 1];
+  last = F[M - 1];
+}
+
+// Bound the 256 nodes [base, base + 256) of a pool (one per lane), writing
+// lb_out[idx] for idx < count.  For n > 32, tile_slots is this tile's part of
+// the mask scratch: kBlock / 64 slots of I.slot_bytes, never used by another
+// tile of the same launch (unused, may be null, for n <= 32).  Every lane of
+// the workgroup must call it (the chunked form synchronises the workgroup).
+template <int M, bool WIDE, bool CHUNKED>
+__device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
+                                            const uint8_t *nodes, int stride,
+                                            bool aligned, int64_t base,
+                                            int64_t count, int32_t *lb_out,
+                                            char *tile_slots) {
+  const int tid = threadIdx.x;
+  const int n = I.n, mp = I.mp, npad = I.npad;
+  char *s_rec = L.s_rec;
+  const int32_t *s_p = L.s_p;
+  uint32_t *words_lane = WIDE ? L.s_words + tid : nullptr;
+  const int64_t idx = base + tid;
+  const bool live = idx < count;
+
+  uint32_t U;
+  int d, last;
+  bool bad;
+  int T256[M], R256[M], Q256[M];
+  node_state<M, WIDE, 8>(I, s_p, words_lane, nodes, stride, aligned, idx, live,
+                         U, d, bad, last, R256, T256, Q256);
   const int u_left = WIDE ? n - d : __builtin_popcount(U);
 
   // ---- 3. (n > 32) the wave's job masks, then every machine pair.  The
@@ -477,6 +497,168 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   int lb = u_left == 0 ? last : (LB256 >> 8);
   if (bad) lb = FSP_LB_INVALID;
   if (live) lb_out[idx] = lb;
+}
+
+// ---- two nodes per lane in packed 16-bit halves (instances whose total
+//      work is at most 32767: every head, tail, clock difference and bound
+//      of the method then lies in [0, 32767], and z + x in [-32767, 32767]) --
+//
+// The lane holds node A in the low and node B in the high 16 bits of every
+// state value.  The unscheduled sets are interleaved into one 64-bit word
+// W = {A jobs 0..15, B jobs 0..15, A jobs 16..31, B jobs 16..31} (16 bits
+// each), so that (W >> s) with s = (job & 15) + 32 (job >> 4) has A's bit in
+// bit 0 and B's bit in bit 16.  One position then costs
+//   al = (W >> s) & 0x10001                     (v_lshrrev_b64, v_and_b32)
+//   t  = z + al * x,  u = al * y               (v_pk_mad_u16, v_pk_mul_lo_u16;
+//        x and y are the halves of one record word, broadcast by op_sel)
+//   z  = max(t, u)                              (v_pk_max_i16)
+// i.e. 5 instructions for two nodes instead of 8.
+__device__ __forceinline__ uint32_t step_p16(uint64_t W, uint32_t xy,
+                                             uint32_t s, uint32_t z) {
+  const uint32_t al = (uint32_t)(W >> s) & 0x10001u;
+  uint32_t t, u, r;
+  asm("v_pk_mad_u16 %0, %1, %2, %3 op_sel_hi:[1,0,1]"
+      : "=v"(t) : "v"(al), "v"(xy), "v"(z));
+  asm("v_pk_mul_lo_u16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,1]"
+      : "=v"(u) : "v"(al), "v"(xy));
+  asm("v_pk_max_i16 %0, %1, %2" : "=v"(r) : "v"(t), "v"(u));
+  return r;
+}
+
+__device__ __forceinline__ uint32_t walk1_p16(const char *rp_raw, int npad,
+                                              uint64_t W, uint32_t Z) {
+  const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);  // 2 records
+  for (int i = 0; i < npad / 4; ++i) {
+    const int4 r0 = rp[2 * i], r1 = rp[2 * i + 1];
+    Z = step_p16(W, r0.x, r0.y, Z);
+    Z = step_p16(W, r0.z, r0.w, Z);
+    Z = step_p16(W, r1.x, r1.y, Z);
+    Z = step_p16(W, r1.z, r1.w, Z);
+  }
+  return Z;
+}
+
+__device__ __forceinline__ void walk2_p16(const char *ra_raw, const char *rb_raw,
+                                          int npad, uint64_t W, uint32_t &ZA,
+                                          uint32_t &ZB) {
+  const int4 *ra = reinterpret_cast<const int4 *>(ra_raw);
+  const int4 *rb = reinterpret_cast<const int4 *>(rb_raw);
+  for (int i = 0; i < npad / 4; ++i) {
+    const int4 a0 = ra[2 * i], a1 = ra[2 * i + 1];
+    const int4 b0 = rb[2 * i], b1 = rb[2 * i + 1];
+    ZA = step_p16(W, a0.x, a0.y, ZA);
+    ZB = step_p16(W, b0.x, b0.y, ZB);
+    ZA = step_p16(W, a0.z, a0.w, ZA);
+    ZB = step_p16(W, b0.z, b0.w, ZB);
+    ZA = step_p16(W, a1.x, a1.y, ZA);
+    ZB = step_p16(W, b1.x, b1.y, ZB);
+    ZA = step_p16(W, a1.z, a1.w, ZA);
+    ZB = step_p16(W, b1.z, b1.w, ZB);
+  }
+}
+
+__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) +
+                                          __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) -
+                                          __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t,
+                            __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                      __builtin_bit_cast(u16x2, b)));
+}
+
+// Every pair (the whole table is in LDS: n <= 32).  Returns the packed max
+// over pairs of the pair bounds of nodes A and B.
+template <int M>
+__device__ __forceinline__ uint32_t pair_sweep_p16(const char *s_rec, int npad,
+                                                   uint64_t W,
+                                                   const uint32_t (&R)[M],
+                                                   const uint32_t (&T)[M],
+                                                   const uint32_t (&Q)[M]) {
+  int pb = npad * (int)sizeof(Rec);
+  asm volatile("" : "+s"(pb));
+  int off = 0;
+  uint32_t LB = 0;
+#pragma unroll
+  for (int k = 0; k < M - 1; ++k) {
+#pragma unroll
+    for (int l = k + 1; l < M; l += 2) {
+      if (l + 1 < M) {
+        uint32_t ZA = pk_sub(R[l], R[k]), ZB = pk_sub(R[l + 1], R[k]);
+        walk2_p16(s_rec + off, s_rec + off + pb, npad, W, ZA, ZB);
+        // T + Q + z wraps in 16 bits only on the way: the sum is a bound of
+        // the method, at most the total work
+        LB = pk_max(LB, pk_max(pk_add(pk_add(T[k], Q[l]), ZA),
+                               pk_add(pk_add(T[k], Q[l + 1]), ZB)));
+        asm volatile("" : "+v"(LB));
+        off += 2 * pb;
+      } else {
+        uint32_t Z = walk1_p16(s_rec + off, npad, W, pk_sub(R[l], R[k]));
+        LB = pk_max(LB, pk_add(pk_add(T[k], Q[l]), Z));
+        asm volatile("" : "+v"(LB));
+        off += pb;
+      }
+    }
+  }
+  return LB;
+}
+
+// Bound the 512 nodes [base, base + 512) of a pool, nodes base + tid (low
+// halves) and base + 256 + tid (high halves), writing lb_out[idx] for
+// idx < count.  n <= 32 and the table is whole in LDS (I.rec is the packed
+// table).  Every lane of the workgroup must call it.
+template <int M>
+__device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView &L,
+                                                const uint8_t *nodes, int stride,
+                                                bool aligned, int64_t base,
+                                                int64_t count, int32_t *lb_out) {
+  const int tid = threadIdx.x;
+  const int64_t ia = base + tid, ib = base + kBlock + tid;
+  const bool la = ia < count, lbv = ib < count;
+  uint32_t R[M], T[M], Q[M];
+  uint32_t UA, UB;
+  int dA, dB, lastA, lastB;
+  bool badA, badB;
+  {
+    int r[M], t[M], q[M];
+    node_state<M, false, 0>(I, L.s_p, nullptr, nodes, stride, aligned, ia, la, UA,
+                            dA, badA, lastA, r, t, q);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      R[k] = (uint32_t)r[k] & 0xffffu;
+      T[k] = (uint32_t)t[k] & 0xffffu;
+      Q[k] = (uint32_t)q[k] & 0xffffu;
+    }
+  }
+  {
+    int r[M], t[M], q[M];
+    node_state<M, false, 0>(I, L.s_p, nullptr, nodes, stride, aligned, ib, lbv, UB,
+                            dB, badB, lastB, r, t, q);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      R[k] |= (uint32_t)r[k] << 16;
+      T[k] |= (uint32_t)t[k] << 16;
+      Q[k] |= (uint32_t)q[k] << 16;
+    }
+  }
+  const uint64_t W =
+      (uint64_t)((UA & 0xffffu) | (UB << 16)) |
+      ((uint64_t)((UA >> 16) | (UB & 0xffff0000u)) << 32);
+#pragma unroll
+  for (int k = 0; k < M; ++k) asm volatile("" : "+v"(R[k]), "+v"(T[k]), "+v"(Q[k]));
+  const uint32_t LB = pair_sweep_p16<M>(L.s_rec, I.npad, W, R, T, Q);
+  if (la) {
+    int lb = __builtin_popcount(UA) == 0 ? lastA : (int)(LB & 0xffffu);
+    lb_out[ia] = badA ? FSP_LB_INVALID : lb;
+  }
+  if (lbv) {
+    int lb = __builtin_popcount(UB) == 0 ? lastB : (int)(LB >> 16);
+    lb_out[ib] = badB ? FSP_LB_INVALID : lb;
+  }
 }
 
 // InstView of a loaded instance with the pair table split into LDS chunks of

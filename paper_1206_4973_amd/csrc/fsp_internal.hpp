@@ -57,6 +57,11 @@ struct fsp_instance {
   int32_t *d_p = nullptr, *d_H = nullptr, *d_Q = nullptr, *d_tot = nullptr;
   uint32_t *d_Hp = nullptr, *d_Qp = nullptr;  // H, Q as packed 16-bit pairs
   fspi::Rec *d_rec = nullptr;  // [P][npad]
+  // Packed 16-bit table for two nodes per lane (p16 = 1: n <= 32 and total
+  // work <= 32767, so every quantity of the bound fits in 16 bits):
+  //   {x | y << 16 with x = b - a, y = lag + b;  s = (job & 15) + 32 (job >> 4)}
+  int p16 = 0;
+  fspi::Rec *d_rec16 = nullptr;  // [P][npad]
   uint32_t *d_joff = nullptr;  // [P][npad] 8 * job id per table position
   std::vector<int32_t> p_host;  // [n][m], for host-side set-up work (NEH)
 };

@@ -57,7 +57,8 @@ __global__ void stage_totals(const int32_t *__restrict__ p, int n, int mp,
 
 __global__ __launch_bounds__(256) void stage_pairs(
     const int32_t *__restrict__ p, int n, int m, int mp, int npad,
-    Rec *__restrict__ rec_out, uint32_t *__restrict__ joff_out) {
+    Rec *__restrict__ rec_out, uint32_t *__restrict__ joff_out,
+    Rec *__restrict__ rec16_out) {
   __shared__ int sA[256], sB[256];
   const int pi = blockIdx.x;
   // (k,l) of pair pi in lexicographic order
@@ -107,6 +108,15 @@ __global__ __launch_bounds__(256) void stage_pairs(
   const size_t slot = (size_t)pi * npad + pos;
   rec_out[slot] = make_int2(x, y);
   joff_out[slot] = 8u * (uint32_t)(j < n ? j : n);
+  if (rec16_out) {
+    // padding: x = y = 0 leaves the packed state unchanged whatever s selects
+    int xy = 0, s = 0;
+    if (j < n) {
+      xy = (int)(((uint32_t)(b - a) & 0xffffu) | ((uint32_t)(lag + b) << 16));
+      s = (j & 15) + 32 * (j >> 4);
+    }
+    rec16_out[slot] = make_int2(xy, s);
+  }
 }
 
 void free_device(fsp_instance *in) {
@@ -116,12 +126,14 @@ void free_device(fsp_instance *in) {
   if (in->d_tot) (void)hipFree(in->d_tot);
   if (in->d_rec) (void)hipFree(in->d_rec);
   if (in->d_joff) (void)hipFree(in->d_joff);
+  if (in->d_rec16) (void)hipFree(in->d_rec16);
   if (in->d_Hp) (void)hipFree(in->d_Hp);
   if (in->d_Qp) (void)hipFree(in->d_Qp);
   in->d_Hp = in->d_Qp = nullptr;
   in->d_p = in->d_H = in->d_Q = in->d_tot = nullptr;
   in->d_rec = nullptr;
   in->d_joff = nullptr;
+  in->d_rec16 = nullptr;
 }
 
 int build_tables(fsp_instance *in, const int32_t *p_host) {
@@ -133,6 +145,8 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
       hipMalloc(&in->d_tot, mp * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&in->d_rec, (size_t)in->P * in->npad * sizeof(Rec)) != hipSuccess ||
       hipMalloc(&in->d_joff, joff_bytes(in->P, in->npad)) != hipSuccess ||
+      (in->p16 && hipMalloc(&in->d_rec16, (size_t)in->P * in->npad * sizeof(Rec)) !=
+                      hipSuccess) ||
       hipMalloc(&in->d_Hp, mat / 2) != hipSuccess ||
       hipMalloc(&in->d_Qp, mat / 2) != hipSuccess)
     return FSP_ENOMEM;
@@ -154,7 +168,8 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
     hipLaunchKernelGGL(stage_totals, dim3(1), dim3(64), 0, s, in->d_p, n, mp,
                        in->d_tot);
     hipLaunchKernelGGL(stage_pairs, dim3(in->P), dim3(256), 0, s, in->d_p, n,
-                       m, mp, in->npad, in->d_rec, in->d_joff);
+                       m, mp, in->npad, in->d_rec, in->d_joff,
+                       in->d_rec16);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
       rc = FSP_EDEVICE;
   }
@@ -205,6 +220,7 @@ int fsp_load_instance(const int32_t *p_host, int32_t n, int32_t m,
   in->P = npairs(m);
   in->npad = round_up(n, 4);
   in->wide = n > 32 ? 1 : 0;
+  in->p16 = (n <= 32 && total <= 32767) ? 1 : 0;
   in->p_host.assign(p_host, p_host + (size_t)n * m);
   if (hipGetDevice(&in->device) != hipSuccess) {
     delete in;
@@ -233,6 +249,12 @@ int fsp_instance_info(const fsp_instance *inst, int32_t *n, int32_t *m,
   if (n) *n = inst->n;
   if (m) *m = inst->m;
   if (device) *device = inst->device;
+  return FSP_OK;
+}
+
+int fsp_instance_path(const fsp_instance *inst, int32_t *path) {
+  if (!inst || !path) return FSP_EINVAL;
+  *path = inst->wide ? FSP_PATH_MASKS : (inst->p16 ? FSP_PATH_PACKED : FSP_PATH_REGISTER);
   return FSP_OK;
 }
 

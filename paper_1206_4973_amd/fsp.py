@@ -90,6 +90,8 @@ def lib() -> ctypes.CDLL:
     L.fsp_free_instance.restype = ctypes.c_int
     L.fsp_instance_info.argtypes = [P, P, P, P]
     L.fsp_instance_info.restype = ctypes.c_int
+    L.fsp_instance_path.argtypes = [P, P]
+    L.fsp_instance_path.restype = ctypes.c_int
     L.fsp_bound_pool.argtypes = [ctypes.POINTER(_Nodes), i64, P, P]
     L.fsp_bound_pool.restype = ctypes.c_int
     L.fsp_branch_and_bound.argtypes = [P, ctypes.POINTER(_Policy), i32,
@@ -173,6 +175,14 @@ class Instance:
         dev = ctypes.c_int32()
         _check(lib().fsp_instance_info(h, None, None, ctypes.byref(dev)), "fsp_instance_info")
         self.device = torch.device("cuda", dev.value)
+
+    @property
+    def bound_path(self) -> str:
+        """Form of the bounding walk used for this instance: "register",
+        "packed" (two nodes per lane, 16-bit) or "masks" (n > 32)."""
+        v = ctypes.c_int32(0)
+        _check(lib().fsp_instance_path(self.handle, ctypes.byref(v)), "fsp_instance_path")
+        return {0: "register", 1: "packed", 2: "masks"}[v.value]
 
     @property
     def handle(self) -> ctypes.c_void_p:

@@ -84,6 +84,8 @@ def test_other_entry_points_reject_null(L):
     assert L.fsp_free_instance(None) == 0
     L.fsp_instance_info.argtypes = [ctypes.c_void_p] * 4
     assert L.fsp_instance_info(None, None, None, None) == -1
+    L.fsp_instance_path.argtypes = [ctypes.c_void_p] * 2
+    assert L.fsp_instance_path(None, None) == -1
     L.fsp_bound_pool.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.c_void_p]
     assert L.fsp_bound_pool(None, 10, None, None) == -1

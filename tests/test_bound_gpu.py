@@ -178,3 +178,35 @@ def test_full_size_pool_sampled(fsp, orc, n, m, seed, dlo, dhi):
     # the last records of the pool
     tail = np.arange(count - 37, count)
     assert np.array_equal(got[tail], orc.bound_pool(p, pool[tail], nthreads=8))
+
+
+@pytest.mark.parametrize("n,m,total,big", [(20, 20, 32767, 0), (20, 20, 32768, 0),
+                                           (12, 6, 32767, 30000), (31, 20, 32767, 20000),
+                                           (2, 2, 32767, 32767)])
+def test_packed_path_limits(fsp, orc, n, m, total, big):
+    """Instances whose total work sits at the limit of the two-nodes-per-lane
+    16-bit path (<= 32767 takes it, 32768 does not), some with one processing
+    time close to the largest 16-bit value: every bound must equal the
+    oracle's."""
+    rng = np.random.default_rng(total + n + big)
+    p = rng.integers(0, 100, size=(n, m)).astype(np.int64)
+    if big:
+        p[0, m // 2] = big
+    # put the difference on entries of other jobs (job totals stay <= 65535)
+    diff = total - int(p.sum())
+    j = 1 % n
+    while diff != 0:
+        k = int(rng.integers(0, m))
+        step = max(-int(p[j, k]), min(diff, 32767 - int(p[j, k]), 65535 - int(p[j].sum())))
+        p[j, k] += step
+        diff -= step
+        j = (j + 1) % n
+    p = p.astype(np.int32)
+    assert int(p.sum()) == total and p.max() <= 32767
+    pool = I.random_pool(n, 2000, 0, n, 900000 + total + n)
+    say(f"packed limit n={n} m={m} total={total} max p={int(p.max())}")
+    inst = fsp.Instance(p)
+    assert inst.bound_path == ("packed" if total <= 32767 else "register")
+    got = gpu_bounds(fsp, inst, pool)
+    want = orc.bound_pool(p, pool, nthreads=8)
+    assert np.array_equal(got, want)
