@@ -63,7 +63,7 @@ def measured_traffic() -> float | None:
         return None
 
 
-def cpu_baseline(p, pool, target_s: float = 10.0) -> dict:
+def cpu_baseline(p, pool, target_s: float = 15.0) -> dict:
     from oracle import oracle as O
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     probe = pool[:4096]
@@ -235,6 +235,38 @@ def large_workload(steps, warmup, bnb_time) -> dict:
     return out
 
 
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix cores
+
+
+def policy_workload(steps, warmup) -> dict:
+    """The policy network on 2^20 rows of 22 features (the 20x10 model):
+    forward, and backward with weight gradients (forward recomputed), on the
+    matrix cores.  Algorithmic FLOPs use the real layer sizes 22-128-128-2;
+    the kernels run them padded to 32 inputs and 16 outputs."""
+    import torch
+    from paper_1206_4973_amd import train_policy
+    model = train_policy.load(os.path.join(ROOT, "paper_1206_4973_amd", "policy_20x10.npz"))
+    rows = 1 << 20
+    g = torch.Generator(device="cpu").manual_seed(6000)
+    x = torch.zeros((rows, 32), dtype=torch.float32)
+    x[:, :22] = torch.rand((rows, 22), generator=g)
+    x = x.to(torch.bfloat16).cuda()
+    dy = torch.randn((rows, 2), generator=g).cuda()
+    stream = torch.cuda.current_stream()
+    t_fwd = timed(lambda: model.forward(x, stream=stream), steps, warmup, stream)
+    t_bwd = timed(lambda: model.backward(x, dy, stream=stream), steps, warmup, stream)
+    fwd = 2 * (22 * 128 + 128 * 128 + 128 * 2)
+    bwd = fwd + 2 * (2 * 128 * 2) + 2 * (2 * 128 * 128) + 2 * 22 * 128
+    out = {"workload": "policy network 22-128-128-2, 2^20 rows (seed 6000)", "rows": rows}
+    for name, t, f in (("forward", t_fwd, fwd), ("backward", t_bwd, bwd)):
+        tf = rows * f / t / 1e12
+        out[name] = {"ms": t * 1e3, "rows_per_s": rows / t, "flop_per_row": f,
+                     "achieved_TFLOPs": tf, "peak_TFLOPs": BF16_PEAK_TFLOPS,
+                     "frac": tf / BF16_PEAK_TFLOPS}
+        progress(f"policy {name}: {t * 1e3:.3f} ms, {tf:.1f} TFLOP/s")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,9 +275,10 @@ def main() -> int:
     ap.add_argument("--log2-pool", type=int, default=22)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-bnb", action="store_true", help="skip the B&B time-to-optimum leg")
-    ap.add_argument("--workload", default="pool", choices=["pool", "batch", "large"],
+    ap.add_argument("--workload", default="pool", choices=["pool", "batch", "large", "policy"],
                     help="pool: the 20x20 line (default); batch: 64 mixed instances in one "
-                         "launch; large: 50x20 and 200x20 pools and time-limited searches")
+                         "launch; large: 50x20 and 200x20 pools and time-limited searches; "
+                         "policy: the policy network's forward and backward kernels")
     ap.add_argument("--bnb-time", type=float, default=60.0,
                     help="time limit of each search of the large workload (s)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -275,6 +308,9 @@ def main() -> int:
         return 0
     if args.workload == "large":
         print(json.dumps(large_workload(args.steps, args.warmup, args.bnb_time)), flush=True)
+        return 0
+    if args.workload == "policy":
+        print(json.dumps(policy_workload(args.steps, args.warmup)), flush=True)
         return 0
     n, m, seed = 20, 20, 2000
     count = 1 << args.log2_pool
