@@ -7,9 +7,9 @@
 // gradients that feed a product are rounded to bf16 exactly where a product
 // consumes them.
 //
-// Forward: one wave per 16 rows, weights read as MFMA B fragments from global
-// memory (L2-resident), the hidden activations of the wave's rows staged in
-// LDS between layers.
+// Forward: layers computed transposed so that each result tile is already
+// the next layer's operand (see forward_kernel); weights and biases stay in
+// registers and each wave streams 16-row tiles.
 // Backward: one workgroup per 64-row tile (4 waves); the forward is recomputed,
 // then dW3, dH2, dW2 = H1^T dZ2, dH1 = dZ2 W2^T, dW1 = X^T dZ1 and dX = dZ1 W1^T
 // are products on the matrix cores; each workgroup accumulates its weight
@@ -63,7 +63,12 @@ constexpr int eW1n = eW1t + kH * kIn;
 constexpr int eW2t = eW1n + kIn * kH;
 constexpr int eW2n = eW2t + kH * kH;
 constexpr int eW3t = eW2n + kH * kH;
-constexpr int kExport = eW3t + kOut * kH;
+// Forward-kernel layouts of W2 and W3 (A operands of the transposed products,
+// see forward_kernel): [out][kt][g][j] = W[32 kt + perm(g, j)][out] with
+// perm(g, j) = 4g + j for j < 4 and 16 + 4g + (j - 4) for j >= 4.
+constexpr int eW2p = eW3t + kOut * kH;
+constexpr int eW3p = eW2p + kH * kH;
+constexpr int kExport = eW3p + kOut * kH;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -101,73 +106,97 @@ __global__ void export_kernel(const float *__restrict__ P, bf16 *__restrict__ E)
     const int c = t / kOut, o = t % kOut;  // W3[c][o]
     E[eW3t + o * kH + c] = (bf16)P[oW3 + t];
   }
+  // permuted-K layouts, indexed by destination: t = ((out * 4 + kt) * 4 + g) * 8 + j
+  {
+    const int j = t & 7, g = (t >> 3) & 3, kt = (t >> 5) & 3, out = t >> 7;
+    const int in = 32 * kt + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+    if (t < kH * kH) E[eW2p + t] = (bf16)P[oW2 + in * kH + out];
+    if (t < kOut * kH) E[eW3p + t] = (bf16)P[oW3 + in * kOut + out];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // forward: x [N][kIn] bf16 -> y [N][nout] fp32
+//
+// Every layer is computed transposed, Z^T = W^T A^T: the MFMA A operand is a
+// 16-feature slice of W^T, the B operand 16 rows of the layer input.  The
+// result tile holds, in lane (g, c), features 4g .. 4g+3 of row c, which is
+// half of what lane (g, c) must supply as the next layer's B operand for a
+// 32-feature K step.  Taking two consecutive result tiles gives the lane
+// features {4g..4g+3} and {16+4g..16+4g+3} of the step: a fixed permutation
+// of K, which the next layer's weights follow (the eW2p / eW3p exports), so
+// no activation passes through LDS.  The bias is the accumulator's initial
+// value.  All 44 weight fragments and the biases stay in registers for the
+// whole kernel; each wave streams 16-row tiles.
+__device__ __forceinline__ bf16x8 relu_pack(f32x4 a, f32x4 b) {
+  bf16x8 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r[i] = (bf16)fmaxf(a[i], 0.f);
+    r[4 + i] = (bf16)fmaxf(b[i], 0.f);
+  }
+  return r;
+}
+
 __global__ __launch_bounds__(256) void forward_kernel(
     const bf16 *__restrict__ X, int64_t N, const int32_t *__restrict__ n_dev,
     const float *__restrict__ P, const bf16 *__restrict__ E, float *__restrict__ Y,
     int nout) {
-  __shared__ __align__(16) bf16 sH[4][16 * kH];  // one 16-row stripe per wave
-  const int w = threadIdx.x >> 6;
-  bf16 *H = sH[w];
   if (n_dev) N = *n_dev;  // row count produced on the device
   if (N <= 0) return;
-  const int64_t stripes = (N + 15) / 16;
-  // every wave of the workgroup runs the same number of rounds (a wave past
-  // the last stripe recomputes the clamped last rows and stores nothing), so
-  // the workgroup barriers below are reached by all of them
-  for (int64_t s0 = (int64_t)blockIdx.x * 4; s0 < stripes; s0 += (int64_t)gridDim.x * 4) {
-    // opaque per round: otherwise every weight fragment is loop-invariant and
-    // gets hoisted out of the loop into its own registers
-    asm volatile("" : "+s"(E));
-    const int64_t s = s0 + w;
-    const int64_t r0 = s * 16;
-    bf16x8 xa;
-    {
-      const int l = lane_id();
-      int64_t r = r0 + (l & 15);
-      if (r >= N) r = N - 1;
-      xa = *reinterpret_cast<const bf16x8 *>(X + r * kIn + 8 * (l >> 4));
-    }
-    // layer 1: 8 column tiles, K = 32
-    for (int nt = 0; nt < kH / 16; ++nt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = mma(xa, frag(E + eW1t, kIn, nt * 16, 0), acc);
-      const int col = nt * 16 + dcol();
-      const float b = P[oB1 + col];
-      for (int i = 0; i < 4; ++i) H[drow(i) * kH + col] = (bf16)fmaxf(acc[i] + b, 0.f);
-    }
-    __syncthreads();
-    // layer 2: K = 128 (4 steps) -> keep in registers, then overwrite H
-    f32x4 h2[kH / 16];
-    for (int nt = 0; nt < kH / 16; ++nt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      for (int kt = 0; kt < kH / 32; ++kt)
-        acc = mma(frag(H, kH, 0, kt * 32), frag(E + eW2t, kH, nt * 16, kt * 32), acc);
-      h2[nt] = acc;
-    }
-    __syncthreads();
-    for (int nt = 0; nt < kH / 16; ++nt) {
-      const int col = nt * 16 + dcol();
-      const float b = P[oB2 + col];
-      for (int i = 0; i < 4; ++i) H[drow(i) * kH + col] = (bf16)fmaxf(h2[nt][i] + b, 0.f);
-    }
-    __syncthreads();
-    // layer 3: one 16-column tile, K = 128
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int l = lane_id(), g = l >> 4, c = l & 15;
+  const int wave = threadIdx.x >> 6;
+  // A operands: lane (g, c) holds out feature 16 mt + c, K elements 8g .. 8g+7
+  // of the step (permuted for W2 and W3)
+  bf16x8 w1[kH / 16], w2[kH / 16][kH / 32], w3[kH / 32];
+  f32x4 b1[kH / 16], b2[kH / 16], b3;
+#pragma unroll
+  for (int mt = 0; mt < kH / 16; ++mt) {
+    w1[mt] = *reinterpret_cast<const bf16x8 *>(E + eW1t + (mt * 16 + c) * kIn + 8 * g);
+#pragma unroll
     for (int kt = 0; kt < kH / 32; ++kt)
-      acc = mma(frag(H, kH, 0, kt * 32), frag(E + eW3t, kH, 0, kt * 32), acc);
-    const int col = dcol();
-    if (col < nout && s < stripes) {
-      const float b = P[oB3 + col];
-      for (int i = 0; i < 4; ++i) {
-        const int64_t r = r0 + drow(i);
-        if (r < N) Y[r * nout + col] = acc[i] + b;
-      }
+      w2[mt][kt] = *reinterpret_cast<const bf16x8 *>(
+          E + eW2p + ((mt * 16 + c) * 4 + kt) * 32 + 8 * g);
+    b1[mt] = *reinterpret_cast<const f32x4 *>(P + oB1 + mt * 16 + 4 * g);
+    b2[mt] = *reinterpret_cast<const f32x4 *>(P + oB2 + mt * 16 + 4 * g);
+  }
+#pragma unroll
+  for (int kt = 0; kt < kH / 32; ++kt)
+    w3[kt] = *reinterpret_cast<const bf16x8 *>(E + eW3p + (c * 4 + kt) * 32 + 8 * g);
+  b3 = *reinterpret_cast<const f32x4 *>(P + oB3 + 4 * g);
+
+  const int64_t tiles = (N + 15) / 16;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < tiles;
+       t += (int64_t)gridDim.x * 4) {
+    const int64_t row = t * 16 + c;
+    const int64_t rr = row < N ? row : N - 1;
+    const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(X + rr * kIn + 8 * g);
+    bf16x8 h1[kH / 32];
+#pragma unroll
+    for (int kt = 0; kt < kH / 32; ++kt) {
+      const f32x4 a0 = mma(w1[2 * kt], xb, b1[2 * kt]);
+      const f32x4 a1 = mma(w1[2 * kt + 1], xb, b1[2 * kt + 1]);
+      h1[kt] = relu_pack(a0, a1);
     }
-    __syncthreads();
+    bf16x8 h2[kH / 32];
+#pragma unroll
+    for (int ot = 0; ot < kH / 32; ++ot) {
+      f32x4 a0 = b2[2 * ot], a1 = b2[2 * ot + 1];
+#pragma unroll
+      for (int kt = 0; kt < kH / 32; ++kt) {
+        a0 = mma(w2[2 * ot][kt], h1[kt], a0);
+        a1 = mma(w2[2 * ot + 1][kt], h1[kt], a1);
+      }
+      h2[ot] = relu_pack(a0, a1);
+    }
+    f32x4 y = b3;
+#pragma unroll
+    for (int kt = 0; kt < kH / 32; ++kt) y = mma(w3[kt], h2[kt], y);
+    if (row < N) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * g + i < nout) Y[row * nout + 4 * g + i] = y[i];
+    }
   }
 }
 
@@ -209,7 +238,9 @@ __global__ __launch_bounds__(256) void backward_kernel(
 
   const int64_t tiles = (N + kRows - 1) / kRows;
   for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-    asm volatile("" : "+s"(E), "+s"(P));  // see forward_kernel
+    // opaque per tile: otherwise every weight fragment is loop-invariant and
+    // gets hoisted out of the tile loop into registers of its own
+    asm volatile("" : "+s"(E), "+s"(P));
     const int64_t base = t * kRows;
     __syncthreads();
     // load x (rows past N are zero) and dY
@@ -453,7 +484,7 @@ uint64_t splitmix(uint64_t &s) {
 }
 
 int export_weights(fsp_model *m, hipStream_t s) {
-  hipLaunchKernelGGL(export_kernel, dim3((kH * kH + 255) / 256), dim3(256), 0, s, m->P, m->E);
+  hipLaunchKernelGGL(export_kernel, dim3((kH * kH + 255) / 256), dim3(256), 0, s, m->P, m->E);  // covers every layout
   FSP_HIP_TRY(hipGetLastError());
   return FSP_OK;
 }
@@ -476,9 +507,11 @@ namespace fspi {
 int model_forward_dev(const fsp_model *m, const void *x, const int32_t *n_dev, int64_t max_n,
                       float *y, hipStream_t s) {
   if (max_n <= 0) return FSP_OK;
-  const int64_t stripes = (max_n + 15) / 16;
-  int64_t grid = (stripes + 3) / 4;
-  if (grid > (int64_t)m->cus * 8) grid = (int64_t)m->cus * 8;
+  // one workgroup per CU: every wave keeps all weights in registers and
+  // streams 16-row tiles
+  const int64_t tiles = (max_n + 15) / 16;
+  int64_t grid = (tiles + 3) / 4;
+  if (grid > (int64_t)m->cus) grid = (int64_t)m->cus;
   hipLaunchKernelGGL(forward_kernel, dim3((unsigned)grid), dim3(256), 0, s,
                      reinterpret_cast<const bf16 *>(x), max_n, n_dev, m->P, m->E, y,
                      m->outputs);
