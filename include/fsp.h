@@ -84,15 +84,19 @@ int fsp_instance_info(const fsp_instance *inst, int32_t *n, int32_t *m,
 
 /* Which form of the pool-bounding walk (Sec. V.D's bound; the forms give
  * identical bounds) fsp_bound_pool uses for this instance:
- *   FSP_PATH_REGISTER  n <= 32: one node per lane, the unscheduled set in a
- *                      register;
- *   FSP_PATH_PACKED    n <= 32 and total work <= 32767: two nodes per lane in
- *                      packed 16-bit arithmetic (every value of the bound then
- *                      fits in 16 bits);
- *   FSP_PATH_MASKS     n > 32: one node per lane, per-wave job masks read by
- *                      scalar loads.
- * The batch kernel always uses the register or mask form. */
-enum { FSP_PATH_REGISTER = 0, FSP_PATH_PACKED = 1, FSP_PATH_MASKS = 2 };
+ *   FSP_PATH_REGISTER    n <= 32: one node per lane, the unscheduled set in a
+ *                        register;
+ *   FSP_PATH_PACKED      n <= 32 and total work <= 32767: two nodes per lane
+ *                        in packed 16-bit arithmetic (every value of the bound
+ *                        then fits in 16 bits);
+ *   FSP_PATH_MASKS       n > 64: one node per lane, per-wave job masks read
+ *                        by scalar loads;
+ *   FSP_PATH_REGISTER64  32 < n <= 64: one node per lane, the unscheduled set
+ *                        in a 64-bit register pair.
+ * The batch kernel uses the register form for n <= 32 and the mask form
+ * above. */
+enum { FSP_PATH_REGISTER = 0, FSP_PATH_PACKED = 1, FSP_PATH_MASKS = 2,
+       FSP_PATH_REGISTER64 = 3 };
 int fsp_instance_path(const fsp_instance *inst, int32_t *path);
 
 /* ---- pool bounding (Sec. III: one launch bounds a whole pool) --------- */

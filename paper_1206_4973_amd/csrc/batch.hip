@@ -56,7 +56,8 @@ __device__ __forceinline__ void run_tile(const BatchSeg &S, char *smem,
     stage_instance<WIDE>(I, L);
     __syncthreads();
   }
-  bound_nodes<M, WIDE, CHUNKED>(I, L, S.nodes, S.stride, S.aligned != 0,
+  bound_nodes<M, WIDE ? kFormMasks : kFormReg32, CHUNKED>(I, L, S.nodes, S.stride,
+                                                          S.aligned != 0,
                                 (t - S.tile_begin) * kBlock, S.count, S.lb,
                                 tile_slots);
 }

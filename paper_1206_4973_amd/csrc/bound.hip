@@ -71,8 +71,9 @@ struct BoundParams {
   char *slots;  // bound_scratch_bytes(n, count) bytes of job-mask slots (n > 32)
 };
 
-template <int M, bool WIDE, bool CHUNKED>
+template <int M, int FORM, bool CHUNKED>
 __global__ __launch_bounds__(kBlock, 4) void bound_kernel(const BoundParams a) {
+  constexpr bool WIDE = FORM == kFormMasks;
   extern __shared__ __align__(16) char smem[];
   int64_t count = a.count, ntiles = a.ntiles;
   if (a.count_dev) {
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(kBlock, 4) void bound_kernel(const BoundParams a) {
   __syncthreads();
   const size_t tile_bytes = (size_t)(kBlock / 64) * (size_t)a.I.slot_bytes;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-    bound_nodes<M, WIDE, CHUNKED>(a.I, L, a.nodes, a.stride, a.aligned != 0,
+    bound_nodes<M, FORM, CHUNKED>(a.I, L, a.nodes, a.stride, a.aligned != 0,
                                   tile * kBlock, count, a.lb,
                                   a.slots + (size_t)tile * tile_bytes);
 }
@@ -122,32 +123,35 @@ BoundFn p16_kernel(int m, std::integer_sequence<int, Ks...>) {
 }
 
 template <int M>
-BoundFn pick(bool wide, bool chunked) {
-  if (!wide) return bound_kernel<M, false, false>;
-  return chunked ? bound_kernel<M, true, true> : bound_kernel<M, true, false>;
+BoundFn pick(int form, bool chunked) {
+  // the 64-bit register form always takes the chunked body (it also serves a
+  // table of one chunk)
+  if (form == kFormReg64) return bound_kernel<M, kFormReg64, true>;
+  if (form == kFormReg32) return bound_kernel<M, kFormReg32, false>;
+  return chunked ? bound_kernel<M, kFormMasks, true> : bound_kernel<M, kFormMasks, false>;
 }
 
-BoundFn kernel_for(int m, bool wide, bool chunked) {
+BoundFn kernel_for(int m, int form, bool chunked) {
   switch (m) {
-    case 2: return pick<2>(wide, chunked);
-    case 3: return pick<3>(wide, chunked);
-    case 4: return pick<4>(wide, chunked);
-    case 5: return pick<5>(wide, chunked);
-    case 6: return pick<6>(wide, chunked);
-    case 7: return pick<7>(wide, chunked);
-    case 8: return pick<8>(wide, chunked);
-    case 9: return pick<9>(wide, chunked);
-    case 10: return pick<10>(wide, chunked);
-    case 11: return pick<11>(wide, chunked);
-    case 12: return pick<12>(wide, chunked);
-    case 13: return pick<13>(wide, chunked);
-    case 14: return pick<14>(wide, chunked);
-    case 15: return pick<15>(wide, chunked);
-    case 16: return pick<16>(wide, chunked);
-    case 17: return pick<17>(wide, chunked);
-    case 18: return pick<18>(wide, chunked);
-    case 19: return pick<19>(wide, chunked);
-    case 20: return pick<20>(wide, chunked);
+    case 2: return pick<2>(form, chunked);
+    case 3: return pick<3>(form, chunked);
+    case 4: return pick<4>(form, chunked);
+    case 5: return pick<5>(form, chunked);
+    case 6: return pick<6>(form, chunked);
+    case 7: return pick<7>(form, chunked);
+    case 8: return pick<8>(form, chunked);
+    case 9: return pick<9>(form, chunked);
+    case 10: return pick<10>(form, chunked);
+    case 11: return pick<11>(form, chunked);
+    case 12: return pick<12>(form, chunked);
+    case 13: return pick<13>(form, chunked);
+    case 14: return pick<14>(form, chunked);
+    case 15: return pick<15>(form, chunked);
+    case 16: return pick<16>(form, chunked);
+    case 17: return pick<17>(form, chunked);
+    case 18: return pick<18>(form, chunked);
+    case 19: return pick<19>(form, chunked);
+    case 20: return pick<20>(form, chunked);
     default: return nullptr;
   }
 }
@@ -252,6 +256,8 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
                   ? 1
                   : 0;
   a.lb = lb_out;
+  // n > 32: the 64-bit register form up to 64 jobs, job masks above
+  const int form = !wide ? kFormReg32 : (inst->n <= 64 ? kFormReg64 : kFormMasks);
   a.I = inst_view(inst, wide ? kTableBudgetWide : kTableBudgetNarrow);
   BoundFn fn;
   if (p16) {
@@ -260,10 +266,10 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
              ? p16_kernel(inst->m, std::make_integer_sequence<int, kMaxMachines - 1>())
              : nullptr;
   } else {
-    fn = kernel_for(inst->m, wide, a.I.nchunks > 1);
+    fn = kernel_for(inst->m, form, a.I.nchunks > 1);
   }
   if (!fn) return FSP_EUNSUPPORTED;
-  const size_t lds = lds_bytes(a.I.n, a.I.mp, a.I.npad, a.I.ppc, wide);
+  const size_t lds = lds_bytes(a.I.n, a.I.mp, a.I.npad, a.I.ppc, form == kFormMasks);
 
   // device attributes and per-kernel occupancy are queried once per
   // (device, kernel, LDS size) and cached for this thread

@@ -33,6 +33,13 @@ struct LdsView {
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
+// Forms of the one-node-per-lane walk (see the header comment of bound.hip).
+enum Form : int {
+  kFormReg32 = 0,  // n <= 32: unscheduled set in one register
+  kFormMasks = 1,  // n > 32: per-wave job masks read by scalar loads
+  kFormReg64 = 2,  // 32 < n <= 64: unscheduled set in a 64-bit register pair
+};
+
 // Read-only views through the constant address space: loads from these with
 // a wave-uniform address are scalar loads whose result lands in SGPRs.
 typedef const __attribute__((address_space(4))) char kchar;
@@ -156,6 +163,51 @@ __device__ __forceinline__ void walk2_u(const char *ra_raw, const char *rb_raw,
   }
 }
 
+// ---- 32 < n <= 64: the node's unscheduled jobs are a 64-bit register pair ----
+// alpha = bit `job` of U, taken by a 64-bit shift by y (the shift uses the low
+// 6 bits of y, which hold the job id) and an and; then the same three
+// operations as above: 5 VALU per position and no memory access besides the
+// LDS record.
+__device__ __forceinline__ int step_u64(uint64_t U, int x, int y, int Z) {
+  uint64_t sh;
+  asm("v_lshrrev_b64 %0, %1, %2" : "=v"(sh) : "v"(y), "v"(U));
+  const uint32_t al = (uint32_t)sh & 1u;
+  const int up = __mul24((int)al, x) + Z;
+  const int lo = (int)__umul24(al, (uint32_t)y);
+  return max(up, lo);
+}
+
+__device__ __forceinline__ int walk1_u64(const char *rp_raw, int npad, uint64_t U,
+                                         int Z) {
+  const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);  // 2 records
+  for (int i = 0; i < npad / 4; ++i) {
+    const int4 r0 = rp[2 * i], r1 = rp[2 * i + 1];
+    Z = step_u64(U, r0.x, r0.y, Z);
+    Z = step_u64(U, r0.z, r0.w, Z);
+    Z = step_u64(U, r1.x, r1.y, Z);
+    Z = step_u64(U, r1.z, r1.w, Z);
+  }
+  return Z;
+}
+
+__device__ __forceinline__ void walk2_u64(const char *ra_raw, const char *rb_raw,
+                                          int npad, uint64_t U, int &ZA, int &ZB) {
+  const int4 *ra = reinterpret_cast<const int4 *>(ra_raw);
+  const int4 *rb = reinterpret_cast<const int4 *>(rb_raw);
+  for (int i = 0; i < npad / 4; ++i) {
+    const int4 a0 = ra[2 * i], a1 = ra[2 * i + 1];
+    const int4 b0 = rb[2 * i], b1 = rb[2 * i + 1];
+    ZA = step_u64(U, a0.x, a0.y, ZA);
+    ZB = step_u64(U, b0.x, b0.y, ZB);
+    ZA = step_u64(U, a0.z, a0.w, ZA);
+    ZB = step_u64(U, b0.z, b0.w, ZB);
+    ZA = step_u64(U, a1.x, a1.y, ZA);
+    ZB = step_u64(U, b1.x, b1.y, ZB);
+    ZA = step_u64(U, a1.z, a1.w, ZA);
+    ZB = step_u64(U, b1.z, b1.w, ZB);
+  }
+}
+
 // ---- n > 32: the wave's job masks, read back as SGPR pairs ----
 // One position of the two-machine walk (see the header comment of bound.hip):
 // z = max(z + x, y) in the lanes whose node has the position's job
@@ -223,14 +275,22 @@ __device__ __forceinline__ void walk2(const char *ra_raw, const char *rb_raw,
   }
 }
 
+template <int FORM>
+__device__ __forceinline__ int walk1_any(const char *rp, kchar *jp, kchar *ms,
+                                         int npad, uint64_t U, int Z) {
+  if constexpr (FORM == kFormMasks) return walk1(rp, jp, ms, npad, Z);
+  else if constexpr (FORM == kFormReg64) return walk1_u64(rp, npad, U, Z);
+  else return walk1_u(rp, npad, (uint32_t)U, Z);
+}
+
 // Every pair whose index lies in [lo, hi): pairs (k,l) and (k,l+1) are walked
 // together.  s_rec holds the records of pairs lo.. (LDS), jt the mask offsets
 // of pair lo.  Returns the max over those pairs of 256*(pair bound) + junk.
 // The record and job pointers advance pair by pair (pair index order = table
 // order) so that no per-pair address stays live.
-template <int M, bool WIDE>
+template <int M, int FORM>
 __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
-                                          int hi, int npad, uint32_t U,
+                                          int hi, int npad, uint64_t U,
                                           kchar *ms, const int (&R256)[M],
                                           const int (&T256)[M],
                                           const int (&Q256)[M], int LB256) {
@@ -253,11 +313,13 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
         const int offb = off + pb, joffb = joff + jb;
         if (ina && inb) {
           int ZA = R256[l] - R256[k], ZB = R256[l + 1] - R256[k];
-          if constexpr (WIDE)
+          if constexpr (FORM == kFormMasks)
             walk2(s_rec + off, s_rec + offb, jt + joff, jt + joffb, ms, npad,
                   ZA, ZB);
+          else if constexpr (FORM == kFormReg64)
+            walk2_u64(s_rec + off, s_rec + offb, npad, U, ZA, ZB);
           else
-            walk2_u(s_rec + off, s_rec + offb, npad, U, ZA, ZB);
+            walk2_u(s_rec + off, s_rec + offb, npad, (uint32_t)U, ZA, ZB);
           LB256 = max(LB256, max(T256[k] + Q256[l] + ZA,
                                  T256[k] + Q256[l + 1] + ZB));
           // keep the max chain sequential (a reassociated max tree would hold
@@ -265,16 +327,14 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
           asm volatile("" : "+v"(LB256));
         } else {
           if (ina) {
-            int Z = WIDE ? walk1(s_rec + off, jt + joff, ms, npad,
-                                 R256[l] - R256[k])
-                         : walk1_u(s_rec + off, npad, U, R256[l] - R256[k]);
+            int Z = walk1_any<FORM>(s_rec + off, jt + joff, ms, npad, U,
+                                    R256[l] - R256[k]);
             LB256 = max(LB256, T256[k] + Q256[l] + Z);
             asm volatile("" : "+v"(LB256));
           }
           if (inb) {
-            int Z = WIDE ? walk1(s_rec + offb, jt + joffb, ms, npad,
-                                 R256[l + 1] - R256[k])
-                         : walk1_u(s_rec + offb, npad, U, R256[l + 1] - R256[k]);
+            int Z = walk1_any<FORM>(s_rec + offb, jt + joffb, ms, npad, U,
+                                    R256[l + 1] - R256[k]);
             LB256 = max(LB256, T256[k] + Q256[l + 1] + Z);
             asm volatile("" : "+v"(LB256));
           }
@@ -283,9 +343,8 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
         joff += 2 * jb;
       } else {
         if (pa >= lo && pa < hi) {
-          int Z = WIDE ? walk1(s_rec + off, jt + joff, ms, npad,
-                               R256[l] - R256[k])
-                       : walk1_u(s_rec + off, npad, U, R256[l] - R256[k]);
+          int Z = walk1_any<FORM>(s_rec + off, jt + joff, ms, npad, U,
+                                  R256[l] - R256[k]);
           LB256 = max(LB256, T256[k] + Q256[l] + Z);
           asm volatile("" : "+v"(LB256));
         }
@@ -301,16 +360,17 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
 // the front F, the prefix column sums), then heads r[k], tails q[k] and
 // r[k] + S[k] (S = remaining work), each shifted left by SH into R, T, Q.
 // last = F[m-1], the makespan of the prefix.
-template <int M, bool WIDE, int SH>
+template <int M, bool WIDE, int SH, typename SetT = uint32_t>
 __device__ __forceinline__ void node_state(const InstView I, const int32_t *s_p,
                                            uint32_t *words_lane,
                                            const uint8_t *nodes, int stride,
                                            bool aligned, int64_t idx, bool live,
-                                           uint32_t &U, int &d, bool &bad,
+                                           SetT &U, int &d, bool &bad,
                                            int &last, int (&R)[M], int (&T)[M],
                                            int (&Q)[M]) {
   const int n = I.n, mp = I.mp;
-  const uint32_t full = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
+  constexpr int kSetBits = 8 * (int)sizeof(SetT);
+  const SetT full = n >= kSetBits ? ~SetT(0) : ((SetT(1) << n) - SetT(1));
   // ---- 1. decode the prefix, front recurrence, prefix column sums ----
   int F[M], Pk[M];
 #pragma unroll
@@ -363,7 +423,7 @@ __device__ __forceinline__ void node_state(const InstView I, const int32_t *s_p,
             *wp = v & ~bit;
           } else {
             if (!((U >> j) & 1u)) bad = true;
-            U &= ~(1u << j);
+            U &= ~(SetT(1) << j);
           }
           const int32_t *row = WIDE ? I.p + j * mp : s_p + j * mp;
           F[0] += row[0];
@@ -393,6 +453,8 @@ __device__ __forceinline__ void node_state(const InstView I, const int32_t *s_p,
       uint32_t g;
       if constexpr (WIDE)
         g = (uint32_t)__builtin_amdgcn_sbfe((int)~words_lane[(j >> 5) * kBlock], j & 31, 1);
+      else if constexpr (sizeof(SetT) == 8)
+        g = 0u - (uint32_t)((~U >> j) & 1u);
       else
         g = (uint32_t)__builtin_amdgcn_sbfe((int)~U, j, 1);
       const u16x2 gv = __builtin_bit_cast(u16x2, g);
@@ -426,12 +488,13 @@ __device__ __forceinline__ void node_state(const InstView I, const int32_t *s_p,
 // the mask scratch: kBlock / 64 slots of I.slot_bytes, never used by another
 // tile of the same launch (unused, may be null, for n <= 32).  Every lane of
 // the workgroup must call it (the chunked form synchronises the workgroup).
-template <int M, bool WIDE, bool CHUNKED>
+template <int M, int FORM, bool CHUNKED>
 __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
                                             const uint8_t *nodes, int stride,
                                             bool aligned, int64_t base,
                                             int64_t count, int32_t *lb_out,
                                             char *tile_slots) {
+  constexpr bool WIDE = FORM == kFormMasks;
   const int tid = threadIdx.x;
   const int n = I.n, mp = I.mp, npad = I.npad;
   char *s_rec = L.s_rec;
@@ -440,13 +503,20 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   const int64_t idx = base + tid;
   const bool live = idx < count;
 
-  uint32_t U;
+  using SetT = typename std::conditional<FORM == kFormReg64, uint64_t, uint32_t>::type;
+  SetT U;
   int d, last;
   bool bad;
   int T256[M], R256[M], Q256[M];
-  node_state<M, WIDE, 8>(I, s_p, words_lane, nodes, stride, aligned, idx, live,
-                         U, d, bad, last, R256, T256, Q256);
-  const int u_left = WIDE ? n - d : __builtin_popcount(U);
+  node_state<M, WIDE, 8, SetT>(I, s_p, words_lane, nodes, stride, aligned, idx,
+                               live, U, d, bad, last, R256, T256, Q256);
+  int u_left;
+  if constexpr (WIDE)
+    u_left = n - d;
+  else if constexpr (FORM == kFormReg64)
+    u_left = __builtin_popcountll(U);
+  else
+    u_left = __builtin_popcount(U);
 
   // ---- 3. (n > 32) the wave's job masks, then every machine pair.  The
   //         slot is written with vector stores and read back with scalar
@@ -474,7 +544,7 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
 #pragma unroll
     for (int k = 0; k < M; ++k)
       asm volatile("" : "+v"(R256[k]), "+v"(T256[k]), "+v"(Q256[k]));
-    LB256 = pair_sweep<M, WIDE>(s_rec, jt, 0, M * (M - 1) / 2, npad, U, ms,
+    LB256 = pair_sweep<M, FORM>(s_rec, jt, 0, M * (M - 1) / 2, npad, U, ms,
                                 R256, T256, Q256, LB256);
   } else {
     for (int chunk = 0; chunk < I.nchunks; ++chunk) {
@@ -488,7 +558,7 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
         asm volatile("" : "+v"(R256[k]), "+v"(T256[k]), "+v"(Q256[k]));
       int lo = chunk * I.ppc, hi = lo + I.ppc;
       asm volatile("" : "+s"(lo), "+s"(hi));
-      LB256 = pair_sweep<M, WIDE>(s_rec, jt + (size_t)lo * npad * 4, lo, hi,
+      LB256 = pair_sweep<M, FORM>(s_rec, jt + (size_t)lo * npad * 4, lo, hi,
                                   npad, U, ms, R256, T256, Q256, LB256);
     }
   }

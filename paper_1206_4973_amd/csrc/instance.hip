@@ -254,7 +254,10 @@ int fsp_instance_info(const fsp_instance *inst, int32_t *n, int32_t *m,
 
 int fsp_instance_path(const fsp_instance *inst, int32_t *path) {
   if (!inst || !path) return FSP_EINVAL;
-  *path = inst->wide ? FSP_PATH_MASKS : (inst->p16 ? FSP_PATH_PACKED : FSP_PATH_REGISTER);
+  if (inst->wide)
+    *path = inst->n <= 64 ? FSP_PATH_REGISTER64 : FSP_PATH_MASKS;
+  else
+    *path = inst->p16 ? FSP_PATH_PACKED : FSP_PATH_REGISTER;
   return FSP_OK;
 }
 

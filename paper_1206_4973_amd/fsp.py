@@ -179,10 +179,11 @@ class Instance:
     @property
     def bound_path(self) -> str:
         """Form of the bounding walk used for this instance: "register",
-        "packed" (two nodes per lane, 16-bit) or "masks" (n > 32)."""
+        "packed" (two nodes per lane, 16-bit), "register64" (33..64 jobs) or
+        "masks" (n > 64)."""
         v = ctypes.c_int32(0)
         _check(lib().fsp_instance_path(self.handle, ctypes.byref(v)), "fsp_instance_path")
-        return {0: "register", 1: "packed", 2: "masks"}[v.value]
+        return {0: "register", 1: "packed", 2: "masks", 3: "register64"}[v.value]
 
     @property
     def handle(self) -> ctypes.c_void_p:
