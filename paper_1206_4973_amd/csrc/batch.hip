@@ -24,7 +24,9 @@ using namespace fspi;
 namespace {
 
 enum Variant : int {
-  V5N, V5W, V5C, V10N, V10W, V10C, V20N, V20W, V20C, VNONE
+  // per machine count: register (n <= 32), masks (one table chunk), masks
+  // (chunked), 64-bit register (33..64 jobs, chunked body)
+  V5N, V5W, V5C, V5R, V10N, V10W, V10C, V10R, V20N, V20W, V20C, V20R, VNONE
 };
 
 struct BatchSeg {
@@ -46,18 +48,18 @@ __global__ void reset_counter(unsigned long long *c) {
   if (threadIdx.x == 0) *c = 0ull;
 }
 
-template <int M, bool WIDE, bool CHUNKED>
+template <int M, int FORM, bool CHUNKED>
 __device__ __forceinline__ void run_tile(const BatchSeg &S, char *smem,
                                          int64_t t, bool restage,
                                          char *tile_slots) {
+  constexpr bool WIDE = FORM == kFormMasks;
   const InstView I = S.I;
   const LdsView L = carve<WIDE>(smem, I);
   if (restage) {
     stage_instance<WIDE>(I, L);
     __syncthreads();
   }
-  bound_nodes<M, WIDE ? kFormMasks : kFormReg32, CHUNKED>(I, L, S.nodes, S.stride,
-                                                          S.aligned != 0,
+  bound_nodes<M, FORM, CHUNKED>(I, L, S.nodes, S.stride, S.aligned != 0,
                                 (t - S.tile_begin) * kBlock, S.count, S.lb,
                                 tile_slots);
 }
@@ -88,15 +90,18 @@ __global__ __launch_bounds__(kBlock, 4) void batch_kernel(
     cur = lo;
     char *ts = slots + t * tile_bytes;  // this tile's job-mask slots
     switch (S.variant) {
-      case V5N: run_tile<5, false, false>(S, smem, t, restage, ts); break;
-      case V5W: run_tile<5, true, false>(S, smem, t, restage, ts); break;
-      case V5C: run_tile<5, true, true>(S, smem, t, restage, ts); break;
-      case V10N: run_tile<10, false, false>(S, smem, t, restage, ts); break;
-      case V10W: run_tile<10, true, false>(S, smem, t, restage, ts); break;
-      case V10C: run_tile<10, true, true>(S, smem, t, restage, ts); break;
-      case V20N: run_tile<20, false, false>(S, smem, t, restage, ts); break;
-      case V20W: run_tile<20, true, false>(S, smem, t, restage, ts); break;
-      case V20C: run_tile<20, true, true>(S, smem, t, restage, ts); break;
+      case V5N: run_tile<5, kFormReg32, false>(S, smem, t, restage, ts); break;
+      case V5W: run_tile<5, kFormMasks, false>(S, smem, t, restage, ts); break;
+      case V5C: run_tile<5, kFormMasks, true>(S, smem, t, restage, ts); break;
+      case V5R: run_tile<5, kFormReg64, true>(S, smem, t, restage, ts); break;
+      case V10N: run_tile<10, kFormReg32, false>(S, smem, t, restage, ts); break;
+      case V10W: run_tile<10, kFormMasks, false>(S, smem, t, restage, ts); break;
+      case V10C: run_tile<10, kFormMasks, true>(S, smem, t, restage, ts); break;
+      case V10R: run_tile<10, kFormReg64, true>(S, smem, t, restage, ts); break;
+      case V20N: run_tile<20, kFormReg32, false>(S, smem, t, restage, ts); break;
+      case V20W: run_tile<20, kFormMasks, false>(S, smem, t, restage, ts); break;
+      case V20C: run_tile<20, kFormMasks, true>(S, smem, t, restage, ts); break;
+      case V20R: run_tile<20, kFormReg64, true>(S, smem, t, restage, ts); break;
       default: break;
     }
   }
@@ -111,6 +116,7 @@ int variant_of(const fsp_instance *inst, const InstView &v) {
     default: return VNONE;
   }
   if (!inst->wide) return base;
+  if (inst->n <= 64) return base + 3;
   return v.nchunks > 1 ? base + 2 : base + 1;
 }
 
@@ -223,7 +229,8 @@ int fsp_batch_create(const fsp_segment *segs, int32_t nsegs,
   for (Item &it : items) {
     it.s.tile_begin = tiles;
     tiles += (it.s.count + kBlock - 1) / kBlock;
-    const bool wide = it.s.variant % 3 != 0;
+    const int form = it.s.variant % 4;  // 0 register, 1-2 masks, 3 register64
+    const bool wide = form == 1 || form == 2;
     lds = std::max(lds, lds_bytes(it.s.I.n, it.s.I.mp, it.s.I.npad, it.s.I.ppc, wide));
     table.push_back(it.s);
   }
