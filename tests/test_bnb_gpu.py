@@ -194,3 +194,27 @@ def test_policy_samples(fsp, orc):
         assert np.all(rem <= tot * 1.01 + 1) and np.all(np.diff(front) >= -0.01 * neh_c)
         if abs(lb - res.makespan) > 0.01 * neh_c:
             assert T[r, 1] == (1.0 if lb >= res.makespan else 0.0)
+
+
+@pytest.mark.parametrize("n,m,kind", [(40, 5, "adaptive"), (50, 8, "autotuned"),
+                                      (80, 4, "adaptive")])
+def test_larger_instances_inside_the_search(fsp, orc, n, m, kind):
+    """The search on instances whose pools take the 64-bit register walk
+    (33..64 jobs) or the job-mask walk (more than 64 jobs): the root bound
+    equals the oracle's, and whatever the time limit leaves, the returned
+    schedule is valid, no worse than NEH, and not below the smallest pending
+    bound."""
+    p = I.instance(n, m, 7700 + n + m)
+    inst = fsp.Instance(p)
+    assert inst.bound_path == ("register64" if n <= 64 else "masks")
+    say(f"{n}x{m} {kind} with a 1.5 s limit")
+    res = fsp.branch_and_bound(inst, kind, time_limit=1.5)
+    assert res.status in (0, 1)
+    check_schedule(orc, p, res)
+    assert res.root_lb == orc.lower_bound(p, [])
+    neh_c, _ = orc.neh(p)
+    assert res.makespan <= neh_c
+    if res.status == 0:
+        assert res.makespan >= res.root_lb
+    else:
+        assert res.root_lb <= res.open_lb <= res.makespan
