@@ -99,15 +99,18 @@ def geomean(xs):
     return float(np.exp(np.mean(np.log(xs)))) if xs else None
 
 
-def bnb_leg(seeds, time_limit) -> dict:
+def bnb_leg(seeds, time_limit, only=None) -> dict:
     """Time to a proven optimum, plain adaptive (the paper's Algorithm 1,
     launch by launch) vs batched (graph-replayed iterations, autotuned pool)
-    vs batched + learned ordering, on held-out instances."""
+    vs batched + learned ordering, on held-out instances.  `only` restricts
+    the run to one kind (for profiling)."""
     from paper_1206_4973_amd import fsp, inputs
     from paper_1206_4973_amd import train_policy
     model_path = os.path.join(ROOT, "paper_1206_4973_amd", "policy_20x10.npz")
     model = train_policy.load(model_path) if os.path.exists(model_path) else None
     kinds = ["adaptive", "autotuned"] + (["learned"] if model is not None else [])
+    if only:
+        kinds = [only]
     rows = []
     for s in seeds:
         inst = fsp.Instance(inputs.instance(20, 10, s))
@@ -131,7 +134,7 @@ def bnb_leg(seeds, time_limit) -> dict:
     for k in kinds:
         out[k] = {"geomean_t_proof_s": geomean([r[k]["t_proof_s"] for r in rows]),
                   "geomean_nodes": geomean([r[k]["nodes"] for r in rows])}
-    for k in kinds[1:]:
+    for k in (kinds[1:] if "adaptive" in kinds else []):
         out[f"speedup_{k}_vs_adaptive"] = geomean(
             [r["adaptive"]["t_proof_s"] / r[k]["t_proof_s"] for r in rows])
         out[f"node_ratio_{k}_vs_adaptive"] = geomean(
@@ -275,10 +278,14 @@ def main() -> int:
     ap.add_argument("--log2-pool", type=int, default=22)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-bnb", action="store_true", help="skip the B&B time-to-optimum leg")
-    ap.add_argument("--workload", default="pool", choices=["pool", "batch", "large", "policy"],
+    ap.add_argument("--bnb-kind", default=None, choices=["adaptive", "autotuned", "learned"],
+                    help="with --workload bnb: run only this kind")
+    ap.add_argument("--workload", default="pool",
+                    choices=["pool", "batch", "large", "policy", "bnb"],
                     help="pool: the 20x20 line (default); batch: 64 mixed instances in one "
                          "launch; large: 50x20 and 200x20 pools and time-limited searches; "
-                         "policy: the policy network's forward and backward kernels")
+                         "policy: the policy network's forward and backward kernels; "
+                         "bnb: only the B&B time-to-optimum leg")
     ap.add_argument("--bnb-time", type=float, default=60.0,
                     help="time limit of each search of the large workload (s)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -311,6 +318,9 @@ def main() -> int:
         return 0
     if args.workload == "policy":
         print(json.dumps(policy_workload(args.steps, args.warmup)), flush=True)
+        return 0
+    if args.workload == "bnb":
+        print(json.dumps(bnb_leg(BNB_SEEDS, BNB_TIME_LIMIT, args.bnb_kind)), flush=True)
         return 0
     n, m, seed = 20, 20, 2000
     count = 1 << args.log2_pool
