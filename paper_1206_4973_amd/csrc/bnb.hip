@@ -110,8 +110,9 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
   const int total = K * u;  // K <= cap and u <= 255: fits 32 bits
   const int gsz = gridDim.x * blockDim.x;
   const int last_chunk = (1 + d) >> 4;  // chunk holding the new job's byte
+  __shared__ int s_cnt[kThreads / 64 + 1];
   int branched = 0, pruned = 0;
-  // iterate so that every wave of the grid takes part in each round
+  // iterate so that every thread of the grid takes part in each round
   for (int r0 = blockIdx.x * blockDim.x; r0 < total; r0 += gsz) {
     const int slot = r0 + threadIdx.x;
     const bool in = slot < total;
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
         pruned += live ? 0 : 1;
       }
     }
-    const int pos = wave_slot(live, &D->children);
+    const int pos = block_slot(live, &D->children, s_cnt);
     if (!live) continue;
     // opaque per round: otherwise the per-byte tests against d below are
     // hoisted out of the loop, one scalar register pair each
@@ -204,8 +205,8 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
       crec[1 + d] = (uint8_t)job;
     }
   }
-  wave_total(&D->nodes_branched, branched);
-  wave_total(&D->nodes_pruned, pruned);
+  block_total(&D->nodes_branched, branched, s_cnt);
+  block_total(&D->nodes_pruned, pruned, s_cnt);
 }
 
 // ---- prune + compaction ----------------------------------------------------
@@ -233,6 +234,7 @@ __global__ __launch_bounds__(kThreads) void prune_kernel(
     atomicAdd(reinterpret_cast<unsigned long long *>(&D->nodes_bounded),
               (unsigned long long)total);
   const int gsz = gridDim.x * blockDim.x;
+  __shared__ int s_cnt[kThreads / 64 + 1];
   int leaves = 0, pruned = 0;
   for (int r0 = blockIdx.x * blockDim.x; r0 < total; r0 += gsz) {
     const int i = r0 + threadIdx.x;
@@ -242,12 +244,19 @@ __global__ __launch_bounds__(kThreads) void prune_kernel(
     const bool keep = in && !leaf && keeps(rule, lb, ub);
     leaves += leaf ? 1 : 0;
     pruned += (in && !keep && !(leaf && lb < ub)) ? 1 : 0;
-    if (leaf && lb < ub) {
-      const uint64_t key = ((uint64_t)(uint32_t)lb << 32) | (uint64_t)i;
-      atomicMin(reinterpret_cast<unsigned long long *>(&D->best_key),
-                (unsigned long long)key);
+    if (d1 == n) {
+      // the wave's smallest (makespan, index) key, then one atomic per wave
+      uint64_t key = (leaf && lb < ub) ? (((uint64_t)(uint32_t)lb << 32) | (uint64_t)i)
+                                       : ~0ull;
+      for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(key, off);
+        key = o < key ? o : key;
+      }
+      if (__lane_id() == 0 && key != ~0ull)
+        atomicMin(reinterpret_cast<unsigned long long *>(&D->best_key),
+                  (unsigned long long)key);
     }
-    const int pos = wave_slot(keep, &bcount[d1]);
+    const int pos = block_slot(keep, &bcount[d1], s_cnt);
     if (!keep) continue;
     if (log_cap > 0 &&
         sample_hash(((uint64_t)D->pools << 32) ^ (uint64_t)i ^ ((uint64_t)log_seed << 16)) <
@@ -271,8 +280,8 @@ __global__ __launch_bounds__(kThreads) void prune_kernel(
     for (int q = 0; q <= (d1 >> 4); ++q) dst[q] = src[q];
     blb[at] = lb;
   }
-  wave_total(&D->leaves, leaves);
-  wave_total(&D->nodes_pruned, pruned);
+  block_total(&D->leaves, leaves, s_cnt);
+  block_total(&D->nodes_pruned, pruned, s_cnt);
 }
 
 // smallest bound among the pending nodes (for the optimality gap after a

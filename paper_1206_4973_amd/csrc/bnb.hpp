@@ -22,6 +22,46 @@ __device__ __forceinline__ int wave_slot(bool pred, int32_t *counter) {
   return base + rank;
 }
 
+// Workgroup-level compaction: this lane's slot in an array whose length
+// counter is *counter, with one atomic per workgroup.  s_cnt is an LDS array
+// of blockDim.x / 64 + 1 ints.  Every thread of the workgroup must call it
+// (it synchronises the workgroup).
+__device__ __forceinline__ int block_slot(bool pred, int32_t *counter, int *s_cnt) {
+  const uint64_t mask = __ballot(pred);
+  const int lane = __lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+  if (lane == 0) s_cnt[w] = __popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int i = 0; i < nw; ++i) {
+      const int c = s_cnt[i];
+      s_cnt[i] = tot;
+      tot += c;
+    }
+    s_cnt[nw] = tot ? atomicAdd(counter, tot) : 0;
+  }
+  __syncthreads();
+  const int slot = s_cnt[nw] + s_cnt[w] + rank;
+  __syncthreads();  // s_cnt is reused by the next call
+  return slot;
+}
+
+// Adds the workgroup's sum of v to *counter (one atomic per workgroup).
+// s_cnt as above.  Every thread of the workgroup must call it.
+__device__ __forceinline__ void block_total(int64_t *counter, int v, int *s_cnt) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (__lane_id() == 0) s_cnt[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    for (int i = 0; i < nw; ++i) tot += s_cnt[i];
+    if (tot) atomicAdd(reinterpret_cast<unsigned long long *>(counter), (unsigned long long)tot);
+  }
+  __syncthreads();
+}
+
 // Adds the wave's sum of v to *counter (one atomic per wave).  Every active
 // lane of the wave must call it.
 __device__ __forceinline__ void wave_total(int64_t *counter, int v) {

@@ -245,17 +245,18 @@ __global__ void sel_partition_kernel(BnbDesc *D, const uint8_t *__restrict__ bno
   if (!sel_needed(D)) return;
   const int count = D->sel_count, K = D->parents, T = D->sel_T, need = D->sel_need;
   const int64_t base = (int64_t)D->depth * cap;
-  // uniform rounds: every lane of a wave takes part in the wave-level slots
+  __shared__ int s_cnt[256 / 64 + 1];
+  // uniform rounds: every thread takes part in the workgroup-level slots
   for (int r0 = blockIdx.x * blockDim.x; r0 < count; r0 += gridDim.x * blockDim.x) {
     const int i = r0 + threadIdx.x;
     const bool in = i < count;
     const float e = in ? bscore[base + i] : 0.f;
     const int b = est_bin(e);
     const bool tie = in && b == T;
-    const int trank = wave_slot(tie, &D->sel_tie);
+    const int trank = block_slot(tie, &D->sel_tie, s_cnt);
     const bool take = in && (b < T || (tie && trank < need));
-    const int hi = wave_slot(take, &D->sel_hi);
-    const int lo = wave_slot(in && !take, &D->sel_lo);
+    const int hi = block_slot(take, &D->sel_hi, s_cnt);
+    const int lo = block_slot(in && !take, &D->sel_lo, s_cnt);
     if (!in) continue;
     const int pos = take ? count - K + hi : lo;
     const uint4 *src = reinterpret_cast<const uint4 *>(bnodes + (base + i) * stride);
