@@ -93,8 +93,8 @@ int fsp_instance_info(const fsp_instance *inst, int32_t *n, int32_t *m,
  *                        by scalar loads;
  *   FSP_PATH_REGISTER64  32 < n <= 64: one node per lane, the unscheduled set
  *                        in a 64-bit register pair.
- * The batch kernel uses the register form for n <= 32 and the mask form
- * above. */
+ * The batch kernel uses the one-node-per-lane forms (register, register64,
+ * masks). */
 enum { FSP_PATH_REGISTER = 0, FSP_PATH_PACKED = 1, FSP_PATH_MASKS = 2,
        FSP_PATH_REGISTER64 = 3 };
 int fsp_instance_path(const fsp_instance *inst, int32_t *path);
@@ -118,6 +118,13 @@ typedef struct {
  * independently; Sec. V.D bound).  lb_out is a device int32[count].  Malformed
  * records get FSP_LB_INVALID.  count == 0 queues nothing.  Asynchronous on
  * `stream`.
+ * For n > 64 the walk needs device scratch (about n/8 + 1 bytes per node):
+ * the library keeps one workspace per (device, stream), and a call that needs
+ * more than the stream's workspace holds first synchronizes the stream, then
+ * replaces it (so such a call cannot be captured in a graph; a smaller or
+ * equal pool on the same stream can).  Calls on one stream are ordered, so
+ * they share the workspace safely; the workspace lives until the process
+ * ends.
  */
 int fsp_bound_pool(const fsp_nodes *nodes, int64_t count, int32_t *lb_out,
                    void *stream);

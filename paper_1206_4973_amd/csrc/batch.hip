@@ -116,7 +116,7 @@ int variant_of(const fsp_instance *inst, const InstView &v) {
     default: return VNONE;
   }
   if (!inst->wide) return base;
-  if (inst->n <= 64) return base + 3;
+  if (!uses_job_masks(inst->n)) return base + 3;
   return v.nchunks > 1 ? base + 2 : base + 1;
 }
 

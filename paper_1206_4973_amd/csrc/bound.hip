@@ -174,7 +174,7 @@ InstView inst_view(const fsp_instance *inst, size_t table_budget) {
   v.tot = inst->d_tot;
   v.rec = inst->d_rec;
   v.joff = inst->d_joff;
-  v.slot_bytes = inst->wide ? mask_slot_bytes(inst->n) : 0;
+  v.slot_bytes = uses_job_masks(inst->n) ? mask_slot_bytes(inst->n) : 0;
   v.n = inst->n;
   v.mp = inst->mp;
   v.npad = inst->npad;
@@ -257,7 +257,7 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
                   : 0;
   a.lb = lb_out;
   // n > 32: the 64-bit register form up to 64 jobs, job masks above
-  const int form = !wide ? kFormReg32 : (inst->n <= 64 ? kFormReg64 : kFormMasks);
+  const int form = !wide ? kFormReg32 : (uses_job_masks(inst->n) ? kFormMasks : kFormReg64);
   a.I = inst_view(inst, wide ? kTableBudgetWide : kTableBudgetNarrow);
   BoundFn fn;
   if (p16) {

@@ -34,7 +34,7 @@ constexpr int kLogBlock = 8;
 // offset 8 * n.
 using Rec = int2;
 
-// Bytes of one wave's job-mask slot in the bounding scratch (n > 32): one
+// Bytes of one wave's job-mask slot in the bounding scratch (n > 64): one
 // 64-bit lane mask per job id 0..n (n = the padding id), rounded up to 256
 // bytes so that no two slots share a cache line.
 inline int mask_slot_bytes(int n) { return ((n + 1) * 8 + 255) / 256 * 256; }
@@ -75,10 +75,11 @@ struct fsp_instance {
 
 namespace fspi {
 // Device scratch that one bounding launch of `count` nodes of an n-job
-// instance needs: for n > 32, one mask slot per wave of every tile; none for
-// n <= 32 (the job set of a node is a register there).
+// instance needs: for n > 64 (the job-mask walk), one mask slot per wave of
+// every tile; none up to 64 jobs (the job set of a node is a register there).
+inline bool uses_job_masks(int n) { return n > 64; }
 inline size_t bound_scratch_bytes(int n, int64_t count) {
-  if (n <= 32) return 0;
+  if (!uses_job_masks(n)) return 0;
   const int64_t tiles = (count + kBlock - 1) / kBlock;
   return (size_t)tiles * (kBlock / 64) * (size_t)mask_slot_bytes(n);
 }

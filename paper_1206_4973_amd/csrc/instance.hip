@@ -255,7 +255,7 @@ int fsp_instance_info(const fsp_instance *inst, int32_t *n, int32_t *m,
 int fsp_instance_path(const fsp_instance *inst, int32_t *path) {
   if (!inst || !path) return FSP_EINVAL;
   if (inst->wide)
-    *path = inst->n <= 64 ? FSP_PATH_REGISTER64 : FSP_PATH_MASKS;
+    *path = uses_job_masks(inst->n) ? FSP_PATH_MASKS : FSP_PATH_REGISTER64;
   else
     *path = inst->p16 ? FSP_PATH_PACKED : FSP_PATH_REGISTER;
   return FSP_OK;

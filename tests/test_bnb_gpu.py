@@ -152,7 +152,9 @@ def test_graphed_kinds_reach_the_optimum(fsp, orc, kind):
 
 
 def test_autotuner_picks_a_candidate_and_caches_it(fsp):
-    inst = fsp.Instance(I.instance(20, 10, 4046))
+    # a shape no other test tunes: the pick is cached per (device, n, m) for
+    # the process, and this short budget must not decide other tests' pools
+    inst = fsp.Instance(I.instance(20, 12, 4046))
     pool, rate = fsp.autotune_pool(inst, 0.8)
     say("autotuned pool", pool, "rate", rate)
     assert pool >= 1 << 14 and (pool & (pool - 1)) == 0 and rate > 0

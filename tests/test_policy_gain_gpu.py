@@ -51,6 +51,10 @@ def test_learned_ordering_beats_plain_adaptive(fsp, orc):
     for s in SEEDS:
         p = I.instance(20, 10, s)
         inst = fsp.Instance(p)
+        # the learned kind takes the pool size the autotuner picks for the
+        # shape with its default budget (cached; tuned on the first seed)
+        pool, _ = fsp.autotune_pool(inst)
+        say(f"autotuned pool for 20x10: {pool}")
         row = {}
         for kind in ("adaptive", "learned"):
             kw = {"model": model} if kind == "learned" else {}
