@@ -210,3 +210,24 @@ def test_packed_path_limits(fsp, orc, n, m, total, big):
     got = gpu_bounds(fsp, inst, pool)
     want = orc.bound_pool(p, pool, nthreads=8)
     assert np.array_equal(got, want)
+
+
+def test_concurrent_streams_with_job_mask_scratch(fsp, orc):
+    """Instances above 64 jobs bound with per-wave mask scratch that the
+    library keeps per stream: two streams bounding different pools at the same
+    time, then a larger pool on the first stream (its workspace grows), must
+    all match the oracle."""
+    p = I.instance(100, 5, 7101)
+    inst = fsp.Instance(p)
+    assert inst.bound_path == "masks"
+    pools = [I.random_pool(100, c, 0, 100, 7200 + c) for c in (3000, 2500, 9000)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    dev = [torch.from_numpy(np.ascontiguousarray(q)).cuda() for q in pools]
+    torch.cuda.synchronize()
+    say("two streams, 100x5, pools of 3000 and 2500 nodes, then 9000")
+    out1 = inst.bound_pool(dev[0], stream=s1)
+    out2 = inst.bound_pool(dev[1], stream=s2)
+    out3 = inst.bound_pool(dev[2], stream=s1)
+    torch.cuda.synchronize()
+    for q, o in zip(pools, (out1, out2, out3)):
+        assert np.array_equal(o.cpu().numpy(), orc.bound_pool(p, q, nthreads=8))
