@@ -43,7 +43,7 @@ extern "C" {
 #define FSP_EINVAL (-1)       /* bad argument (null pointer, size, range)   */
 #define FSP_ENOMEM (-2)       /* device or host allocation failed           */
 #define FSP_EDEVICE (-3)      /* a HIP call failed                          */
-#define FSP_EUNSUPPORTED (-4) /* valid input outside what this build serves */
+#define FSP_EUNSUPPORTED (-4) /* valid input outside what this library serves */
 
 /* Bound written for a malformed node: depth > n, a job id >= n, or a job
  * scheduled twice. */
@@ -64,7 +64,7 @@ typedef struct fsp_instance fsp_instance;
  *            free it on return.
  *   n      : 1 <= n <= 255 jobs (a job id is one byte).
  *   m      : 2 <= m <= 20 machines (a pair needs two machines; 20 is the
- *            largest machine count this build instantiates: FSP_EUNSUPPORTED
+ *            largest machine count this library instantiates: FSP_EUNSUPPORTED
  *            above it).
  *   out    : receives the handle; release it with fsp_free_instance.
  * Limits (FSP_EUNSUPPORTED otherwise): every p[j][k] in [0, 32767], every

@@ -187,7 +187,7 @@ const char *fsp_status_string(int32_t status) {
     case FSP_EINVAL: return "invalid argument";
     case FSP_ENOMEM: return "out of memory";
     case FSP_EDEVICE: return "HIP device error";
-    case FSP_EUNSUPPORTED: return "unsupported input for this build";
+    case FSP_EUNSUPPORTED: return "unsupported input for this library";
     default: return "unknown status";
   }
 }
