@@ -220,6 +220,54 @@ int64_t orc_lower_bound(const int32_t *p, int n, int m, const uint8_t *node) {
 }
 
 /* ------------------------------------------------------------------ */
+/* One-machine bound of a node (Sec. VI names other lower bounds as    */
+/* future work; this is the classic cheaper one): on each machine h,    */
+/* every                                                                */
+/* unscheduled job passes h no earlier than the head of h, one after   */
+/* the other, and whichever passes last still has the smallest tail of  */
+/* h ahead of it.  Bound = max over h of head + remaining work + tail;  */
+/* the makespan for a complete node; ORC_INVALID for a malformed one.   */
+/* ------------------------------------------------------------------ */
+int64_t orc_lower_bound_one_machine(const int32_t *p, int n, int m,
+                                    const uint8_t *node) {
+  const int depth = node[0];
+  if (depth > n) return ORC_INVALID;
+  uint8_t seen[256];
+  memset(seen, 0, sizeof(seen));
+  for (int i = 1; i <= depth; ++i) {
+    const int job = node[i];
+    if (job >= n || seen[job]) return ORC_INVALID;
+    seen[job] = 1;
+  }
+  int64_t front[256];
+  front_of(p, n, m, node + 1, depth, front);
+  if (depth == n) return front[m - 1];
+  int64_t best = 0;
+  for (int h = 0; h < m; ++h) {
+    int64_t work = 0, min_before = -1, min_after = -1;
+    for (int job = 0; job < n; ++job) {
+      if (seen[job]) continue;
+      int64_t before = 0, after = 0;
+      for (int g = 0; g < m; ++g) {
+        if (g < h) before += p[job * m + g];
+        if (g > h) after += p[job * m + g];
+      }
+      work += p[job * m + h];
+      if (min_before < 0 || before < min_before) min_before = before;
+      if (min_after < 0 || after < min_after) min_after = after;
+    }
+    /* head of h: machine h is free at front[h]; the first unscheduled job
+     * leaves machine 0 no earlier than front[0] and then needs its work
+     * on machines 0..h-1 */
+    int64_t head = front[0] + min_before;
+    if (front[h] > head) head = front[h];
+    const int64_t v = head + work + min_after;
+    if (v > best) best = v;
+  }
+  return best;
+}
+
+/* ------------------------------------------------------------------ */
 /* Bounding a pool (Sec. III: every sub-problem of the pool is bounded  */
 /* independently).  Records are `stride` bytes: [d, s_1..s_d, ...].     */
 /* nthreads > 1 splits the pool into equal contiguous parts.            */
@@ -230,18 +278,38 @@ typedef struct {
   const uint8_t *nodes;
   int64_t begin, end;
   int32_t *out;
+  int one_machine; /* 1: the one-machine bound instead of the pair bound */
 } pool_job;
 
 static void *pool_worker(void *arg) {
   pool_job *w = (pool_job *)arg;
-  for (int64_t i = w->begin; i < w->end; ++i)
-    w->out[i] = (int32_t)orc_lower_bound(w->p, w->n, w->m,
-                                         w->nodes + i * (int64_t)w->stride);
+  for (int64_t i = w->begin; i < w->end; ++i) {
+    const uint8_t *rec = w->nodes + i * (int64_t)w->stride;
+    w->out[i] = (int32_t)(w->one_machine
+                              ? orc_lower_bound_one_machine(w->p, w->n, w->m, rec)
+                              : orc_lower_bound(w->p, w->n, w->m, rec));
+  }
   return NULL;
 }
 
+static void bound_pool_with(const int32_t *p, int n, int m, const uint8_t *nodes,
+                            int stride, int64_t count, int32_t *lb_out, int nthreads,
+                            int one_machine);
+
 void orc_bound_pool(const int32_t *p, int n, int m, const uint8_t *nodes,
                     int stride, int64_t count, int32_t *lb_out, int nthreads) {
+  bound_pool_with(p, n, m, nodes, stride, count, lb_out, nthreads, 0);
+}
+
+void orc_bound_pool_one_machine(const int32_t *p, int n, int m, const uint8_t *nodes,
+                                int stride, int64_t count, int32_t *lb_out,
+                                int nthreads) {
+  bound_pool_with(p, n, m, nodes, stride, count, lb_out, nthreads, 1);
+}
+
+static void bound_pool_with(const int32_t *p, int n, int m, const uint8_t *nodes,
+                            int stride, int64_t count, int32_t *lb_out, int nthreads,
+                            int one_machine) {
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
   pool_job jobs[256];
@@ -252,7 +320,7 @@ void orc_bound_pool(const int32_t *p, int n, int m, const uint8_t *nodes,
     int64_t b = t * per, e = b + per;
     if (e > count) e = count;
     if (b >= e) break;
-    jobs[t] = (pool_job){p, n, m, stride, nodes, b, e, lb_out};
+    jobs[t] = (pool_job){p, n, m, stride, nodes, b, e, lb_out, one_machine};
     if (nthreads == 1) {
       pool_worker(&jobs[t]);
     } else {

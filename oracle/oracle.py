@@ -81,6 +81,11 @@ def _load(path: str | None = None):
     lib.orc_bound_pool.argtypes = [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, i64,
                                    P, ctypes.c_int]
     lib.orc_bound_pool.restype = None
+    lib.orc_lower_bound_one_machine.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
+    lib.orc_lower_bound_one_machine.restype = i64
+    lib.orc_bound_pool_one_machine.argtypes = [P, ctypes.c_int, ctypes.c_int, P,
+                                               ctypes.c_int, i64, P, ctypes.c_int]
+    lib.orc_bound_pool_one_machine.restype = None
     lib.orc_neh.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
     lib.orc_neh.restype = i64
     lib.orc_brute_force.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
@@ -168,6 +173,25 @@ def bound_pool(p, nodes, nthreads: int = 1):
     out = np.zeros(count, dtype=np.int32)
     _load().orc_bound_pool(_ptr(p), n, m, _ptr(nodes), stride, count, _ptr(out),
                            int(nthreads))
+    return out
+
+
+def lower_bound_one_machine(p, prefix):
+    """One-machine bound of the node whose scheduled prefix is ``prefix``:
+    max over machines of head + remaining work + smallest tail."""
+    p, n, m = _p(p)
+    rec = _node(prefix, n)
+    return int(_load().orc_lower_bound_one_machine(_ptr(p), n, m, _ptr(rec)))
+
+
+def bound_pool_one_machine(p, nodes, nthreads: int = 1):
+    """One-machine bounds of every record of a ``uint8[count, stride]`` pool."""
+    p, n, m = _p(p)
+    nodes = np.ascontiguousarray(nodes, dtype=np.uint8)
+    count, stride = nodes.shape
+    out = np.zeros(count, dtype=np.int32)
+    _load().orc_bound_pool_one_machine(_ptr(p), n, m, _ptr(nodes), stride, count,
+                                       _ptr(out), int(nthreads))
     return out
 
 

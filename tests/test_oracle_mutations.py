@@ -34,6 +34,13 @@ MUTATIONS = [
     ("prune_rule_inverted", "return rule == 1 ? (lb <= ub) : (lb < ub);", "return rule == 1 ? (lb < ub) : (lb <= ub);"),
     ("leaf_accepts_ties", "if (clb < ub) {\n          ub = clb;", "if (clb <= ub) {\n          ub = clb;"),
     ("duplicate_ids_accepted", "if (j >= n || used[j]) return ORC_INVALID;", "if (j >= n) return ORC_INVALID;"),
+    ("one_machine_tail_dropped", "const int64_t v = head + work + min_after;",
+     "const int64_t v = head + work;"),
+    ("one_machine_head_ignores_front", "if (front[h] > head) head = front[h];", ""),
+    ("one_machine_head_includes_machine_h", "if (g < h) before += p[job * m + g];",
+     "if (g <= h) before += p[job * m + g];"),
+    ("one_machine_largest_tail", "if (min_after < 0 || after < min_after) min_after = after;",
+     "if (min_after < 0 || after > min_after) min_after = after;"),
 ]
 
 PINS = [
@@ -48,6 +55,10 @@ PINS = [
     pins.test_pair_values_equal_relaxation_optimum,
     pins.test_malformed_nodes_bound_to_minus_one,
     pins.test_bnb_tiny_config_nine_jobs_five_machines,
+    pins.test_one_machine_bound_never_exceeds_the_pair_bound,
+    pins.test_one_machine_bound_never_exceeds_any_completion,
+    pins.test_one_machine_bound_exact_with_zero_or_one_job_left,
+    pins.test_one_machine_bound_identical_jobs_closed_form,
 ]
 
 

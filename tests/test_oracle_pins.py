@@ -352,3 +352,56 @@ def test_pool_bounding_matches_single_node_calls(orc):
     for i in range(0, 300, 7):
         d = int(pool[i, 0])
         assert lb1[i] == orc.lower_bound(p, pool[i, 1:1 + d].tolist())
+
+
+# ----------------------------------------------------------------------------
+# One-machine bound (the cheaper bound used as a pre-filter)
+# ----------------------------------------------------------------------------
+def test_one_machine_bound_never_exceeds_the_pair_bound(orc):
+    """For l >= 1, machine l's one-machine value is at most the completion on l
+    of any pair (k, l) relaxation (which starts l at its head and then runs
+    every unscheduled job on l) plus the tail; for l = 0 a pair (0, l) ends
+    with a job whose work after machine 0 is at least q[0]."""
+    rng = np.random.default_rng(40)
+    for _ in range(400):
+        n, m = int(rng.integers(1, 12)), int(rng.integers(2, 9))
+        p = rng.integers(0, 60, size=(n, m)).astype(np.int32)
+        pre = random_prefix(rng, n, int(rng.integers(0, n + 1)))
+        assert orc.lower_bound_one_machine(p, pre) <= orc.lower_bound(p, pre)
+
+
+def test_one_machine_bound_never_exceeds_any_completion(orc):
+    rng = np.random.default_rng(41)
+    for _ in range(150):
+        n, m = int(rng.integers(1, 7)), int(rng.integers(2, 7))
+        p = rng.integers(0, 40, size=(n, m)).astype(np.int32)
+        pre = random_prefix(rng, n, int(rng.integers(0, n + 1)))
+        assert orc.lower_bound_one_machine(p, pre) <= orc.best_completion(p, pre)
+
+
+def test_one_machine_bound_exact_with_zero_or_one_job_left(orc):
+    """With one job j left the schedule is fixed, and its makespan is the
+    heaviest lattice path: it enters the last column at some machine h after
+    the prefix reaches h, i.e. max over h of F[h] + work of j on h..m-1, which
+    is what the one-machine value of h gives (plus the F[0] + all of j
+    term)."""
+    rng = np.random.default_rng(42)
+    for _ in range(100):
+        n, m = int(rng.integers(1, 7)), int(rng.integers(2, 7))
+        p = rng.integers(0, 50, size=(n, m)).astype(np.int32)
+        perm = [int(x) for x in rng.permutation(n)]
+        want = lattice_makespan(p, perm)
+        assert orc.lower_bound_one_machine(p, perm) == want
+        assert orc.lower_bound_one_machine(p, perm[:-1]) == want
+
+
+def test_one_machine_bound_identical_jobs_closed_form(orc):
+    """Identical jobs with times c: the root value of machine h is
+    sum_{g<h} c_g + n c_h + sum_{g>h} c_g, whose max over h is the makespan
+    sum(c) + (n-1) max(c)."""
+    rng = np.random.default_rng(43)
+    for _ in range(30):
+        n, m = int(rng.integers(1, 9)), int(rng.integers(2, 8))
+        c = rng.integers(0, 50, size=m).astype(np.int32)
+        p = np.tile(c, (n, 1)).astype(np.int32)
+        assert orc.lower_bound_one_machine(p, []) == int(c.sum()) + (n - 1) * int(c.max())
