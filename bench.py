@@ -99,7 +99,7 @@ def geomean(xs):
     return float(np.exp(np.mean(np.log(xs)))) if xs else None
 
 
-def bnb_leg(seeds, time_limit, only=None) -> dict:
+def bnb_leg(seeds, time_limit, only=None, prefilter=False) -> dict:
     """Time to a proven optimum, plain adaptive (the paper's Algorithm 1,
     launch by launch) vs batched (graph-replayed iterations, autotuned pool)
     vs batched + learned ordering, on held-out instances.  `only` restricts
@@ -118,7 +118,8 @@ def bnb_leg(seeds, time_limit, only=None) -> dict:
         row = {"seed": s}
         for kind in kinds:
             kw = {"model": model} if kind == "learned" else {}
-            r = fsp.branch_and_bound(inst, kind, time_limit=time_limit, **kw)
+            r = fsp.branch_and_bound(inst, kind, time_limit=time_limit,
+                                     prefilter=prefilter, **kw)
             progress(f"bnb seed {s} {kind}: {r.makespan} in {r.t_total_s:.3f} s")
             row[kind] = {"makespan": r.makespan, "proven": r.status == 0,
                          "t_proof_s": r.t_total_s, "t_found_s": r.t_found_s,
@@ -126,7 +127,7 @@ def bnb_leg(seeds, time_limit, only=None) -> dict:
         inst.close()
         rows.append(row)
     out = {"instances": "20x10, seeds " + ",".join(str(s) for s in seeds),
-           "time_limit_s": time_limit, "kinds": kinds}
+           "time_limit_s": time_limit, "kinds": kinds, "one_machine_prefilter": prefilter}
     all_proven = all(r[k]["proven"] for r in rows for k in kinds)
     same_opt = all(len({r[k]["makespan"] for k in kinds}) == 1 for r in rows)
     out["all_proven"] = all_proven
@@ -198,14 +199,15 @@ def batch_workload(steps, warmup) -> dict:
             "identical_bounds": bool(same), "peak_TOPs": INT32_PEAK_TOPS}
 
 
-def large_workload(steps, warmup, bnb_time) -> dict:
+def large_workload(steps, warmup, bnb_time, prefilter=False) -> dict:
     """50x20 (seed 5000) and 200x20 (seed 5001): pools of 2^22 nodes (depth
     uniform 1..n-1), then time-limited searches (plain adaptive, batched,
     batched + learned when a 20-machine policy is present) reporting the best
     UB, the smallest pending bound, the gap and nodes per second."""
     import torch
     from paper_1206_4973_amd import fsp, inputs, train_policy
-    out = {"workload": "large: 50x20 and 200x20", "bnb_time_limit_s": bnb_time}
+    out = {"workload": "large: 50x20 and 200x20", "bnb_time_limit_s": bnb_time,
+           "one_machine_prefilter": prefilter}
     model_path = os.path.join(ROOT, "paper_1206_4973_amd", "policy_m20.npz")
     model = train_policy.load(model_path) if os.path.exists(model_path) else None
     stream = torch.cuda.current_stream()
@@ -225,7 +227,8 @@ def large_workload(steps, warmup, bnb_time) -> dict:
         kinds = ["adaptive", "autotuned"] + (["learned"] if model is not None else [])
         for kind in kinds:
             kw = {"model": model} if kind == "learned" else {}
-            r = fsp.branch_and_bound(inst, kind, time_limit=bnb_time, **kw)
+            r = fsp.branch_and_bound(inst, kind, time_limit=bnb_time, prefilter=prefilter,
+                                     **kw)
             progress(f"large {n}x{m} {kind}: UB {r.makespan}, open bound {r.open_lb}, "
                      f"{r.nodes_bounded} nodes in {r.t_total_s:.1f} s")
             rec[kind] = {"best_ub": r.makespan, "open_lb": r.open_lb,
@@ -280,6 +283,8 @@ def main() -> int:
     ap.add_argument("--no-bnb", action="store_true", help="skip the B&B time-to-optimum leg")
     ap.add_argument("--bnb-kind", default=None, choices=["adaptive", "autotuned", "learned"],
                     help="with --workload bnb: run only this kind")
+    ap.add_argument("--prefilter", action="store_true",
+                    help="with --workload bnb or large: one-machine pre-filter in every search")
     ap.add_argument("--workload", default="pool",
                     choices=["pool", "batch", "large", "policy", "bnb"],
                     help="pool: the 20x20 line (default); batch: 64 mixed instances in one "
@@ -314,13 +319,15 @@ def main() -> int:
         print(json.dumps(batch_workload(args.steps, args.warmup)), flush=True)
         return 0
     if args.workload == "large":
-        print(json.dumps(large_workload(args.steps, args.warmup, args.bnb_time)), flush=True)
+        print(json.dumps(large_workload(args.steps, args.warmup, args.bnb_time, args.prefilter)),
+              flush=True)
         return 0
     if args.workload == "policy":
         print(json.dumps(policy_workload(args.steps, args.warmup)), flush=True)
         return 0
     if args.workload == "bnb":
-        print(json.dumps(bnb_leg(BNB_SEEDS, BNB_TIME_LIMIT, args.bnb_kind)), flush=True)
+        print(json.dumps(bnb_leg(BNB_SEEDS, BNB_TIME_LIMIT, args.bnb_kind, args.prefilter)),
+              flush=True)
         return 0
     n, m, seed = 20, 20, 2000
     count = 1 << args.log2_pool

@@ -129,6 +129,18 @@ typedef struct {
 int fsp_bound_pool(const fsp_nodes *nodes, int64_t count, int32_t *lb_out,
                    void *stream);
 
+/*
+ * fsp_bound_pool_one_machine -- lb_out[i] = the one-machine bound of record
+ * i: the largest over machines k of head r[k] + remaining work of the
+ * unscheduled jobs on k + their smallest tail after k (heads and tails as for
+ * the pair bound; Sec. VI names other bounds as future work).  Never larger
+ * than fsp_bound_pool's bound; the makespan for a complete record;
+ * FSP_LB_INVALID for a malformed one.  Same arguments and behaviour as
+ * fsp_bound_pool.
+ */
+int fsp_bound_pool_one_machine(const fsp_nodes *nodes, int64_t count,
+                               int32_t *lb_out, void *stream);
+
 /* ---- batched bounding: many instances in one launch ------------------- */
 
 /* One pool of one instance.  data/lb_out: device pointers as in
@@ -211,7 +223,10 @@ typedef struct {
                              n * (max_pool + n) * stride bytes of HBM.     */
   double time_limit_s;    /* stop after this wall time; <= 0: no limit     */
   int32_t prune_rule;     /* FSP_PRUNE_GE or FSP_PRUNE_GT                  */
-  int32_t reserved;
+  int32_t prefilter;      /* 1: one-machine pre-filter in every bounding
+                             launch (a wave whose nodes that bound already
+                             eliminates skips the pair walks; same
+                             eliminations, same optimum); 0: none          */
   const void *model;      /* FSP_POOL_LEARNED: the policy network          */
   const char *log_path;   /* one JSON line per batch of pools; NULL: none  */
 } fsp_pool_policy;

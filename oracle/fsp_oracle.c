@@ -222,11 +222,11 @@ int64_t orc_lower_bound(const int32_t *p, int n, int m, const uint8_t *node) {
 /* ------------------------------------------------------------------ */
 /* One-machine bound of a node (Sec. VI names other lower bounds as    */
 /* future work; this is the classic cheaper one): on each machine h,    */
-/* every                                                                */
-/* unscheduled job passes h no earlier than the head of h, one after   */
-/* the other, and whichever passes last still has the smallest tail of  */
-/* h ahead of it.  Bound = max over h of head + remaining work + tail;  */
-/* the makespan for a complete node; ORC_INVALID for a malformed one.   */
+/* every unscheduled job passes h no earlier than the head of h, one    */
+/* after the other, and whichever passes last still has the smallest    */
+/* tail of h ahead of it.  Bound = max over h of head + remaining work  */
+/* + tail; the makespan for a complete node; ORC_INVALID for a          */
+/* malformed one.                                                       */
 /* ------------------------------------------------------------------ */
 int64_t orc_lower_bound_one_machine(const int32_t *p, int n, int m,
                                     const uint8_t *node) {

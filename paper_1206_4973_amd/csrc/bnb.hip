@@ -479,7 +479,12 @@ int BnbState::enqueue_iteration(hipStream_t s) {
   hipLaunchKernelGGL(branch_kernel, dim3(grid), dim3(kThreads), 0, s, desc,
                      bnodes, blb, pool, n, stride, cap, rule);
   FSP_HIP_TRY(hipGetLastError());
-  rc = launch_bound(inst, pool, stride, cap, pool_lb, s, &desc->children, slots);
+  Prefilter pf;
+  if (prefilter) {
+    pf.ub = &desc->ub;  // constant from this iteration's plan to the next
+    pf.rule = rule;
+  }
+  rc = launch_bound(inst, pool, stride, cap, pool_lb, s, &desc->children, slots, pf);
   if (rc != FSP_OK) return rc;
   hipLaunchKernelGGL(prune_kernel, dim3(grid), dim3(kThreads), 0, s, desc,
                      pool, pool_lb, bnodes, blb, bcount, n, stride, cap, rule, log_cap,
@@ -688,6 +693,7 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
 
   BnbState S;
   int rc = S.init(inst, max_pool, policy->prune_rule);
+  S.prefilter = policy->prefilter == 1 ? 1 : 0;
   if (rc == FSP_OK && model) rc = S.init_model(model, 1.0f / (float)neh);
   if (rc == FSP_OK && samples) rc = S.init_log(samples->cap, samples->prob, samples->seed);
   if (rc == FSP_OK) rc = S.start(ub0, perm0);

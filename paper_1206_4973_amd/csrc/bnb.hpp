@@ -97,6 +97,7 @@ struct BnbDesc {
 struct BnbState {
   const fsp_instance *inst = nullptr;
   int n = 0, stride = 0, rule = 0, cus = 0;
+  int prefilter = 0;  // one-machine pre-filter in the bounding launches
   int64_t cap = 0;  // records per bucket and in the pool buffer
   uint8_t *bnodes = nullptr;   // [n][cap][stride]
   int32_t *blb = nullptr;      // [n][cap]

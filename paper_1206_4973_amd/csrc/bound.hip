@@ -68,7 +68,8 @@ struct BoundParams {
   int stride;
   int aligned;  // records 16-byte aligned: load them as uint4
   int32_t *lb;
-  char *slots;  // bound_scratch_bytes(n, count) bytes of job-mask slots (n > 32)
+  char *slots;  // bound_scratch_bytes(n, count) bytes of job-mask slots (n > 64)
+  Prefilter pf;
 };
 
 template <int M, int FORM, bool CHUNKED>
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(kBlock, 4) void bound_kernel(const BoundParams a) {
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
     bound_nodes<M, FORM, CHUNKED>(a.I, L, a.nodes, a.stride, a.aligned != 0,
                                   tile * kBlock, count, a.lb,
-                                  a.slots + (size_t)tile * tile_bytes);
+                                  a.slots + (size_t)tile * tile_bytes, a.pf);
 }
 
 // Two nodes per lane in packed 16-bit arithmetic (n <= 32, total work <=
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(kBlock, 3) void bound_kernel_p16(const BoundParams 
   __syncthreads();
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
     bound_nodes_p16<M>(a.I, L, a.nodes, a.stride, a.aligned != 0,
-                       tile * 2 * kBlock, count, a.lb);
+                       tile * 2 * kBlock, count, a.lb, a.pf);
 }
 
 using BoundFn = void (*)(BoundParams);
@@ -234,7 +235,7 @@ int stream_scratch(hipStream_t stream, size_t bytes, void **out) {
 
 int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
                  int64_t count, int32_t *lb_out, hipStream_t stream,
-                 const int32_t *count_dev, void *scratch) {
+                 const int32_t *count_dev, void *scratch, const Prefilter &pf) {
   if (count == 0) return FSP_OK;
   const bool wide = inst->wide != 0;
   const size_t need = bound_scratch_bytes(inst->n, count);
@@ -245,6 +246,7 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
   const bool p16 = inst->p16 != 0;
   const int64_t tile_nodes = p16 ? 2 * kBlock : kBlock;
   BoundParams a{};
+  a.pf = pf;
   a.slots = static_cast<char *>(scratch);
   a.nodes = nodes;
   a.count = count;
@@ -308,6 +310,19 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
 }
 
 }  // namespace fspi
+
+extern "C" int fsp_bound_pool_one_machine(const fsp_nodes *nodes, int64_t count,
+                                          int32_t *lb_out, void *stream) {
+  if (!nodes || !nodes->inst || count < 0) return FSP_EINVAL;
+  if (count == 0) return FSP_OK;
+  if (!nodes->data || !lb_out) return FSP_EINVAL;
+  if (nodes->stride < nodes->inst->n + 1) return FSP_EINVAL;
+  Prefilter pf;
+  pf.lb1_only = 1;
+  return fspi::launch_bound(nodes->inst, nodes->data, nodes->stride, count,
+                            lb_out, reinterpret_cast<hipStream_t>(stream),
+                            nullptr, nullptr, pf);
+}
 
 extern "C" int fsp_bound_pool(const fsp_nodes *nodes, int64_t count,
                               int32_t *lb_out, void *stream) {

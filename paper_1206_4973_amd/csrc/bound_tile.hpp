@@ -483,6 +483,11 @@ __device__ __forceinline__ void node_state(const InstView I, const int32_t *s_p,
   last = F[M - 1];
 }
 
+// Whether a node with bound lb is eliminated against ub (the B&B's rule).
+__device__ __forceinline__ bool eliminated(int lb, int ub, int rule) {
+  return rule == FSP_PRUNE_GT ? lb > ub : lb >= ub;
+}
+
 // Bound the 256 nodes [base, base + 256) of a pool (one per lane), writing
 // lb_out[idx] for idx < count.  For n > 32, tile_slots is this tile's part of
 // the mask scratch: kBlock / 64 slots of I.slot_bytes, never used by another
@@ -493,7 +498,8 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
                                             const uint8_t *nodes, int stride,
                                             bool aligned, int64_t base,
                                             int64_t count, int32_t *lb_out,
-                                            char *tile_slots) {
+                                            char *tile_slots,
+                                            const Prefilter pf = Prefilter()) {
   constexpr bool WIDE = FORM == kFormMasks;
   const int tid = threadIdx.x;
   const int n = I.n, mp = I.mp, npad = I.npad;
@@ -518,6 +524,20 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   else
     u_left = __builtin_popcount(U);
 
+  // one-machine bound max_k r[k] + S[k] + q[k] (T and Q carry r + S and q);
+  // the wave skips the pair walks when it decides every live node
+  bool skip = false;
+  int lb1 = 0;
+  if (pf.lb1_only || pf.ub) {
+    int m1 = 0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) m1 = max(m1, T256[k] + Q256[k]);
+    lb1 = m1 >> 8;
+    bool decided = !live || bad || u_left == 0;
+    if (!pf.lb1_only) decided = decided || eliminated(lb1, *pf.ub, pf.rule);
+    skip = pf.lb1_only || __ballot(!decided) == 0;
+  }
+
   // ---- 3. (n > 32) the wave's job masks, then every machine pair.  The
   //         slot is written with vector stores and read back with scalar
   //         loads.  The vector L1 writes through, so once the wave's stores
@@ -526,7 +546,7 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   //         cache starts every dispatch invalidated), so no scalar cache line
   //         can hold an older copy of it. ----
   kchar *ms = nullptr, *jt = nullptr;
-  if constexpr (WIDE) {
+  if constexpr (WIDE) if (!skip) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     uint64_t *slot = reinterpret_cast<uint64_t *>(
         tile_slots + (size_t)wave * (size_t)I.slot_bytes);
@@ -544,8 +564,9 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
 #pragma unroll
     for (int k = 0; k < M; ++k)
       asm volatile("" : "+v"(R256[k]), "+v"(T256[k]), "+v"(Q256[k]));
-    LB256 = pair_sweep<M, FORM>(s_rec, jt, 0, M * (M - 1) / 2, npad, U, ms,
-                                R256, T256, Q256, LB256);
+    if (!skip)
+      LB256 = pair_sweep<M, FORM>(s_rec, jt, 0, M * (M - 1) / 2, npad, U, ms,
+                                  R256, T256, Q256, LB256);
   } else {
     for (int chunk = 0; chunk < I.nchunks; ++chunk) {
       __syncthreads();
@@ -558,13 +579,15 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
         asm volatile("" : "+v"(R256[k]), "+v"(T256[k]), "+v"(Q256[k]));
       int lo = chunk * I.ppc, hi = lo + I.ppc;
       asm volatile("" : "+s"(lo), "+s"(hi));
-      LB256 = pair_sweep<M, FORM>(s_rec, jt + (size_t)lo * npad * 4, lo, hi,
-                                  npad, U, ms, R256, T256, Q256, LB256);
+      // the barriers above are kept when the wave skips its walks
+      if (!skip)
+        LB256 = pair_sweep<M, FORM>(s_rec, jt + (size_t)lo * npad * 4, lo, hi,
+                                    npad, U, ms, R256, T256, Q256, LB256);
     }
   }
 
   // ---- 4. result ----
-  int lb = u_left == 0 ? last : (LB256 >> 8);
+  int lb = u_left == 0 ? last : (skip ? lb1 : (LB256 >> 8));
   if (bad) lb = FSP_LB_INVALID;
   if (live) lb_out[idx] = lb;
 }
@@ -685,7 +708,8 @@ template <int M>
 __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView &L,
                                                 const uint8_t *nodes, int stride,
                                                 bool aligned, int64_t base,
-                                                int64_t count, int32_t *lb_out) {
+                                                int64_t count, int32_t *lb_out,
+                                                const Prefilter pf = Prefilter()) {
   const int tid = threadIdx.x;
   const int64_t ia = base + tid, ib = base + kBlock + tid;
   const bool la = ia < count, lbv = ib < count;
@@ -718,15 +742,29 @@ __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView 
   const uint64_t W =
       (uint64_t)((UA & 0xffffu) | (UB << 16)) |
       ((uint64_t)((UA >> 16) | (UB & 0xffff0000u)) << 32);
+  // one-machine bounds of both nodes (see bound_nodes)
+  bool skip = false;
+  uint32_t LB1 = 0;
+  if (pf.lb1_only || pf.ub) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) LB1 = pk_max(LB1, pk_add(T[k], Q[k]));
+    bool da = !la || badA || UA == 0u, db = !lbv || badB || UB == 0u;
+    if (!pf.lb1_only) {
+      const int ub = *pf.ub;
+      da = da || eliminated((int)(LB1 & 0xffffu), ub, pf.rule);
+      db = db || eliminated((int)(LB1 >> 16), ub, pf.rule);
+    }
+    skip = pf.lb1_only || __ballot(!(da && db)) == 0;
+  }
 #pragma unroll
   for (int k = 0; k < M; ++k) asm volatile("" : "+v"(R[k]), "+v"(T[k]), "+v"(Q[k]));
-  const uint32_t LB = pair_sweep_p16<M>(L.s_rec, I.npad, W, R, T, Q);
+  const uint32_t LB = skip ? LB1 : pair_sweep_p16<M>(L.s_rec, I.npad, W, R, T, Q);
   if (la) {
-    int lb = __builtin_popcount(UA) == 0 ? lastA : (int)(LB & 0xffffu);
+    int lb = UA == 0u ? lastA : (int)(LB & 0xffffu);
     lb_out[ia] = badA ? FSP_LB_INVALID : lb;
   }
   if (lbv) {
-    int lb = __builtin_popcount(UB) == 0 ? lastB : (int)(LB >> 16);
+    int lb = UB == 0u ? lastB : (int)(LB >> 16);
     lb_out[ib] = badB ? FSP_LB_INVALID : lb;
   }
 }

@@ -91,9 +91,21 @@ inline size_t bound_scratch_bytes(int n, int64_t count) {
 // bytes and is used by no other work running at the same time; null takes
 // the workspace that the library keeps for the stream (allocated or grown on
 // first need, which synchronises the stream).
+// One-machine pre-filter of a bounding launch.  With ub set, a wave whose
+// live nodes all have a one-machine bound that the rule eliminates against
+// *ub skips the pair walks and reports those bounds (the eliminations are
+// the same: the pair bound is never smaller).  lb1_only: every node gets
+// its one-machine bound.
+struct Prefilter {
+  const int32_t *ub = nullptr;  // device pointer, read when the kernel starts
+  int rule = 0;                 // FSP_PRUNE_GE or FSP_PRUNE_GT
+  int lb1_only = 0;
+};
+
 int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
                  int64_t count, int32_t *lb_out, hipStream_t stream,
-                 const int32_t *count_dev, void *scratch);
+                 const int32_t *count_dev, void *scratch,
+                 const Prefilter &pf = Prefilter());
 
 // The library's per-stream bounding workspace of at least `bytes` bytes.
 int stream_scratch(hipStream_t stream, size_t bytes, void **out);

@@ -56,7 +56,7 @@ class _Policy(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nb_iterations", ctypes.c_int32),
                 ("fixed_pool", ctypes.c_int64), ("max_pool", ctypes.c_int64),
                 ("time_limit_s", ctypes.c_double), ("prune_rule", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("model", ctypes.c_void_p),
+                ("prefilter", ctypes.c_int32), ("model", ctypes.c_void_p),
                 ("log_path", ctypes.c_char_p)]
 
 
@@ -90,6 +90,8 @@ def lib() -> ctypes.CDLL:
     L.fsp_free_instance.restype = ctypes.c_int
     L.fsp_instance_info.argtypes = [P, P, P, P]
     L.fsp_instance_info.restype = ctypes.c_int
+    L.fsp_bound_pool_one_machine.argtypes = [ctypes.POINTER(_Nodes), i64, P, P]
+    L.fsp_bound_pool_one_machine.restype = ctypes.c_int
     L.fsp_instance_path.argtypes = [P, P]
     L.fsp_instance_path.restype = ctypes.c_int
     L.fsp_bound_pool.argtypes = [ctypes.POINTER(_Nodes), i64, P, P]
@@ -207,20 +209,30 @@ class Instance:
         """Bounds of a ``uint8 [count, stride]`` device pool (fsp_bound_pool).
 
         Asynchronous on ``stream`` (default: torch's current stream)."""
-        if nodes.dtype != torch.uint8 or nodes.dim() != 2 or not nodes.is_cuda:
-            raise ValueError("nodes must be a uint8 [count, stride] device tensor")
-        if nodes.stride(1) != 1:
-            raise ValueError("records must be contiguous")
-        count, stride = int(nodes.shape[0]), int(nodes.stride(0))
-        if out is None:
-            out = torch.empty(count, dtype=torch.int32, device=nodes.device)
-        if out.dtype != torch.int32 or out.numel() < count or not out.is_contiguous():
-            raise ValueError("out must be a contiguous int32 device tensor of >= count")
-        desc = _Nodes(self.handle.value, nodes.data_ptr(), stride)
-        _check(lib().fsp_bound_pool(ctypes.byref(desc), count,
-                                    ctypes.c_void_p(out.data_ptr()),
-                                    _stream_handle(stream)), "fsp_bound_pool")
-        return out
+        return _bound_call(self, "fsp_bound_pool", nodes, out, stream)
+
+    def bound_pool_one_machine(self, nodes: torch.Tensor, out: torch.Tensor | None = None,
+                               stream=None) -> torch.Tensor:
+        """One-machine bounds of a ``uint8 [count, stride]`` device pool
+        (fsp_bound_pool_one_machine); asynchronous on ``stream``."""
+        return _bound_call(self, "fsp_bound_pool_one_machine", nodes, out, stream)
+
+
+def _bound_call(inst, fn_name, nodes, out, stream):
+    if nodes.dtype != torch.uint8 or nodes.dim() != 2 or not nodes.is_cuda:
+        raise ValueError("nodes must be a uint8 [count, stride] device tensor")
+    if nodes.stride(1) != 1:
+        raise ValueError("records must be contiguous")
+    count, stride = int(nodes.shape[0]), int(nodes.stride(0))
+    if out is None:
+        out = torch.empty(count, dtype=torch.int32, device=nodes.device)
+    if out.dtype != torch.int32 or out.numel() < count or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 device tensor of >= count")
+    desc = _Nodes(inst.handle.value, nodes.data_ptr(), stride)
+    _check(getattr(lib(), fn_name)(ctypes.byref(desc), count,
+                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+           fn_name)
+    return out
 
 
 class Result:
@@ -241,7 +253,8 @@ class Result:
 
 def make_policy(kind: str = "adaptive", *, fixed_pool: int = 0, max_pool: int = 0,
                 nb_iterations: int = 10, time_limit: float | None = None,
-                prune_rule: str = "ge", model=None, log_path: str | None = None) -> _Policy:
+                prune_rule: str = "ge", model=None, log_path: str | None = None,
+                prefilter: bool = False) -> _Policy:
     pol = _Policy()
     pol.kind = POOL_KINDS[kind]
     pol.nb_iterations = int(nb_iterations)
@@ -249,6 +262,7 @@ def make_policy(kind: str = "adaptive", *, fixed_pool: int = 0, max_pool: int = 
     pol.max_pool = int(max_pool)
     pol.time_limit_s = float(time_limit) if time_limit else 0.0
     pol.prune_rule = PRUNE_RULES[prune_rule]
+    pol.prefilter = 1 if prefilter else 0
     pol.model = ctypes.c_void_p(model.handle.value) if model is not None else None
     pol.log_path = log_path.encode() if log_path else None
     return pol

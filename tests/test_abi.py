@@ -89,3 +89,6 @@ def test_other_entry_points_reject_null(L):
     L.fsp_bound_pool.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.c_void_p]
     assert L.fsp_bound_pool(None, 10, None, None) == -1
+    L.fsp_bound_pool_one_machine.argtypes = [ctypes.c_void_p, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_void_p]
+    assert L.fsp_bound_pool_one_machine(None, 10, None, None) == -1

@@ -102,7 +102,12 @@ def test_critical_tree_counts_equal_oracle(fsp, orc, n, m, seed, rule):
     for kind, kw in (("fixed", {"fixed_pool": 1}), ("fixed", {"fixed_pool": 37}),
                      ("fixed", {"fixed_pool": 100000}), ("adaptive", {}),
                      ("autotuned", {"fixed_pool": 64}), ("learned", {"fixed_pool": 5, "model": model}),
-                     ("learned", {"fixed_pool": 3000, "model": model})):
+                     ("learned", {"fixed_pool": 3000, "model": model}),
+                     # the one-machine pre-filter skips pair walks, never an elimination
+                     ("fixed", {"fixed_pool": 37, "prefilter": True}),
+                     ("adaptive", {"prefilter": True}),
+                     ("autotuned", {"fixed_pool": 64, "prefilter": True}),
+                     ("learned", {"fixed_pool": 3000, "model": model, "prefilter": True})):
         res = fsp.branch_and_bound(inst, kind, ub=opt, prune_rule=rule, **kw)
         say(f"{n}x{m} {rule} {kind} {kw}: {res.nodes_bounded} vs {ost.nodes_bounded}")
         assert res.makespan == opt and res.found == 0 and res.status == 0
@@ -220,3 +225,18 @@ def test_larger_instances_inside_the_search(fsp, orc, n, m, kind):
         assert res.makespan >= res.root_lb
     else:
         assert res.root_lb <= res.open_lb <= res.makespan
+
+
+@pytest.mark.parametrize("rule", ["ge", "gt"])
+def test_prefilter_reaches_the_brute_force_optimum(fsp, orc, rule):
+    rng = np.random.default_rng(91 if rule == "ge" else 92)
+    for t in range(10):
+        n, m = int(rng.integers(2, 9)), int(rng.integers(2, 8))
+        p = rng.integers(1, 99, size=(n, m)).astype(np.int32)
+        opt, _ = orc.brute_force(p)
+        inst = fsp.Instance(p)
+        for kind in ("adaptive", "autotuned"):
+            res = fsp.branch_and_bound(inst, kind, prune_rule=rule, prefilter=True,
+                                       **({"fixed_pool": 50} if kind == "autotuned" else {}))
+            assert res.status == 0 and res.makespan == opt
+            check_schedule(orc, p, res)

@@ -231,3 +231,26 @@ def test_concurrent_streams_with_job_mask_scratch(fsp, orc):
     torch.cuda.synchronize()
     for q, o in zip(pools, (out1, out2, out3)):
         assert np.array_equal(o.cpu().numpy(), orc.bound_pool(p, q, nthreads=8))
+
+
+
+@pytest.mark.parametrize("n,m", [(9, 5), (20, 20), (31, 20), (32, 20), (20, 10), (50, 20),
+                                 (64, 13), (100, 10), (255, 3)],
+                         ids=lambda v: str(v))
+def test_one_machine_bound_matches_oracle(fsp, orc, n, m):
+    """fsp_bound_pool_one_machine in every walk form (packed, register,
+    register64, masks) against the oracle's one-machine bound, bit for bit,
+    and never above the pair bound."""
+    count = 1537 if n <= 100 else 700
+    p = I.instance(n, m, 8100 + 7 * n + m)
+    pool = I.random_pool(n, count, 0, n, 8200 + 7 * n + m)
+    say(f"one-machine bound n={n} m={m}: {count} nodes")
+    inst = fsp.Instance(p)
+    t = torch.from_numpy(np.ascontiguousarray(pool)).cuda()
+    got = inst.bound_pool_one_machine(t)
+    both = inst.bound_pool(t)
+    torch.cuda.synchronize()
+    got, both = got.cpu().numpy(), both.cpu().numpy()
+    want = orc.bound_pool_one_machine(p, pool, nthreads=8)
+    assert np.array_equal(got, want)
+    assert np.all(got <= both)
