@@ -95,11 +95,10 @@ __global__ __launch_bounds__(kBlock, 4) void bound_kernel(const BoundParams a) {
 }
 
 // Two nodes per lane in packed 16-bit arithmetic (n <= 32, total work <=
-// 32767): tiles of 2 * kBlock nodes.  Setting up the second node while the
-// first one's packed state is live needs more than 128 VGPRs at 16+
-// machines, so the bound is three workgroups per CU (up to 168 VGPRs).
+// 32767): tiles of 2 * kBlock nodes.  Both nodes are set up together in
+// packed form, so the kernel fits four workgroups per CU (128 VGPRs).
 template <int M>
-__global__ __launch_bounds__(kBlock, 3) void bound_kernel_p16(const BoundParams a) {
+__global__ __launch_bounds__(kBlock, 4) void bound_kernel_p16(const BoundParams a) {
   extern __shared__ __align__(16) char smem[];
   int64_t count = a.count, ntiles = a.ntiles;
   if (a.count_dev) {
@@ -108,7 +107,7 @@ __global__ __launch_bounds__(kBlock, 3) void bound_kernel_p16(const BoundParams 
   }
   if ((int64_t)blockIdx.x >= ntiles) return;
   const LdsView L = carve<false>(smem, a.I);
-  stage_instance<false>(a.I, L);
+  stage_p16_rows(a.I, L);
   __syncthreads();
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
     bound_nodes_p16<M>(a.I, L, a.nodes, a.stride, a.aligned != 0,

@@ -53,13 +53,19 @@ __host__ __device__ constexpr int pair_index(int k, int l) {
   return k * (2 * M - k - 1) / 2 + (l - k - 1);
 }
 
+// Row pitch (32-bit words) of the packed rows of p in LDS: mp / 2 rounded
+// up to 16 bytes, so that a row is read with 16-byte loads.
+__host__ __device__ constexpr int p16_row_words(int mp) { return (mp / 2 + 3) & ~3; }
+
 __host__ __device__ inline size_t lds_bytes(int n, int mp, int npad, int ppc,
                                             bool wide) {
   size_t b = (size_t)ppc * npad * sizeof(Rec);
   if (wide)
     b += (size_t)((n + 31) / 32) * kBlock * 4;
-  else
-    b += (size_t)n * mp * 4;
+  else {  // 32-bit rows of p, or the packed rows plus a row of zeros
+    const int rows32 = n * mp, rows16 = (n + 1) * p16_row_words(mp);
+    b += (size_t)(rows32 > rows16 ? rows32 : rows16) * 4;
+  }
   return (b + 15) & ~size_t(15);
 }
 
@@ -700,10 +706,161 @@ __device__ __forceinline__ uint32_t pair_sweep_p16(const char *s_rec, int npad,
   return LB;
 }
 
+// Lane view of one 16-byte chunk of a node record: chunk c of the record at
+// rp (zeros when `take` is false).  Unaligned pools read byte by byte.
+__device__ __forceinline__ void record_chunk(const uint8_t *rp, int c, bool take,
+                                             bool aligned, int stride,
+                                             uint32_t (&w)[4]) {
+  w[0] = w[1] = w[2] = w[3] = 0u;
+  if (!take) return;
+  if (aligned) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(rp + c * 16);
+    w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int o = c * 16 + q * 4 + b;
+        const uint32_t v = o < stride ? rp[o] : 0u;
+        acc |= v << (8 * b);
+      }
+      w[q] = acc;
+    }
+  }
+}
+
+// One prefix position of one node: job byte `j` at position `pos` of a node
+// of depth d.  Returns the row of s_p16 to add (n, the row of zeros, past the
+// node's depth or for an invalid job), clears the job in U and flags a job
+// out of range or already scheduled.
+__device__ __forceinline__ int prefix_job(uint32_t j, int pos, int d, int n,
+                                          uint32_t &U, bool &bad) {
+  const bool in = pos <= d;
+  const bool ok = j < (uint32_t)n;
+  const bool free = __builtin_amdgcn_ubfe(U, j, 1u) != 0u;
+  bad = bad || (in && !(ok && free));
+  const bool take = in && ok;
+  U &= take ? ~(1u << (j & 31u)) : ~0u;
+  return take ? (int)j : n;
+}
+
+// The state of both nodes of a lane at once, node A in the low and node B
+// in the high 16 bits of every value (total work <= 32767, so every front,
+// head, tail and column sum fits).  Step 1 walks the two prefixes together
+// up to the deeper one; a position past a node's own depth adds the row of
+// zeros (row n of s_p16), which leaves its front unchanged because a front
+// is non-decreasing along the machines.  Step 2 takes the head and tail
+// minima over each node's unscheduled jobs with the job's sums broadcast to
+// both halves and a per-half all-ones mask for a scheduled job.
+//   s_p16: [n + 1][p16_row_words(mp)] packed machine pairs of p, row n zero.
+template <int M>
+__device__ __forceinline__ void node_state_p16(
+    const InstView I, const uint32_t *s_p16, const uint8_t *nodes, int stride,
+    bool aligned, int64_t ia, int64_t ib, bool la, bool lbv, uint32_t &UA,
+    uint32_t &UB, bool &badA, bool &badB, uint32_t &last, uint32_t (&R)[M],
+    uint32_t (&T)[M], uint32_t (&Q)[M]) {
+  const int n = I.n, h = p16_row_words(I.mp);
+  const uint32_t full = n >= 32 ? ~0u : ((1u << n) - 1u);
+  u16x2 F[M], Pk[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) F[k] = Pk[k] = (u16x2){0, 0};
+  UA = UB = full;
+  badA = badB = false;
+  int dA = 0, dB = 0;
+  const uint8_t *pa = nodes + ia * (int64_t)stride;
+  const uint8_t *pb = nodes + ib * (int64_t)stride;
+  if (la) dA = pa[0];
+  if (lbv) dB = pb[0];
+  if (dA > n) { badA = true; dA = 0; }
+  if (dB > n) { badB = true; dB = 0; }
+  const int dmax = max(dA, dB);
+  // ---- 1. both prefixes: front recurrence and prefix column sums ----
+  for (int c = 0; c * 16 <= dmax; ++c) {
+    uint32_t wa[4], wb[4];
+    record_chunk(pa, c, c * 16 <= dA, aligned, stride, wa);
+    record_chunk(pb, c, c * 16 <= dB, aligned, stride, wb);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      const int pos = c * 16 + b;
+      if (pos >= 1 && pos <= dmax) {
+        const int ja = prefix_job((wa[b >> 2] >> (8 * (b & 3))) & 0xffu, pos, dA, n, UA, badA);
+        const int jb = prefix_job((wb[b >> 2] >> (8 * (b & 3))) & 0xffu, pos, dB, n, UB, badB);
+        const uint32_t *ra = s_p16 + ja * h, *rb = s_p16 + jb * h;
+#pragma unroll
+        for (int t = 0; 2 * t < M; ++t) {
+          const uint32_t xa = ra[t], xb = rb[t];
+          // machine 2t of both nodes, then machine 2t + 1
+          const u16x2 lo = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(xb, xa, 0x05040100u));
+          const u16x2 hi = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(xb, xa, 0x07060302u));
+          const int k = 2 * t;
+          F[k] = (k == 0 ? F[0] : __builtin_elementwise_max(F[k], F[k - 1])) + lo;
+          Pk[k] += lo;
+          if (k + 1 < M) {
+            F[k + 1] = __builtin_elementwise_max(F[k + 1], F[k]) + hi;
+            Pk[k + 1] += hi;
+          }
+        }
+      }
+    }
+  }
+  // ---- 2. head and tail minima over the unscheduled jobs of each node ----
+  const uint64_t W = (uint64_t)((UA & 0xffffu) | (UB << 16)) |
+                     ((uint64_t)((UA >> 16) | (UB & 0xffff0000u)) << 32);
+  u16x2 hm[M], qm[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) hm[k] = qm[k] = (u16x2){0xffff, 0xffff};
+  const int mp2 = I.mp / 2;
+  // the sums are the same for every lane: scalar loads
+  ku32 *Hk = reinterpret_cast<ku32 *>(reinterpret_cast<uint64_t>(I.Hp));
+  ku32 *Qk = reinterpret_cast<ku32 *>(reinterpret_cast<uint64_t>(I.Qp));
+  for (int j = 0; j < n; ++j) {
+    const uint32_t s = (uint32_t)((j & 15) + 32 * (j >> 4));
+    // 1 in a half whose node has job j unscheduled; minus one: 0 or 0xffff
+    const u16x2 al = __builtin_bit_cast(u16x2, (uint32_t)(W >> s) & 0x10001u);
+    const u16x2 g = al - (u16x2){1, 1};
+    ku32 *hr = Hk + j * mp2;
+    ku32 *qr = Qk + j * mp2;
+#pragma unroll
+    for (int t = 0; 2 * t < M; ++t) {
+      const uint32_t hw = hr[t], qw = qr[t];
+      const u16x2 h0 = {(unsigned short)hw, (unsigned short)hw};
+      const u16x2 q0 = {(unsigned short)qw, (unsigned short)qw};
+      hm[2 * t] = __builtin_elementwise_min(hm[2 * t], __builtin_elementwise_max(h0, g));
+      qm[2 * t] = __builtin_elementwise_min(qm[2 * t], __builtin_elementwise_max(q0, g));
+      if (2 * t + 1 < M) {
+        const u16x2 h1 = {(unsigned short)(hw >> 16), (unsigned short)(hw >> 16)};
+        const u16x2 q1 = {(unsigned short)(qw >> 16), (unsigned short)(qw >> 16)};
+        hm[2 * t + 1] =
+            __builtin_elementwise_min(hm[2 * t + 1], __builtin_elementwise_max(h1, g));
+        qm[2 * t + 1] =
+            __builtin_elementwise_min(qm[2 * t + 1], __builtin_elementwise_max(q1, g));
+      }
+    }
+  }
+  // the column totals are loaded here, not hoisted above the loop
+  asm volatile("" ::: "memory");
+  ku32 *tot = reinterpret_cast<ku32 *>(reinterpret_cast<uint64_t>(I.tot));
+  // ---- 3. heads r = max(F, F[0] + min H), r + remaining work, tails ----
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const u16x2 r = __builtin_elementwise_max(F[k], F[0] + hm[k]);
+    const unsigned short tk = (unsigned short)tot[k];
+    // r + tot - Pk may pass 65535 on the way; the result is at most the
+    // total work, so the 16-bit wrap-around cancels
+    R[k] = __builtin_bit_cast(uint32_t, r);
+    T[k] = __builtin_bit_cast(uint32_t, r + (u16x2){tk, tk} - Pk[k]);
+    Q[k] = __builtin_bit_cast(uint32_t, qm[k]);
+  }
+  last = __builtin_bit_cast(uint32_t, F[M - 1]);
+}
+
 // Bound the 512 nodes [base, base + 512) of a pool, nodes base + tid (low
 // halves) and base + 256 + tid (high halves), writing lb_out[idx] for
 // idx < count.  n <= 32 and the table is whole in LDS (I.rec is the packed
-// table).  Every lane of the workgroup must call it.
+// table, L.s_p holds the packed rows of p).  Every lane of the workgroup must
+// call it.
 template <int M>
 __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView &L,
                                                 const uint8_t *nodes, int stride,
@@ -714,31 +871,10 @@ __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView 
   const int64_t ia = base + tid, ib = base + kBlock + tid;
   const bool la = ia < count, lbv = ib < count;
   uint32_t R[M], T[M], Q[M];
-  uint32_t UA, UB;
-  int dA, dB, lastA, lastB;
+  uint32_t UA, UB, last;
   bool badA, badB;
-  {
-    int r[M], t[M], q[M];
-    node_state<M, false, 0>(I, L.s_p, nullptr, nodes, stride, aligned, ia, la, UA,
-                            dA, badA, lastA, r, t, q);
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-      R[k] = (uint32_t)r[k] & 0xffffu;
-      T[k] = (uint32_t)t[k] & 0xffffu;
-      Q[k] = (uint32_t)q[k] & 0xffffu;
-    }
-  }
-  {
-    int r[M], t[M], q[M];
-    node_state<M, false, 0>(I, L.s_p, nullptr, nodes, stride, aligned, ib, lbv, UB,
-                            dB, badB, lastB, r, t, q);
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-      R[k] |= (uint32_t)r[k] << 16;
-      T[k] |= (uint32_t)t[k] << 16;
-      Q[k] |= (uint32_t)q[k] << 16;
-    }
-  }
+  node_state_p16<M>(I, reinterpret_cast<const uint32_t *>(L.s_p), nodes, stride,
+                    aligned, ia, ib, la, lbv, UA, UB, badA, badB, last, R, T, Q);
   const uint64_t W =
       (uint64_t)((UA & 0xffffu) | (UB << 16)) |
       ((uint64_t)((UA >> 16) | (UB & 0xffff0000u)) << 32);
@@ -760,13 +896,31 @@ __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView 
   for (int k = 0; k < M; ++k) asm volatile("" : "+v"(R[k]), "+v"(T[k]), "+v"(Q[k]));
   const uint32_t LB = skip ? LB1 : pair_sweep_p16<M>(L.s_rec, I.npad, W, R, T, Q);
   if (la) {
-    int lb = UA == 0u ? lastA : (int)(LB & 0xffffu);
+    int lb = UA == 0u ? (int)(last & 0xffffu) : (int)(LB & 0xffffu);
     lb_out[ia] = badA ? FSP_LB_INVALID : lb;
   }
   if (lbv) {
-    int lb = UB == 0u ? lastB : (int)(LB >> 16);
+    int lb = UB == 0u ? (int)(last >> 16) : (int)(LB >> 16);
     lb_out[ib] = badB ? FSP_LB_INVALID : lb;
   }
+}
+
+// Stage the packed rows of p for node_state_p16: s_p16[j][t] = p[j][2t] |
+// p[j][2t + 1] << 16 for j < n and t < mp / 2; zeros elsewhere (row n and
+// the pitch padding).  It takes the region of the 32-bit rows of the other
+// narrow kernels, which lds_bytes sizes for both.
+__device__ __forceinline__ void stage_p16_rows(const InstView I, const LdsView &L) {
+  const int h = p16_row_words(I.mp);
+  uint32_t *dst = reinterpret_cast<uint32_t *>(L.s_p);
+  for (int i = threadIdx.x; i < (I.n + 1) * h; i += kBlock) {
+    const int j = i / h, t = i - j * h;
+    uint32_t v = 0;
+    if (j < I.n && 2 * t < I.mp)
+      v = ((uint32_t)I.p[j * I.mp + 2 * t] & 0xffffu) |
+          ((uint32_t)I.p[j * I.mp + 2 * t + 1] << 16);
+    dst[i] = v;
+  }
+  if (I.nchunks == 1) stage_chunk(I, L.s_rec, 0);
 }
 
 // InstView of a loaded instance with the pair table split into LDS chunks of

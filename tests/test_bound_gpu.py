@@ -99,11 +99,17 @@ def test_malformed_nodes(fsp, orc):
         recs[11, 0] = max(1, recs[11, 0]); recs[11, 1] = n         # id == n
         recs[13, 0] = max(1, recs[13, 0]); recs[13, 1] = 255       # id 255
         recs[17, 0] = 255                     # depth 255
+        # the same faults on nodes 256 + i, which the packed path bounds in
+        # the high halves of the lanes that hold nodes i
+        recs[261, 0] = n + 1
+        recs[265, 0] = max(2, recs[265, 0]); recs[265, 2] = recs[265, 1]
+        recs[268, 0] = max(1, recs[268, 0]); recs[268, 1] = n
+        recs[7 + 256, 0] = max(3, recs[7 + 256, 0]); recs[7 + 256, 3] = recs[7 + 256, 2]
         inst = fsp.Instance(p)
         got = gpu_bounds(fsp, inst, recs)
         want = orc.bound_pool(p, recs, 8)
         assert np.array_equal(got, want)
-        for i in (3, 7, 11, 13, 17):
+        for i in (3, 7, 11, 13, 17, 261, 263, 265, 268):
             assert got[i] == -1
 
 
