@@ -282,8 +282,10 @@ int fsp_branch_and_bound(const fsp_instance *inst,
  * fsp_autotune_pool -- the pool size (children per pool) that maximises
  * nodes bounded per second of search for this instance's shape: FSP_POOL_
  * AUTOTUNED searches of budget_s / #candidates seconds each (budget_s <= 0:
- * 0.25 s per candidate) over 2^14 .. min(resident threads, 2^20); a larger
- * pool must win by more than 3 %.  Cached per (device, n, m) for the life of
+ * 0.25 s per candidate) over 2^14 .. min(resident threads, 2^20), each rated
+ * on the batches after the first third of its search time (a search that
+ * ends sooner is rated whole); a larger pool must win by more than 3 %.
+ * Cached per (device, n, m) for the life of
  * the process.  rate_out (may be NULL): the winner's nodes per second.
  */
 int fsp_autotune_pool(const fsp_instance *inst, double budget_s,

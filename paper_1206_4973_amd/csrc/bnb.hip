@@ -619,6 +619,16 @@ struct SampleSpec {
   int64_t *n_out;   // host
 };
 
+// Search throughput over the batches that start after the first `skip`
+// fraction of the search loop's share of the time limit (the first batches of
+// a search from the root hold few nodes, the more so the larger the pool
+// target, and would bias a short measurement toward small pools).
+struct RateWindow {
+  double skip;
+  int64_t nodes = 0;
+  double secs = 0.0;
+};
+
 struct TuneEntry {
   int dev, n, m;
   int64_t pool;
@@ -628,7 +638,7 @@ std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune;
 
 int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_in,
-            fsp_result *out, const SampleSpec *samples);
+            fsp_result *out, const SampleSpec *samples, RateWindow *window = nullptr);
 
 int tuned_pool(const fsp_instance *inst, int64_t *pool) {
   int64_t p = 0;
@@ -639,7 +649,7 @@ int tuned_pool(const fsp_instance *inst, int64_t *pool) {
 }
 
 int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_in,
-            fsp_result *out, const SampleSpec *samples) {
+            fsp_result *out, const SampleSpec *samples, RateWindow *window) {
   if (!inst || !policy || !out) return FSP_EINVAL;
   if (policy->prune_rule != FSP_PRUNE_GE && policy->prune_rule != FSP_PRUNE_GT)
     return FSP_EINVAL;
@@ -729,6 +739,10 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
     const BnbDesc &h = *S.host_desc;
     const int64_t batch_nodes = h.nodes_bounded - last_bounded;
     last_bounded = h.nodes_bounded;
+    if (window && t0 >= t_loop0 + window->skip * (policy->time_limit_s - t_loop0)) {
+      window->nodes += batch_nodes;
+      window->secs += t1 - t0;
+    }
     if (h.improved) t_found = t1;
     if (log)
       std::fprintf(log,
@@ -883,9 +897,13 @@ int fsp_autotune_pool(const fsp_instance *inst, double budget_s, int64_t *pool_o
     pol.time_limit_s = slice;
     pol.prune_rule = FSP_PRUNE_GE;
     fsp_result r{};
-    const int rc = run_bnb(inst, &pol, 0, &r, nullptr);
+    RateWindow win{1.0 / 3.0};
+    const int rc = run_bnb(inst, &pol, 0, &r, nullptr, &win);
     if (rc != FSP_OK) return rc;
-    const double rate = r.t_search_s > 0 ? (double)r.nodes_bounded / r.t_search_s : 0.0;
+    // steady-state rate; a search that ends before the window counts whole
+    const double rate = win.secs > 0 ? (double)win.nodes / win.secs
+                        : r.t_search_s > 0 ? (double)r.nodes_bounded / r.t_search_s
+                                           : 0.0;
     if (rate > best_rate * 1.03) {  // a larger pool must win by more than 3 %
       best_rate = rate;
       best = c;

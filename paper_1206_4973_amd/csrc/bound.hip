@@ -262,7 +262,7 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
   a.I = inst_view(inst, wide ? kTableBudgetWide : kTableBudgetNarrow);
   BoundFn fn;
   if (p16) {
-    a.I.rec = inst->d_rec16;  // same size and LDS layout as the 32-bit table
+    a.I.rec = inst->d_rec16;  // same size as the 32-bit table
     fn = inst->m >= 2 && inst->m <= kMaxMachines
              ? p16_kernel(inst->m, std::make_integer_sequence<int, kMaxMachines - 1>())
              : nullptr;

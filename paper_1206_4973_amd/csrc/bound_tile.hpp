@@ -612,9 +612,9 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
 //        x and y are the halves of one record word, broadcast by op_sel)
 //   z  = max(t, u)                              (v_pk_max_i16)
 // i.e. 5 instructions for two nodes instead of 8.
-__device__ __forceinline__ uint32_t step_p16(uint64_t W, uint32_t xy,
+__device__ __forceinline__ uint32_t step_p16(uint64_t W, uint32_t bits, uint32_t xy,
                                              uint32_t s, uint32_t z) {
-  const uint32_t al = (uint32_t)(W >> s) & 0x10001u;
+  const uint32_t al = (uint32_t)(W >> s) & bits;
   uint32_t t, u, r;
   asm("v_pk_mad_u16 %0, %1, %2, %3 op_sel_hi:[1,0,1]"
       : "=v"(t) : "v"(al), "v"(xy), "v"(z));
@@ -625,34 +625,35 @@ __device__ __forceinline__ uint32_t step_p16(uint64_t W, uint32_t xy,
 }
 
 __device__ __forceinline__ uint32_t walk1_p16(const char *rp_raw, int npad,
-                                              uint64_t W, uint32_t Z) {
+                                              uint64_t W, uint32_t bits, uint32_t Z) {
   const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);  // 2 records
   for (int i = 0; i < npad / 4; ++i) {
     const int4 r0 = rp[2 * i], r1 = rp[2 * i + 1];
-    Z = step_p16(W, r0.x, r0.y, Z);
-    Z = step_p16(W, r0.z, r0.w, Z);
-    Z = step_p16(W, r1.x, r1.y, Z);
-    Z = step_p16(W, r1.z, r1.w, Z);
+    Z = step_p16(W, bits, r0.x, r0.y, Z);
+    Z = step_p16(W, bits, r0.z, r0.w, Z);
+    Z = step_p16(W, bits, r1.x, r1.y, Z);
+    Z = step_p16(W, bits, r1.z, r1.w, Z);
   }
   return Z;
 }
 
-__device__ __forceinline__ void walk2_p16(const char *ra_raw, const char *rb_raw,
-                                          int npad, uint64_t W, uint32_t &ZA,
-                                          uint32_t &ZB) {
-  const int4 *ra = reinterpret_cast<const int4 *>(ra_raw);
-  const int4 *rb = reinterpret_cast<const int4 *>(rb_raw);
+// Two pairs walked together; their tables are interleaved four positions at
+// a time (four of the first pair, four of the second, ...), so both are read
+// from one address.
+__device__ __forceinline__ void walk2_p16(const char *rp_raw, int npad, uint64_t W,
+                                          uint32_t bits, uint32_t &ZA, uint32_t &ZB) {
+  const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);
   for (int i = 0; i < npad / 4; ++i) {
-    const int4 a0 = ra[2 * i], a1 = ra[2 * i + 1];
-    const int4 b0 = rb[2 * i], b1 = rb[2 * i + 1];
-    ZA = step_p16(W, a0.x, a0.y, ZA);
-    ZB = step_p16(W, b0.x, b0.y, ZB);
-    ZA = step_p16(W, a0.z, a0.w, ZA);
-    ZB = step_p16(W, b0.z, b0.w, ZB);
-    ZA = step_p16(W, a1.x, a1.y, ZA);
-    ZB = step_p16(W, b1.x, b1.y, ZB);
-    ZA = step_p16(W, a1.z, a1.w, ZA);
-    ZB = step_p16(W, b1.z, b1.w, ZB);
+    const int4 a0 = rp[4 * i], a1 = rp[4 * i + 1];
+    const int4 b0 = rp[4 * i + 2], b1 = rp[4 * i + 3];
+    ZA = step_p16(W, bits, a0.x, a0.y, ZA);
+    ZB = step_p16(W, bits, b0.x, b0.y, ZB);
+    ZA = step_p16(W, bits, a0.z, a0.w, ZA);
+    ZB = step_p16(W, bits, b0.z, b0.w, ZB);
+    ZA = step_p16(W, bits, a1.x, a1.y, ZA);
+    ZB = step_p16(W, bits, b1.x, b1.y, ZB);
+    ZA = step_p16(W, bits, a1.z, a1.w, ZA);
+    ZB = step_p16(W, bits, b1.z, b1.w, ZB);
   }
 }
 
@@ -680,6 +681,9 @@ __device__ __forceinline__ uint32_t pair_sweep_p16(const char *s_rec, int npad,
                                                    const uint32_t (&Q)[M]) {
   int pb = npad * (int)sizeof(Rec);
   asm volatile("" : "+s"(pb));
+  // the bit mask in an SGPR gives the masking instruction its short encoding
+  uint32_t bits;
+  asm volatile("s_mov_b32 %0, 0x10001" : "=s"(bits));
   int off = 0;
   uint32_t LB = 0;
 #pragma unroll
@@ -688,7 +692,7 @@ __device__ __forceinline__ uint32_t pair_sweep_p16(const char *s_rec, int npad,
     for (int l = k + 1; l < M; l += 2) {
       if (l + 1 < M) {
         uint32_t ZA = pk_sub(R[l], R[k]), ZB = pk_sub(R[l + 1], R[k]);
-        walk2_p16(s_rec + off, s_rec + off + pb, npad, W, ZA, ZB);
+        walk2_p16(s_rec + off, npad, W, bits, ZA, ZB);
         // T + Q + z wraps in 16 bits only on the way: the sum is a bound of
         // the method, at most the total work
         LB = pk_max(LB, pk_max(pk_add(pk_add(T[k], Q[l]), ZA),
@@ -696,7 +700,7 @@ __device__ __forceinline__ uint32_t pair_sweep_p16(const char *s_rec, int npad,
         asm volatile("" : "+v"(LB));
         off += 2 * pb;
       } else {
-        uint32_t Z = walk1_p16(s_rec + off, npad, W, pk_sub(R[l], R[k]));
+        uint32_t Z = walk1_p16(s_rec + off, npad, W, bits, pk_sub(R[l], R[k]));
         LB = pk_max(LB, pk_add(pk_add(T[k], Q[l]), Z));
         asm volatile("" : "+v"(LB));
         off += pb;

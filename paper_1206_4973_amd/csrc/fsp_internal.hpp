@@ -61,7 +61,7 @@ struct fsp_instance {
   // work <= 32767, so every quantity of the bound fits in 16 bits):
   //   {x | y << 16 with x = b - a, y = lag + b;  s = (job & 15) + 32 (job >> 4)}
   int p16 = 0;
-  fspi::Rec *d_rec16 = nullptr;  // [P][npad]
+  fspi::Rec *d_rec16 = nullptr;  // [P][npad], couples of pairs interleaved
   uint32_t *d_joff = nullptr;  // [P][npad] 8 * job id per table position
   std::vector<int32_t> p_host;  // [n][m], for host-side set-up work (NEH)
 };

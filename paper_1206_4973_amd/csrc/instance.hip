@@ -115,7 +115,17 @@ __global__ __launch_bounds__(256) void stage_pairs(
       xy = (int)(((uint32_t)(b - a) & 0xffffu) | ((uint32_t)(lag + b) << 16));
       s = (j & 15) + 32 * (j >> 4);
     }
-    rec16_out[slot] = make_int2(xy, s);
+    // The packed walk takes the pairs of a row two at a time, (k, k+1) with
+    // (k, k+2), (k, k+3) with (k, k+4), ..., the last one alone when the row
+    // has an odd count; the two tables of such a couple are interleaved four
+    // positions at a time, so that one address serves both.
+    const int i = l - k - 1, row = m - 1 - k;
+    size_t slot16 = slot;
+    if ((i | 1) < row) {
+      const size_t base = (size_t)(pi - (i & 1)) * npad;
+      slot16 = base + (size_t)(pos / 4) * 8 + (i & 1) * 4 + (pos & 3);
+    }
+    rec16_out[slot16] = make_int2(xy, s);
   }
 }
 
