@@ -52,31 +52,52 @@ __device__ __forceinline__ bool keeps(int rule, int lb, int ub) {
 }
 
 // ---- plan ------------------------------------------------------------------
-__global__ void plan_kernel(BnbDesc *D, int32_t *bcount, const uint8_t *pool,
-                            uint8_t *best_perm, int n, int stride,
-                            const int64_t *target_dev, int commit_only) {
-  if (threadIdx.x != 0) return;
-  // commit the best leaf of the previous pool
-  const uint64_t key = D->best_key;
-  if (key != ~0ull) {
-    const int mk = (int)(key >> 32);
-    const uint32_t idx = (uint32_t)(key & 0xffffffffu);
-    if (mk < D->ub) {
-      D->ub = mk;
-      const uint8_t *rec = pool + (size_t)idx * stride;
-      for (int i = 0; i < n; ++i) best_perm[i] = rec[1 + i];
-      D->found = 1;
-      D->improved = 1;
+// Plan the next pool, one wave: commit the best leaf of the previous pool,
+// then take the deepest non-empty depth and as many of its nodes (from the
+// top) as make about `target` children (at least one).  The wave reads 64
+// bucket counts per load, so finding the deepest non-empty depth costs one
+// memory round trip up to 64 jobs.
+__global__ __launch_bounds__(64) void plan_kernel(BnbDesc *D, int32_t *bcount,
+                                                  const uint8_t *pool, uint8_t *best_perm,
+                                                  int n, int stride,
+                                                  const int64_t *target_dev,
+                                                  int commit_only) {
+  const int lane = (int)threadIdx.x;
+  int done = 0;
+  if (lane == 0) {
+    const uint64_t key = D->best_key;
+    if (key != ~0ull) {
+      const int mk = (int)(key >> 32);
+      const uint32_t idx = (uint32_t)(key & 0xffffffffu);
+      if (mk < D->ub) {
+        D->ub = mk;
+        const uint8_t *rec = pool + (size_t)idx * stride;
+        for (int i = 0; i < n; ++i) best_perm[i] = rec[1 + i];
+        D->found = 1;
+        D->improved = 1;
+      }
+      D->best_key = ~0ull;
     }
-    D->best_key = ~0ull;
+    D->children = 0;
+    D->active = 0;
+    D->parents = 0;
+    if (D->overflow) D->done = 1;
+    done = D->done;
   }
-  D->children = 0;
-  D->active = 0;
-  D->parents = 0;
-  if (D->overflow) D->done = 1;
-  if (commit_only || D->done) return;
-  int d = n - 1;
-  while (d >= 0 && bcount[d] == 0) --d;
+  done = __shfl(done, 0);
+  if (commit_only || done) return;
+  int d = -1, c = 0;
+  for (int base = ((n - 1) / 64) * 64; base >= 0 && d < 0; base -= 64) {
+    const int idx = base + lane;
+    const int cnt = idx < n ? bcount[idx] : 0;
+    const uint64_t mask = __ballot(cnt > 0);
+    if (mask) {
+      const int hi = 63 - __builtin_clzll(mask);
+      d = base + hi;
+      c = __shfl(cnt, hi);
+    }
+  }
+  if (lane != 0) return;
   if (d < 0) {
     D->done = 1;
     return;
@@ -85,12 +106,12 @@ __global__ void plan_kernel(BnbDesc *D, int32_t *bcount, const uint8_t *pool,
   const int64_t target = *target_dev;
   int64_t k = target / u;
   if (k < 1) k = 1;
-  if (k > bcount[d]) k = bcount[d];
+  if (k > c) k = c;
   D->depth = d;
   D->parents = (int)k;
-  D->sel_count = bcount[d];
-  D->parent_base = bcount[d] - (int)k;
-  bcount[d] -= (int)k;
+  D->sel_count = c;
+  D->parent_base = c - (int)k;
+  bcount[d] = c - (int)k;
   D->active = 1;
   D->pools += 1;
 }
@@ -401,14 +422,12 @@ int BnbState::init(const fsp_instance *inst_, int64_t max_pool, int rule_) {
 int BnbState::init_model(const fsp_model *model_, float inv_scale_) {
   model = model_;
   inv_scale = inv_scale_;
-  const int nout = model_outputs(model);
   if (hipMalloc(&bscore, (size_t)n * cap * sizeof(float)) != hipSuccess ||
       hipMalloc(&tnodes, (size_t)cap * stride) != hipSuccess ||
       hipMalloc(&tlb, (size_t)cap * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&tscore, (size_t)cap * sizeof(float)) != hipSuccess ||
       hipMalloc(&hist, 4096 * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&X, (size_t)cap * 32 * 2) != hipSuccess ||
-      hipMalloc(&Y, (size_t)cap * nout * sizeof(float)) != hipSuccess)
+      hipMalloc(&X, (size_t)cap * 32 * 2) != hipSuccess)
     return FSP_ENOMEM;
   FSP_HIP_TRY(hipMemsetAsync(hist, 0, 4096 * sizeof(int32_t), stream));
   // the root (bucket 0) is alone: any score will do
@@ -434,7 +453,7 @@ void BnbState::release() {
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (void *p : {(void *)bnodes, (void *)blb, (void *)bcount, (void *)pool, (void *)pool_lb, slots,
                   (void *)desc, (void *)best_perm, (void *)target_dev, (void *)bscore,
-                  (void *)tnodes, (void *)tlb, (void *)tscore, (void *)hist, X, (void *)Y,
+                  (void *)tnodes, (void *)tlb, (void *)tscore, (void *)hist, X,
                   (void *)log_nodes, (void *)log_lb})
     if (p) (void)hipFree(p);
   if (host_desc) (void)hipHostFree(host_desc);

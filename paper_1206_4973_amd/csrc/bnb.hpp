@@ -122,7 +122,6 @@ struct BnbState {
   float *tscore = nullptr;
   int32_t *hist = nullptr;    // selection histogram (kept zeroed)
   void *X = nullptr;          // [cap][32] bf16 features
-  float *Y = nullptr;         // [cap][outputs]
 
   // training samples (log_cap > 0)
   int64_t log_cap = 0;
@@ -162,6 +161,18 @@ int policy_in_features(int m);
 // network (mlp.hip)
 int model_forward_dev(const fsp_model *m, const void *x, const int32_t *n_dev, int64_t max_n,
                       float *y, hipStream_t s);
+// Forward pass whose epilogue writes the learned ordering's estimate instead
+// of the outputs: row r is node r of depth d = *depth_dev + 1, and
+// est[d * rows_per_depth + r] = lb[d * rows_per_depth + r] * inv_scale + y0.
+struct ScoreEpilogue {
+  const int32_t *depth_dev;
+  int64_t rows_per_depth;
+  const int32_t *lb;
+  float *est;
+  float inv_scale;
+};
+int model_forward_score_dev(const fsp_model *m, const void *x, const int32_t *n_dev,
+                            int64_t max_n, const ScoreEpilogue &sc, hipStream_t s);
 int model_outputs(const fsp_model *m);
 int model_in_features(const fsp_model *m);
 

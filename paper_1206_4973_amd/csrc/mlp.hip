@@ -141,9 +141,10 @@ __device__ __forceinline__ bf16x8 relu_pack(f32x4 a, f32x4 b) {
 __global__ __launch_bounds__(256) void forward_kernel(
     const bf16 *__restrict__ X, int64_t N, const int32_t *__restrict__ n_dev,
     const float *__restrict__ P, const bf16 *__restrict__ E, float *__restrict__ Y,
-    int nout) {
+    int nout, const fspi::ScoreEpilogue sc) {
   if (n_dev) N = *n_dev;  // row count produced on the device
   if (N <= 0) return;
+  const int64_t sbase = sc.est ? (int64_t)(*sc.depth_dev + 1) * sc.rows_per_depth : 0;
   const int l = lane_id(), g = l >> 4, c = l & 15;
   const int wave = threadIdx.x >> 6;
   // A operands: lane (g, c) holds out feature 16 mt + c, K elements 8g .. 8g+7
@@ -193,9 +194,13 @@ __global__ __launch_bounds__(256) void forward_kernel(
 #pragma unroll
     for (int kt = 0; kt < kH / 32; ++kt) y = mma(w3[kt], h2[kt], y);
     if (row < N) {
+      if (sc.est) {
+        if (g == 0) sc.est[sbase + row] = (float)sc.lb[sbase + row] * sc.inv_scale + y[0];
+      } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (4 * g + i < nout) Y[row * nout + 4 * g + i] = y[i];
+        for (int i = 0; i < 4; ++i)
+          if (4 * g + i < nout) Y[row * nout + 4 * g + i] = y[i];
+      }
     }
   }
 }
@@ -504,8 +509,8 @@ int ensure_scratch(fsp_model *m, int64_t rows) {
 }  // namespace
 
 namespace fspi {
-int model_forward_dev(const fsp_model *m, const void *x, const int32_t *n_dev, int64_t max_n,
-                      float *y, hipStream_t s) {
+int forward_launch(const fsp_model *m, const void *x, const int32_t *n_dev, int64_t max_n,
+                   float *y, const ScoreEpilogue &sc, hipStream_t s) {
   if (max_n <= 0) return FSP_OK;
   // one workgroup per CU: every wave keeps all weights in registers and
   // streams 16-row tiles
@@ -514,9 +519,17 @@ int model_forward_dev(const fsp_model *m, const void *x, const int32_t *n_dev, i
   if (grid > (int64_t)m->cus) grid = (int64_t)m->cus;
   hipLaunchKernelGGL(forward_kernel, dim3((unsigned)grid), dim3(256), 0, s,
                      reinterpret_cast<const bf16 *>(x), max_n, n_dev, m->P, m->E, y,
-                     m->outputs);
+                     m->outputs, sc);
   FSP_HIP_TRY(hipGetLastError());
   return FSP_OK;
+}
+int model_forward_dev(const fsp_model *m, const void *x, const int32_t *n_dev, int64_t max_n,
+                      float *y, hipStream_t s) {
+  return forward_launch(m, x, n_dev, max_n, y, ScoreEpilogue{}, s);
+}
+int model_forward_score_dev(const fsp_model *m, const void *x, const int32_t *n_dev,
+                            int64_t max_n, const ScoreEpilogue &sc, hipStream_t s) {
+  return forward_launch(m, x, n_dev, max_n, nullptr, sc, s);
 }
 int model_forward(const fsp_model *m, const void *x, int64_t n, float *y, hipStream_t s) {
   return model_forward_dev(m, x, nullptr, n, y, s);

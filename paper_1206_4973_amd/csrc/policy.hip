@@ -148,18 +148,6 @@ FeatListFn list_fn(int m, std::integer_sequence<int, Ks...>) {
   return table[m - 2];
 }
 
-__global__ void score_kernel(BnbDesc *D, const int32_t *__restrict__ blb,
-                             float *__restrict__ bscore, int64_t cap,
-                             const float *__restrict__ Y, int nout, float inv_scale) {
-  const int count = D->feat_count;
-  const int d1 = D->depth + 1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t at = (int64_t)d1 * cap + i;
-    bscore[at] = (float)blb[at] * inv_scale + Y[i * nout];
-  }
-}
-
 // ---- best-K selection ------------------------------------------------------
 constexpr int kBins = 4096;
 constexpr float kBinScale = 2048.f;  // est in [0, 2)
@@ -381,12 +369,9 @@ int policy_enqueue_score(BnbState &S, hipStream_t s, int grid) {
                      S.stride, in->d_p, in->d_tot, in->n, in->mp, S.inv_scale,
                      reinterpret_cast<__bf16 *>(S.X));
   FSP_HIP_TRY(hipGetLastError());
-  int rc = model_forward_dev(S.model, S.X, &S.desc->feat_count, S.cap, S.Y, s);
-  if (rc != FSP_OK) return rc;
-  hipLaunchKernelGGL(score_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.blb, S.bscore, S.cap,
-                     S.Y, model_outputs(S.model), S.inv_scale);
-  FSP_HIP_TRY(hipGetLastError());
-  return FSP_OK;
+  // the forward pass writes est = bound / s + predicted gap itself
+  const ScoreEpilogue sc{&S.desc->depth, S.cap, S.blb, S.bscore, S.inv_scale};
+  return model_forward_score_dev(S.model, S.X, &S.desc->feat_count, S.cap, sc, s);
 }
 
 int policy_features(const fsp_instance *in, const uint8_t *nodes, const int32_t *lbs,
