@@ -283,10 +283,13 @@ int fsp_branch_and_bound(const fsp_instance *inst,
  * nodes bounded per second of search for this instance's shape: FSP_POOL_
  * AUTOTUNED searches of budget_s / #candidates seconds each (budget_s <= 0:
  * 0.25 s per candidate) over 2^14 .. min(resident threads, 2^20), each rated
- * on the batches after the first third of its search time (a search that
- * ends sooner is rated whole); a larger pool must win by more than 3 %.
+ * on the batches after the first third of its search time, stretched up to
+ * 8x until six batches were rated (a search that ends sooner is rated
+ * whole); a larger pool is taken unless it is more than 3 % slower than the
+ * best so far.
  * Cached per (device, n, m) for the life of
- * the process.  rate_out (may be NULL): the winner's nodes per second.
+ * the process.  rate_out (may be NULL): the best rate measured (nodes per
+ * second).
  */
 int fsp_autotune_pool(const fsp_instance *inst, double budget_s,
                       int64_t *pool_out, double *rate_out);

@@ -641,11 +641,17 @@ struct SampleSpec {
 // Search throughput over the batches that start after the first `skip`
 // fraction of the search loop's share of the time limit (the first batches of
 // a search from the root hold few nodes, the more so the larger the pool
-// target, and would bias a short measurement toward small pools).
+// target, and would bias a short measurement toward small pools).  The time
+// limit is stretched, up to max_s, until min_batches batches were counted, so
+// that shapes whose batches are long are rated on as many batches as cheap
+// ones.
 struct RateWindow {
   double skip;
+  int min_batches;
+  double max_s;
   int64_t nodes = 0;
   double secs = 0.0;
+  int batches = 0;
 };
 
 struct TuneEntry {
@@ -761,6 +767,7 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
     if (window && t0 >= t_loop0 + window->skip * (policy->time_limit_s - t_loop0)) {
       window->nodes += batch_nodes;
       window->secs += t1 - t0;
+      window->batches += 1;
     }
     if (h.improved) t_found = t1;
     if (log)
@@ -774,7 +781,9 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
       break;
     }
     if (h.done) break;
-    if (policy->time_limit_s > 0 && t1 >= policy->time_limit_s) {
+    const bool stretch = window && window->batches < window->min_batches &&
+                         t1 < window->max_s;
+    if (policy->time_limit_s > 0 && t1 >= policy->time_limit_s && !stretch) {
       status = 1;
       break;
     }
@@ -916,16 +925,20 @@ int fsp_autotune_pool(const fsp_instance *inst, double budget_s, int64_t *pool_o
     pol.time_limit_s = slice;
     pol.prune_rule = FSP_PRUNE_GE;
     fsp_result r{};
-    RateWindow win{1.0 / 3.0};
+    RateWindow win{1.0 / 3.0, 6, 8.0 * slice};
     const int rc = run_bnb(inst, &pol, 0, &r, nullptr, &win);
     if (rc != FSP_OK) return rc;
     // steady-state rate; a search that ends before the window counts whole
     const double rate = win.secs > 0 ? (double)win.nodes / win.secs
                         : r.t_search_s > 0 ? (double)r.nodes_bounded / r.t_search_s
                                            : 0.0;
-    if (rate > best_rate * 1.03) {  // a larger pool must win by more than 3 %
-      best_rate = rate;
+    // candidates come in increasing size; a larger pool is taken unless it
+    // is more than 3 % slower (short searches from the root understate
+    // large pools, whose first batches fill slowest).  The reported rate is
+    // the best measured.
+    if (rate >= best_rate * 0.97) {
       best = c;
+      best_rate = std::max(best_rate, rate);
     }
   }
   {

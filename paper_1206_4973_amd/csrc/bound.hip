@@ -21,21 +21,25 @@
 // whatever the order).  Every lane walks the same table position in
 // lock-step; the record {x = 256 (b - a), y = 256 (lag + b) + job} is a
 // wave-uniform LDS broadcast, and a lane whose node has the position's job
-// already scheduled must keep its z.  Two forms of that choice:
-//   n <= 32: the node's unscheduled set U is one register, and
+// already scheduled must keep its z.  Four forms of that choice:
+//   register (n <= 32): the node's unscheduled set U is one register, and
 //       alpha = bit job of U;  z = max(z + alpha*x, alpha*y)
 //     (v_bfe_u32, v_mad_i32_i24, v_mul_u32_u24, v_max_i32); alpha = 0 gives
 //     max(z, 0) = z.
-//   n > 32: the set spans several words, so each wave first writes, once per
-//     tile, the 64-bit mask of lanes that still have job j, for every j, into
-//     a scratch slot (one ballot per job), and the walk reads the position's
-//     mask with a scalar load (the job's slot offset comes from a second,
-//     scalar-read table):
+//   packed (n <= 32 and total work <= 32767): the same step for two nodes
+//     per lane in 16-bit halves, both sets interleaved in one 64-bit word
+//     (v_lshrrev_b64, v_and_b32, v_pk_mad_u16, v_pk_mul_lo_u16,
+//     v_pk_max_i16: five instructions for two nodes); see bound_tile.hpp.
+//   register64 (33..64 jobs): U in a 64-bit register pair, alpha taken with
+//     v_lshrrev_b64 by the job in y's low bits and v_and_b32.
+//   masks (n > 64): each wave first writes, once per tile, the 64-bit mask of
+//     lanes that still have job j, for every j, into a scratch slot (one
+//     ballot per job), and the walk reads the position's mask with a scalar
+//     load (the job's slot offset comes from a second, scalar-read table):
 //       t = max(z + x, y);  z = mask[job] ? t : z
-//     (v_add_u32, v_max_i32, v_cndmask_b32 on the SGPR pair).  This replaces
-//     an LDS read and a bit extract per position; for n <= 32 the register
-//     form is faster, as the scalar loads then cost more than the bit extract
-//     they save.
+//     (v_add_u32, v_max_i32, v_cndmask_b32 on the SGPR pair).  Up to 64 jobs
+//     the register forms are faster: the scalar loads miss the scalar cache
+//     more than the bit extract they save costs.
 // z is kept scaled by 256 with the job id riding in the low byte of y (so no
 // extra instruction is needed to split the record): for integers the high
 // part of max(256u + e, 256v + j) with 0 <= e, j < 256 is max(u, v), so
@@ -43,10 +47,11 @@
 //
 // Data layout: in LDS (per workgroup) the pair records (whole table, or chunk
 // by chunk when it does not fit), the padded p matrix for the prefix
-// recurrence and, for n > 32, the unscheduled-job words of every lane; in
-// global memory the mask offset of every table position (read by scalar
-// loads) and, for n > 32, the scratch of job-mask slots, one per wave of every
-// tile, each written once per launch.
+// recurrence (packed machine pairs in the packed form) and, for n > 32, the
+// unscheduled-job words of every lane; in global memory the mask offset of
+// every table position (read by scalar loads) and, for n > 64, the scratch
+// of job-mask slots, one per wave of every tile, each written once per
+// launch.
 #include <algorithm>
 #include <mutex>
 #include <thread>
