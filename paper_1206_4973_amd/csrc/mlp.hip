@@ -209,18 +209,25 @@ __global__ __launch_bounds__(256) void forward_kernel(
 // backward: per 64-row tile, recompute the forward, then every gradient.
 // dY [N][nout] fp32 is given.  Each workgroup writes one partial gradient
 // vector (fp32, kParams) to partial[blockIdx.x]; dX (optional) [N][kIn] fp32.
+// Every LDS row is padded by 16 bytes, so consecutive rows start 4 banks
+// apart: the 16-byte fragment reads of 8 rows then cover all 32 banks once,
+// and column-wise accesses conflict 8-way at most (64-way unpadded, where a
+// row of 64 bf16 is exactly one pass over the banks).
+constexpr int kPad = 8;
+constexpr int kLdIn = kIn + kPad, kLdRows = kRows + kPad, kLdH = kH + kPad;
 struct BwdLds {
-  bf16 Xr[kRows][kIn];    // x, row-major
-  bf16 Xt[kIn][kRows];    // x, transposed
-  bf16 A1[kRows][kH];     // h1 row-major, then dZ1 row-major
-  bf16 H1t[kH][kRows];    // h1 transposed
-  bf16 H2t[kH][kRows];    // h2 transposed
-  bf16 Z2r[kRows][kH];    // dZ2 row-major
-  bf16 Z2t[kH][kRows];    // dZ2 transposed
-  bf16 Z1t[kH][kRows];    // dZ1 transposed
-  bf16 DYt[kOut][kRows];  // dY transposed (bf16, padded outputs)
-  float dy[kRows][kOut];  // dY fp32 (padded)
+  bf16 Xr[kRows][kLdIn];     // x, row-major
+  bf16 Xt[kIn][kLdRows];     // x, transposed
+  bf16 A1[kRows][kLdH];      // h1 row-major, then dZ1 row-major
+  bf16 H1t[kH][kLdRows];     // h1 transposed
+  bf16 H2t[kH][kLdRows];     // h2 transposed
+  bf16 Z2r[kRows][kLdH];     // dZ2 row-major
+  bf16 Z2t[kH][kLdRows];     // dZ2 transposed
+  bf16 Z1t[kH][kLdRows];     // dZ1 transposed
+  bf16 DYt[kOut][kLdRows];   // dY transposed (bf16, padded outputs)
+  float dy[kRows][kOut + 1]; // dY fp32 (padded outputs, odd row stride)
 };
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void backward_kernel(
     const bf16 *__restrict__ X, int64_t N, const float *__restrict__ P,
@@ -264,18 +271,20 @@ __global__ __launch_bounds__(256) void backward_kernel(
     __syncthreads();
     // h1 = relu(x W1 + b1): wave w rows [16w, 16w+16)
     {
-      const bf16x8 xa = frag(&S.Xr[0][0], kIn, 16 * w, 0);
+      const bf16x8 xa = frag(&S.Xr[0][0], kLdIn, 16 * w, 0);
       for (int nt = 0; nt < kH / 16; ++nt) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mma(xa, frag(E + eW1t, kIn, nt * 16, 0), acc);
         const int col = nt * 16 + dcol();
         const float b = P[oB1 + col];
+        bf16x4 t;
         for (int i = 0; i < 4; ++i) {
-          const int r = 16 * w + drow(i);
           const bf16 v = (bf16)fmaxf(acc[i] + b, 0.f);
-          S.A1[r][col] = v;
-          S.H1t[col][r] = v;
+          S.A1[16 * w + drow(i)][col] = v;
+          t[i] = v;
         }
+        // rows 16w + 4g .. +3 of the transposed copy in one 8-byte store
+        *reinterpret_cast<bf16x4 *>(&S.H1t[col][16 * w + drow(0)]) = t;
       }
     }
     __syncthreads();
@@ -283,24 +292,25 @@ __global__ __launch_bounds__(256) void backward_kernel(
     for (int nt = 0; nt < kH / 16; ++nt) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
       for (int kt = 0; kt < kH / 32; ++kt)
-        acc = mma(frag(&S.A1[0][0], kH, 16 * w, kt * 32),
+        acc = mma(frag(&S.A1[0][0], kLdH, 16 * w, kt * 32),
                   frag(E + eW2t, kH, nt * 16, kt * 32), acc);
       const int col = nt * 16 + dcol();
       const float b = P[oB2 + col];
-      for (int i = 0; i < 4; ++i) {
-        const int r = 16 * w + drow(i);
-        S.H2t[col][r] = (bf16)fmaxf(acc[i] + b, 0.f);
-      }
+      bf16x4 t;
+      for (int i = 0; i < 4; ++i) t[i] = (bf16)fmaxf(acc[i] + b, 0.f);
+      *reinterpret_cast<bf16x4 *>(&S.H2t[col][16 * w + drow(0)]) = t;
     }
     __syncthreads();
     // dW3[c][o] += sum_r h2[r][c] dY[r][o]: wave w, c-tiles 2w, 2w+1; K = 64 rows
     for (int a = 0; a < 2; ++a)
       for (int kt = 0; kt < kRows / 32; ++kt)
-        gW3[a] = mma(frag(&S.H2t[0][0], kRows, 32 * w + 16 * a, kt * 32),
-                     frag(&S.DYt[0][0], kRows, 0, kt * 32), gW3[a]);
+        gW3[a] = mma(frag(&S.H2t[0][0], kLdRows, 32 * w + 16 * a, kt * 32),
+                     frag(&S.DYt[0][0], kLdRows, 0, kt * 32), gW3[a]);
     // dZ2[r][c] = (sum_o dY[r][o] W3[c][o]) * (h2 > 0)   (VALU: K = nout)
+    // consecutive lanes take consecutive rows of one column c: the transposed
+    // accesses are then contiguous, and W3's row c is one broadcast
     for (int e = tid; e < kRows * kH; e += 256) {
-      const int r = e / kH, c = e % kH;
+      const int r = e % kRows, c = e / kRows;
       float s = 0.f;
       for (int o = 0; o < nout; ++o) s += S.dy[r][o] * (float)E[eW3t + o * kH + c];
       const float g = (float)S.H2t[c][r] > 0.f ? s : 0.f;
@@ -313,28 +323,30 @@ __global__ __launch_bounds__(256) void backward_kernel(
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 8; ++b)
         for (int kt = 0; kt < kRows / 32; ++kt)
-          gW2[a][b] = mma(frag(&S.H1t[0][0], kRows, 32 * w + 16 * a, kt * 32),
-                          frag(&S.Z2t[0][0], kRows, 16 * b, kt * 32), gW2[a][b]);
+          gW2[a][b] = mma(frag(&S.H1t[0][0], kLdRows, 32 * w + 16 * a, kt * 32),
+                          frag(&S.Z2t[0][0], kLdRows, 16 * b, kt * 32), gW2[a][b]);
     // dZ1 = (dZ2 W2^T) * (h1 > 0): wave w rows [16w, 16w+16)
     {
       f32x4 acc[kH / 16];
       for (int nt = 0; nt < kH / 16; ++nt) {
         acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int kt = 0; kt < kH / 32; ++kt)
-          acc[nt] = mma(frag(&S.Z2r[0][0], kH, 16 * w, kt * 32),
+          acc[nt] = mma(frag(&S.Z2r[0][0], kLdH, 16 * w, kt * 32),
                         frag(E + eW2n, kH, nt * 16, kt * 32), acc[nt]);
       }
       __syncthreads();  // every wave is done reading A1 as h1 (layer 2) long ago;
                         // this barrier orders the masks below after all reads
       for (int nt = 0; nt < kH / 16; ++nt) {
         const int col = nt * 16 + dcol();
+        const bf16x4 h = *reinterpret_cast<const bf16x4 *>(&S.H1t[col][16 * w + drow(0)]);
+        bf16x4 t;
         for (int i = 0; i < 4; ++i) {
-          const int r = 16 * w + drow(i);
-          const float g = (float)S.H1t[col][r] > 0.f ? acc[nt][i] : 0.f;
+          const float g = (float)h[i] > 0.f ? acc[nt][i] : 0.f;
           const bf16 v = (bf16)g;
-          S.A1[r][col] = v;  // dZ1 row-major
-          S.Z1t[col][r] = v;
+          S.A1[16 * w + drow(i)][col] = v;  // dZ1 row-major
+          t[i] = v;
         }
+        *reinterpret_cast<bf16x4 *>(&S.Z1t[col][16 * w + drow(0)]) = t;
       }
     }
     __syncthreads();
@@ -342,14 +354,14 @@ __global__ __launch_bounds__(256) void backward_kernel(
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b)
         for (int kt = 0; kt < kRows / 32; ++kt)
-          gW1[a][b] = mma(frag(&S.Xt[0][0], kRows, 16 * a, kt * 32),
-                          frag(&S.Z1t[0][0], kRows, 32 * w + 16 * b, kt * 32), gW1[a][b]);
+          gW1[a][b] = mma(frag(&S.Xt[0][0], kLdRows, 16 * a, kt * 32),
+                          frag(&S.Z1t[0][0], kLdRows, 32 * w + 16 * b, kt * 32), gW1[a][b]);
     // dX = dZ1 W1^T: wave w rows [16w, 16w+16), 2 column tiles, K = 128
     if (dX) {
       for (int nt = 0; nt < kIn / 16; ++nt) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         for (int kt = 0; kt < kH / 32; ++kt)
-          acc = mma(frag(&S.A1[0][0], kH, 16 * w, kt * 32),
+          acc = mma(frag(&S.A1[0][0], kLdH, 16 * w, kt * 32),
                     frag(E + eW1n, kH, nt * 16, kt * 32), acc);
         const int col = nt * 16 + dcol();
         for (int i = 0; i < 4; ++i) {
@@ -358,12 +370,13 @@ __global__ __launch_bounds__(256) void backward_kernel(
         }
       }
     }
-    // bias gradients: column sums
+    // bias gradients: column sums, from the row-major copies (consecutive
+    // threads read consecutive columns)
     if (tid < kH) {
       float s1 = 0.f, s2 = 0.f;
       for (int r = 0; r < kRows; ++r) {
-        s1 += (float)S.Z1t[tid][r];
-        s2 += (float)S.Z2t[tid][r];
+        s1 += (float)S.A1[r][tid];
+        s2 += (float)S.Z2r[r][tid];
       }
       gb1 += s1;
       gb2 += s2;
