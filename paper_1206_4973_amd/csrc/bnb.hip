@@ -121,13 +121,24 @@ __global__ __launch_bounds__(64) void plan_kernel(BnbDesc *D, int32_t *bcount,
 // the chunks up to the one holding byte 1 + d are decoded for the scheduled
 // set and written back, patched, as the child; later bytes of a record are
 // never read at depth d + 1.
+//
+// With the learned ordering, a pool that takes only part of its depth was
+// partitioned into the scratch buffers (tnodes, tlb, tscore: the nodes that
+// stay first, the K taken ones on top).  The parents are then read from the
+// scratch, and this kernel also writes the nodes that stay back into the
+// bucket and clears the selection's histogram and counters for its next use.
 __global__ __launch_bounds__(kThreads) void branch_kernel(
-    BnbDesc *D, const uint8_t *__restrict__ bnodes,
-    const int32_t *__restrict__ blb, uint8_t *__restrict__ pool, int n,
-    int stride, int64_t cap, int rule) {
+    BnbDesc *D, uint8_t *__restrict__ bnodes, int32_t *__restrict__ blb,
+    uint8_t *__restrict__ pool, int n, int stride, int64_t cap, int rule,
+    const uint8_t *__restrict__ tnodes, const int32_t *__restrict__ tlb,
+    const float *__restrict__ tscore, float *__restrict__ bscore,
+    int32_t *__restrict__ hist, int learned) {
   if (!D->active) return;
   const int d = D->depth, u = n - d, K = D->parents, base = D->parent_base;
   const int ub = D->ub;
+  const bool sel = learned && K < D->sel_count;
+  const uint8_t *par_nodes = sel ? tnodes : bnodes + (int64_t)d * cap * stride;
+  const int32_t *par_lb = sel ? tlb : blb + (int64_t)d * cap;
   const int total = K * u;  // K <= cap and u <= 255: fits 32 bits
   const int gsz = gridDim.x * blockDim.x;
   const int last_chunk = (1 + d) >> 4;  // chunk holding the new job's byte
@@ -143,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
       const int q = slot / u;
       c = slot - q * u;
       p = base + q;
-      live = keeps(rule, blb[(int64_t)d * cap + p], ub);
+      live = keeps(rule, par_lb[p], ub);
       if (c == 0) {
         branched += live ? 1 : 0;
         pruned += live ? 0 : 1;
@@ -155,8 +166,7 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
     // hoisted out of the loop, one scalar register pair each
     int dd = d, lc = last_chunk;
     asm volatile("" : "+s"(dd), "+s"(lc));
-    const uint4 *src = reinterpret_cast<const uint4 *>(
-        bnodes + ((int64_t)d * cap + p) * stride);
+    const uint4 *src = reinterpret_cast<const uint4 *>(par_nodes + (int64_t)p * stride);
     uint4 *dst = reinterpret_cast<uint4 *>(pool + (size_t)pos * stride);
     if (n <= 32) {
       // scheduled set in one register; byte 1 + d <= 32 lies in chunk 0..2
@@ -228,6 +238,17 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
   }
   block_total(&D->nodes_branched, branched, s_cnt);
   block_total(&D->nodes_pruned, pruned, s_cnt);
+  if (!sel) return;
+  const int64_t at0 = (int64_t)d * cap;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < base; i += gsz) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(tnodes + (int64_t)i * stride);
+    uint4 *dst = reinterpret_cast<uint4 *>(bnodes + (at0 + i) * stride);
+    for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
+    blb[at0 + i] = tlb[i];
+    bscore[at0 + i] = tscore[i];
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kSelBins; i += gsz) hist[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) D->sel_lo = D->sel_hi = D->sel_tie = 0;
 }
 
 // ---- prune + compaction ----------------------------------------------------
@@ -496,7 +517,8 @@ int BnbState::enqueue_iteration(hipStream_t s) {
   int rc;
   if (model && (rc = policy_enqueue_select(*this, s, grid)) != FSP_OK) return rc;
   hipLaunchKernelGGL(branch_kernel, dim3(grid), dim3(kThreads), 0, s, desc,
-                     bnodes, blb, pool, n, stride, cap, rule);
+                     bnodes, blb, pool, n, stride, cap, rule, tnodes, tlb, tscore, bscore,
+                     hist, model ? 1 : 0);
   FSP_HIP_TRY(hipGetLastError());
   Prefilter pf;
   if (prefilter) {

@@ -74,6 +74,9 @@ __device__ __forceinline__ void wave_total(int64_t *counter, int v) {
 
 // Iteration descriptor and counters, in device memory; the host reads a copy
 // once per batch of pools.
+// bins of the histogram of scores that the best-K selection builds
+constexpr int kSelBins = 4096;
+
 struct BnbDesc {
   int32_t active;       // the current iteration has parents
   int32_t depth;        // parent depth of the current pool
@@ -87,7 +90,7 @@ struct BnbDesc {
   int32_t improved;     // UB improved since the host last cleared this
   int32_t root_lb;
   int32_t sel_count;    // nodes of the parent depth before the plan took K
-  int32_t sel_T, sel_need, sel_lo, sel_hi, sel_tie;  // best-K selection
+  int32_t sel_lo, sel_hi, sel_tie;  // best-K selection slot counters
   int32_t feat_count;   // nodes scored after the last prune
   int32_t log_count;    // training samples logged (may exceed the capacity)
   int64_t nodes_bounded, nodes_branched, nodes_pruned, leaves, pools;

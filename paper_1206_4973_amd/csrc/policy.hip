@@ -149,7 +149,7 @@ FeatListFn list_fn(int m, std::integer_sequence<int, Ks...>) {
 }
 
 // ---- best-K selection ------------------------------------------------------
-constexpr int kBins = 4096;
+constexpr int kBins = kSelBins;
 constexpr float kBinScale = 2048.f;  // est in [0, 2)
 
 __device__ __forceinline__ int est_bin(float e) {
@@ -185,53 +185,65 @@ __global__ __launch_bounds__(256) void sel_hist_kernel(const BnbDesc *D,
     if (sh[b]) atomicAdd(&hist[b], sh[b]);
 }
 
-// one workgroup of 256 threads; clears the histogram for its next use
-__global__ __launch_bounds__(256) void sel_thresh_kernel(BnbDesc *D,
-                                                         int32_t *__restrict__ hist) {
-  if (!sel_needed(D)) return;
+// The bin T of the K-th smallest score and how many nodes of bin T the pool
+// takes, from the histogram: each thread sums 16 bins, a block-wide scan of
+// the sums finds the thread whose bins hold the K-th node, and that thread
+// walks them.  Every workgroup of the partition computes it (same input, same
+// result), which saves a launch.  Every thread of the workgroup calls it.
+__device__ void sel_threshold(const int32_t *__restrict__ hist, int K, int &T, int &need) {
   __shared__ int part[256];
-  const int t = threadIdx.x;
+  __shared__ int s_T, s_need;
   constexpr int per = kBins / 256;
-  int s = 0;
-  for (int b = 0; b < per; ++b) s += hist[t * per + b];
-  part[t] = s;
-  __syncthreads();
+  const int t = threadIdx.x;
+  int h[per];
+  int sum = 0;
+#pragma unroll
+  for (int b = 0; b < per; ++b) {
+    h[b] = hist[t * per + b];
+    sum += h[b];
+  }
   if (t == 0) {
-    const int K = D->parents;
-    int cum = 0, T = kBins - 1, above = 0;
-    for (int c = 0; c < 256; ++c) {
-      if (cum + part[c] >= K) {
-        int cb = cum;
-        for (int b = 0; b < per; ++b) {
-          const int h = hist[c * per + b];
-          if (cb + h >= K) {
-            T = c * per + b;
-            above = cb;
-            break;
-          }
-          cb += h;
-        }
+    s_T = kBins - 1;
+    s_need = K;
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  const int incl = part[t], excl = incl - sum;
+  if (excl < K && incl >= K) {  // exactly one thread: the counts sum to >= K
+    int cb = excl;
+#pragma unroll
+    for (int b = 0; b < per; ++b) {
+      if (cb + h[b] >= K) {
+        s_T = t * per + b;
+        s_need = K - cb;
         break;
       }
-      cum += part[c];
+      cb += h[b];
     }
-    D->sel_T = T;
-    D->sel_need = K - above;
-    D->sel_lo = 0;
-    D->sel_hi = 0;
-    D->sel_tie = 0;
   }
   __syncthreads();
-  for (int b = 0; b < per; ++b) hist[t * per + b] = 0;
+  T = s_T;
+  need = s_need;
 }
 
-__global__ void sel_partition_kernel(BnbDesc *D, const uint8_t *__restrict__ bnodes,
-                                     const int32_t *__restrict__ blb,
-                                     const float *__restrict__ bscore, int64_t cap,
-                                     int stride, uint8_t *__restrict__ tnodes,
-                                     int32_t *__restrict__ tlb, float *__restrict__ tscore) {
+// Partition of the depth by the threshold into the scratch buffers: the
+// nodes that stay first, in slot order, then the K taken ones on top (the
+// positions the plan gave to the pool).  The branch kernel reads the taken
+// ones from there and writes the others back.
+__global__ __launch_bounds__(256) void sel_partition_kernel(
+    BnbDesc *D, const int32_t *__restrict__ hist, const uint8_t *__restrict__ bnodes,
+    const int32_t *__restrict__ blb, const float *__restrict__ bscore, int64_t cap, int stride,
+    uint8_t *__restrict__ tnodes, int32_t *__restrict__ tlb, float *__restrict__ tscore) {
   if (!sel_needed(D)) return;
-  const int count = D->sel_count, K = D->parents, T = D->sel_T, need = D->sel_need;
+  const int count = D->sel_count, K = D->parents;
+  int T, need;
+  sel_threshold(hist, K, T, need);
   const int64_t base = (int64_t)D->depth * cap;
   __shared__ int s_cnt[256 / 64 + 1];
   // uniform rounds: every thread takes part in the workgroup-level slots
@@ -252,24 +264,6 @@ __global__ void sel_partition_kernel(BnbDesc *D, const uint8_t *__restrict__ bno
     for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
     tlb[pos] = blb[base + i];
     tscore[pos] = e;
-  }
-}
-
-__global__ void sel_copyback_kernel(const BnbDesc *D, uint8_t *__restrict__ bnodes,
-                                    int32_t *__restrict__ blb, float *__restrict__ bscore,
-                                    int64_t cap, int stride, const uint8_t *__restrict__ tnodes,
-                                    const int32_t *__restrict__ tlb,
-                                    const float *__restrict__ tscore) {
-  if (!sel_needed(D)) return;
-  const int count = D->sel_count;
-  const int64_t base = (int64_t)D->depth * cap;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint4 *src = reinterpret_cast<const uint4 *>(tnodes + i * stride);
-    uint4 *dst = reinterpret_cast<uint4 *>(bnodes + (base + i) * stride);
-    for (int q = 0; q < stride / 16; ++q) dst[q] = src[q];
-    blb[base + i] = tlb[i];
-    bscore[base + i] = tscore[i];
   }
 }
 
@@ -351,13 +345,12 @@ __global__ void label_kernel(const uint8_t *__restrict__ nodes, const int32_t *_
 
 // ---- host helpers ------------------------------------------------------------
 int policy_enqueue_select(BnbState &S, hipStream_t s, int grid) {
+  // the branch kernel that follows reads the taken nodes from the scratch,
+  // writes the others back and clears the histogram and the slot counters
   hipLaunchKernelGGL(sel_hist_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.bscore, S.cap,
                      S.hist);
-  hipLaunchKernelGGL(sel_thresh_kernel, dim3(1), dim3(256), 0, s, S.desc, S.hist);
-  hipLaunchKernelGGL(sel_partition_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.bnodes,
-                     S.blb, S.bscore, S.cap, S.stride, S.tnodes, S.tlb, S.tscore);
-  hipLaunchKernelGGL(sel_copyback_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.bnodes,
-                     S.blb, S.bscore, S.cap, S.stride, S.tnodes, S.tlb, S.tscore);
+  hipLaunchKernelGGL(sel_partition_kernel, dim3(grid), dim3(256), 0, s, S.desc, S.hist,
+                     S.bnodes, S.blb, S.bscore, S.cap, S.stride, S.tnodes, S.tlb, S.tscore);
   FSP_HIP_TRY(hipGetLastError());
   return FSP_OK;
 }
