@@ -199,11 +199,14 @@ def batch_workload(steps, warmup) -> dict:
             "identical_bounds": bool(same), "peak_TOPs": INT32_PEAK_TOPS}
 
 
-def large_workload(steps, warmup, bnb_time, prefilter=False) -> dict:
+def large_workload(steps, warmup, bnb_time, prefilter=False, shapes=None, kinds=None,
+                   log_dir=None) -> dict:
     """50x20 (seed 5000) and 200x20 (seed 5001): pools of 2^22 nodes (depth
     uniform 1..n-1), then time-limited searches (plain adaptive, batched,
     batched + learned when a 20-machine policy is present) reporting the best
-    UB, the smallest pending bound, the gap and nodes per second."""
+    UB, the smallest pending bound, the gap and nodes per second.  `shapes`
+    and `kinds` select a subset; with `log_dir`, every search writes its
+    per-batch log there (progress of long runs)."""
     import torch
     from paper_1206_4973_amd import fsp, inputs, train_policy
     out = {"workload": "large: 50x20 and 200x20", "bnb_time_limit_s": bnb_time,
@@ -212,6 +215,8 @@ def large_workload(steps, warmup, bnb_time, prefilter=False) -> dict:
     model = train_policy.load(model_path) if os.path.exists(model_path) else None
     stream = torch.cuda.current_stream()
     for n, m, seed in ((50, 20, 5000), (200, 20, 5001)):
+        if shapes and f"{n}x{m}" not in shapes:
+            continue
         p = inputs.instance(n, m, seed)
         inst = fsp.Instance(p)
         pool = inputs.random_pool(n, 1 << 22, 1, n - 1, seed + 500000)
@@ -224,9 +229,12 @@ def large_workload(steps, warmup, bnb_time, prefilter=False) -> dict:
                                  "nodes_per_s": len(pool) / t,
                                  "frac": ops / t / 1e12 / INT32_PEAK_TOPS}}
         del nodes, lb
-        kinds = ["adaptive", "autotuned"] + (["learned"] if model is not None else [])
-        for kind in kinds:
+        run = ["adaptive", "autotuned"] + (["learned"] if model is not None else [])
+        for kind in [k for k in run if not kinds or k in kinds]:
             kw = {"model": model} if kind == "learned" else {}
+            if log_dir:
+                os.makedirs(log_dir, exist_ok=True)
+                kw["log_path"] = os.path.join(log_dir, f"{n}x{m}_{kind}.jsonl")
             r = fsp.branch_and_bound(inst, kind, time_limit=bnb_time, prefilter=prefilter,
                                      **kw)
             progress(f"large {n}x{m} {kind}: UB {r.makespan}, open bound {r.open_lb}, "
@@ -293,6 +301,13 @@ def main() -> int:
                          "bnb: only the B&B time-to-optimum leg")
     ap.add_argument("--bnb-time", type=float, default=60.0,
                     help="time limit of each search of the large workload (s)")
+    ap.add_argument("--large-shapes", default=None,
+                    help="with --workload large: comma-separated subset of 50x20,200x20")
+    ap.add_argument("--large-kinds", default=None,
+                    help="with --workload large: comma-separated subset of "
+                         "adaptive,autotuned,learned")
+    ap.add_argument("--bnb-log-dir", default=None,
+                    help="with --workload large: directory for the per-batch search logs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -319,7 +334,10 @@ def main() -> int:
         print(json.dumps(batch_workload(args.steps, args.warmup)), flush=True)
         return 0
     if args.workload == "large":
-        print(json.dumps(large_workload(args.steps, args.warmup, args.bnb_time, args.prefilter)),
+        split = lambda v: v.split(",") if v else None
+        print(json.dumps(large_workload(args.steps, args.warmup, args.bnb_time, args.prefilter,
+                                        split(args.large_shapes), split(args.large_kinds),
+                                        args.bnb_log_dir)),
               flush=True)
         return 0
     if args.workload == "policy":
