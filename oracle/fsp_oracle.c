@@ -31,8 +31,8 @@
  * Everything is integer.  Intermediate values are held in int64 so that no
  * overflow question arises for any instance the library accepts.
  *
- * Readings where the paper is silent are listed in the design doc; the ones that
- * change results are: the prune rule (LB >= UB eliminates, with a switch for
+ * Where the paper is silent this oracle takes readings of its own; the ones
+ * that change results are: the prune rule (LB >= UB eliminates, with a switch for
  * the literal "greater than"), children generated in ascending job id, the
  * Johnson tie-break (by job id, which cannot change the bound's value), and a
  * malformed node (duplicate id, id >= n, depth > n) bounding to -1.
