@@ -39,6 +39,20 @@ MUTATIONS = [
     ("one_machine_head_ignores_front", "if (front[h] > head) head = front[h];", ""),
     ("one_machine_head_includes_machine_h", "if (g < h) before += p[job * m + g];",
      "if (g <= h) before += p[job * m + g];"),
+    ("neh_total_ascending", "while (b >= 0 && (tot[idx[b]] < tot[x] ||",
+     "while (b >= 0 && (tot[idx[b]] > tot[x] ||"),
+    ("neh_tie_larger_id_first", "(tot[idx[b]] == tot[x] && idx[b] > x))) {",
+     "(tot[idx[b]] == tot[x] && idx[b] < x))) {"),
+    ("neh_latest_position_on_ties", "if (best < 0 || c < best) {\n        best = c;\n        best_pos = pos;",
+     "if (best < 0 || c <= best) {\n        best = c;\n        best_pos = pos;"),
+    ("bnb_leaves_not_counted", "st->leaves++;", ""),
+    ("bnb_leaf_not_counted_pruned", "memcpy(perm_out, child + 1, (size_t)n);\n          st->found = 1;\n        } else {\n          st->nodes_pruned++;",
+     "memcpy(perm_out, child + 1, (size_t)n);\n          st->found = 1;\n        } else {\n          (void)0;"),
+    ("bnb_root_not_counted_branched", "st->nodes_branched++;", "if (d > 0) st->nodes_branched++;"),
+    ("bnb_pruned_root_not_counted", "  } else {\n    st->nodes_pruned++;\n  }\n  uint8_t child",
+     "  } else {\n    (void)0;\n  }\n  uint8_t child"),
+    ("bnb_unkept_child_not_counted", "        ++nk;\n      } else {\n        st->nodes_pruned++;",
+     "        ++nk;\n      } else {\n        (void)0;"),
     ("one_machine_largest_tail", "if (min_after < 0 || after < min_after) min_after = after;",
      "if (min_after < 0 || after > min_after) min_after = after;"),
 ]
@@ -59,6 +73,7 @@ PINS = [
     pins.test_one_machine_bound_never_exceeds_any_completion,
     pins.test_one_machine_bound_exact_with_zero_or_one_job_left,
     pins.test_one_machine_bound_identical_jobs_closed_form,
+    pins.test_identical_jobs_search_counters_closed_form,
 ]
 
 
@@ -69,11 +84,16 @@ def _run_pins():
             f(O)
         except AssertionError:
             failed.append(f.__name__)
-    for case in pins._load_hand_cases():
+    for case in pins._bound_cases():
         try:
             pins.test_hand_worked_examples(O, case)
         except AssertionError:
             failed.append("hand:" + case["name"])
+    for case in pins._neh_cases():
+        try:
+            pins.test_hand_worked_neh(O, case)
+        except AssertionError:
+            failed.append("neh:" + case["name"])
     for rule in (0, 1):
         try:
             pins.test_critical_tree_is_order_independent(O, rule)

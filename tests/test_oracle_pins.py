@@ -251,7 +251,15 @@ def _load_hand_cases():
     return cases
 
 
-@pytest.mark.parametrize("case", _load_hand_cases(), ids=lambda c: c["name"])
+def _bound_cases():
+    return [c for c in _load_hand_cases() if "lb" in c]
+
+
+def _neh_cases():
+    return [c for c in _load_hand_cases() if "neh_perm" in c]
+
+
+@pytest.mark.parametrize("case", _bound_cases(), ids=lambda c: c["name"])
 def test_hand_worked_examples(orc, case):
     p, pre = case["p"], case.get("prefix", [])
     assert p.shape == (case["n"][0], case["m"][0])
@@ -293,6 +301,17 @@ def test_bnb_tiny_config_nine_jobs_five_machines(orc):
     assert orc.lower_bound(p, []) <= opt <= orc.neh(p)[0]
 
 
+@pytest.mark.parametrize("case", _neh_cases(), ids=lambda c: c["name"])
+def test_hand_worked_neh(orc, case):
+    """NEH worked by hand with a tie on total work and ties between insertion
+    positions: the schedule and its makespan."""
+    p = case["p"]
+    assert p.shape == (case["n"][0], case["m"][0])
+    c, perm = orc.neh(p)
+    assert [int(x) for x in perm] == case["neh_perm"]
+    assert c == case["neh_makespan"][0]
+
+
 def test_neh_is_a_valid_upper_bound(orc):
     rng = np.random.default_rng(14)
     for _ in range(30):
@@ -308,27 +327,45 @@ def test_neh_is_a_valid_upper_bound(orc):
         assert orc.neh(p)[0] == orc.brute_force(p)[0]
 
 
-def _critical_tree_count(orc, p, opt, rule):
-    """Bounded-node count of any complete search started with UB = opt,
-    enumerated breadth-first: a node is branched iff it is incomplete and
-    kept (LB < opt for rule 0, LB <= opt for rule 1); every child of a
-    branched node is bounded once."""
+def _critical_tree_counts(orc, p, opt, rule):
+    """Counters of any complete search started with UB = opt, enumerated
+    breadth-first.  No schedule beats opt, so UB never changes: a node is
+    branched iff it is incomplete and kept (LB < opt for rule 0, LB <= opt
+    for rule 1), every child of a branched node is bounded once, a complete
+    child is a leaf and is eliminated (it cannot be strictly better than
+    opt), and every other child that is not kept is eliminated.  The root is
+    bounded, and eliminated when it is not kept."""
     n = p.shape[0]
     keep = (lambda lb: lb < opt) if rule == 0 else (lambda lb: lb <= opt)
-    count = 1
-    frontier = [[]] if keep(orc.lower_bound(p, [])) else []
+    c = {"bounded": 1, "branched": 0, "pruned": 0, "leaves": 0}
+    if keep(orc.lower_bound(p, [])) and n > 0:
+        frontier = [[]]
+    else:
+        frontier = []
+        c["pruned"] += 1
     while frontier:
         nxt = []
         for pre in frontier:
+            c["branched"] += 1
             for j in range(n):
                 if j in pre:
                     continue
                 child = pre + [j]
-                count += 1
-                if len(child) < n and keep(orc.lower_bound(p, child)):
+                c["bounded"] += 1
+                if len(child) == n:
+                    c["leaves"] += 1
+                    c["pruned"] += 1
+                elif keep(orc.lower_bound(p, child)):
                     nxt.append(child)
+                else:
+                    c["pruned"] += 1
         frontier = nxt
-    return count
+    return c
+
+
+def _stats_counts(st):
+    return {"bounded": st.nodes_bounded, "branched": st.nodes_branched,
+            "pruned": st.nodes_pruned, "leaves": st.leaves}
 
 
 @pytest.mark.parametrize("rule", [0, 1])
@@ -340,7 +377,31 @@ def test_critical_tree_is_order_independent(orc, rule):
         opt, _ = orc.brute_force(p)
         c, _, st = orc.bnb(p, opt, rule)
         assert c == opt and st.found == 0 and st.complete == 1
-        assert st.nodes_bounded == _critical_tree_count(orc, p, opt, rule)
+        assert _stats_counts(st) == _critical_tree_counts(orc, p, opt, rule)
+
+
+def test_identical_jobs_search_counters_closed_form(orc):
+    """Identical jobs: every schedule has the makespan opt = sum(c) + (n-1)
+    max(c), and every node's bound is opt (the root's is, by the closed form,
+    and bounds never decrease along a branch nor exceed a completion).  With
+    the rule "eliminate LB >= UB" the root is eliminated at once; with the
+    paper's "eliminate LB > UB" nothing is eliminated before the leaves, so
+    the whole tree is searched: n!/(n-d)! nodes at depth d, every one of the
+    n! leaves bounded and eliminated."""
+    rng = np.random.default_rng(22)
+    for _ in range(8):
+        n, m = int(rng.integers(1, 7)), int(rng.integers(2, 6))
+        cvec = rng.integers(1, 30, size=m).astype(np.int32)
+        p = np.tile(cvec, (n, 1)).astype(np.int32)
+        opt = int(cvec.sum()) + (n - 1) * int(cvec.max())
+        c, _, st = orc.bnb(p, 0, 0)
+        assert c == opt and st.found == 0 and st.complete == 1
+        assert _stats_counts(st) == {"bounded": 1, "branched": 0, "pruned": 1, "leaves": 0}
+        c, _, st = orc.bnb(p, 0, 1)
+        assert c == opt and st.found == 0 and st.complete == 1
+        level = [math.factorial(n) // math.factorial(n - d) for d in range(n + 1)]
+        assert _stats_counts(st) == {"bounded": sum(level), "branched": sum(level[:n]),
+                                     "pruned": level[n], "leaves": level[n]}
 
 
 def test_pool_bounding_matches_single_node_calls(orc):
