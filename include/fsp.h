@@ -279,6 +279,25 @@ int fsp_branch_and_bound(const fsp_instance *inst,
                          fsp_result *out);
 
 /*
+ * fsp_adaptive_schedule -- the pool sizes that FSP_POOL_ADAPTIVE (the paper's
+ * dynamic parameter tuning, Sec. III, Algorithm 1) sets, as a function of the
+ * efficiencies it measures; host only, no device work.  Batch i (of
+ * nb_iterations pools) runs with targets_out[i] children per pool and then
+ * reports efficiency[i] (nodes bounded per second of that batch; the search
+ * logs both per batch, see log_path).  The schedule starts at
+ * threads_per_block x cus, doubles after every batch while the size stays
+ * within min(max_threads, max_pool) (max_pool <= 0: max_threads), then
+ * tries the midpoints between the best size and the ends of [best/2,
+ * 2 best] (two rounds, the interval narrowed around the best after each),
+ * sizes rounded to multiples of threads_per_block, and keeps the size of
+ * the best efficiency from then on (a strictly higher efficiency replaces
+ * the best).  efficiency, targets_out: host arrays of `batches` entries.
+ */
+int fsp_adaptive_schedule(int32_t threads_per_block, int32_t cus, int64_t max_threads,
+                          int64_t max_pool, const double *efficiency, int32_t batches,
+                          int64_t *targets_out);
+
+/*
  * fsp_autotune_pool -- the pool size (children per pool) that maximises
  * nodes bounded per second of search for this instance's shape: FSP_POOL_
  * AUTOTUNED searches of budget_s / #candidates seconds each (budget_s <= 0:

@@ -792,12 +792,14 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
       window->batches += 1;
     }
     if (h.improved) t_found = t1;
+    const double eff = t1 > t0 ? (double)batch_nodes / (t1 - t0) : 0.0;
     if (log)
       std::fprintf(log,
                    "{\"t\": %.6f, \"pool_target\": %lld, \"nodes_bounded\": %lld, "
-                   "\"batch_nodes\": %lld, \"ub\": %d, \"pools\": %lld, \"done\": %d}\n",
+                   "\"batch_nodes\": %lld, \"eff\": %.17g, \"ub\": %d, \"pools\": %lld, "
+                   "\"done\": %d}\n",
                    t1, (long long)target, (long long)h.nodes_bounded,
-                   (long long)batch_nodes, h.ub, (long long)h.pools, h.done);
+                   (long long)batch_nodes, eff, h.ub, (long long)h.pools, h.done);
     if (h.overflow) {
       rc = FSP_ENOMEM;
       break;
@@ -809,8 +811,7 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
       status = 1;
       break;
     }
-    if (kind == FSP_POOL_ADAPTIVE && t1 > t0)
-      ap.observe((double)batch_nodes / (t1 - t0));
+    if (kind == FSP_POOL_ADAPTIVE && t1 > t0) ap.observe(eff);
     // clear the "improved" flag for the next batch
     if (h.improved &&
         hipMemsetAsync(&S.desc->improved, 0, sizeof(int32_t), S.stream) != hipSuccess) {
@@ -895,6 +896,21 @@ int fsp_neh(const fsp_instance *inst, uint8_t *perm_out, int32_t *makespan_out) 
   const int64_t c = neh_host(inst->p_host, inst->n, inst->m, perm);
   if (perm_out) std::copy(perm.begin(), perm.end(), perm_out);
   if (makespan_out) *makespan_out = (int32_t)c;
+  return FSP_OK;
+}
+
+int fsp_adaptive_schedule(int32_t threads_per_block, int32_t cus, int64_t max_threads,
+                          int64_t max_pool, const double *efficiency, int32_t batches,
+                          int64_t *targets_out) {
+  if (threads_per_block < 1 || cus < 1 || max_threads < 1 || batches < 0 ||
+      (batches > 0 && (!efficiency || !targets_out)))
+    return FSP_EINVAL;
+  AdaptivePolicy ap;
+  ap.init(threads_per_block, cus, max_threads, max_pool > 0 ? max_pool : max_threads);
+  for (int32_t i = 0; i < batches; ++i) {
+    targets_out[i] = ap.current;
+    ap.observe(efficiency[i]);
+  }
   return FSP_OK;
 }
 

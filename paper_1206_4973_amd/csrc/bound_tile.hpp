@@ -783,8 +783,9 @@ __device__ __forceinline__ void node_state_p16(
   // ---- 1. both prefixes: front recurrence and prefix column sums ----
   for (int c = 0; c * 16 <= dmax; ++c) {
     uint32_t wa[4], wb[4];
-    record_chunk(pa, c, c * 16 <= dA, aligned, stride, wa);
-    record_chunk(pb, c, c * 16 <= dB, aligned, stride, wb);
+    // a lane past the end of the pool (la / lbv false) reads nothing
+    record_chunk(pa, c, la && c * 16 <= dA, aligned, stride, wa);
+    record_chunk(pb, c, lbv && c * 16 <= dB, aligned, stride, wb);
 #pragma unroll
     for (int b = 0; b < 16; ++b) {
       const int pos = c * 16 + b;

@@ -117,6 +117,8 @@ def lib() -> ctypes.CDLL:
     L.fsp_autotune_pool.argtypes = [P, ctypes.c_double, ctypes.POINTER(i64),
                                     ctypes.POINTER(ctypes.c_double)]
     L.fsp_autotune_pool.restype = ctypes.c_int
+    L.fsp_adaptive_schedule.argtypes = [i32, i32, i64, i64, P, i32, P]
+    L.fsp_adaptive_schedule.restype = ctypes.c_int
     L.fsp_policy_samples.argtypes = [P, ctypes.POINTER(_Policy), i32, i64, ctypes.c_double,
                                      ctypes.c_uint64, P, P, ctypes.POINTER(i64),
                                      ctypes.POINTER(_Result)]
@@ -287,6 +289,19 @@ def autotune_pool(inst: Instance, budget_s: float = 0.0):
     _check(lib().fsp_autotune_pool(inst.handle, float(budget_s), ctypes.byref(pool),
                                    ctypes.byref(rate)), "fsp_autotune_pool")
     return int(pool.value), float(rate.value)
+
+
+def adaptive_schedule(efficiency, cus: int, max_threads: int, max_pool: int = 0,
+                      threads_per_block: int = 256) -> list:
+    """Pool targets Algorithm 1 sets batch by batch for the given measured
+    efficiencies (fsp_adaptive_schedule; host only)."""
+    eff = np.ascontiguousarray(efficiency, dtype=np.float64)
+    out = np.zeros(len(eff), dtype=np.int64)
+    _check(lib().fsp_adaptive_schedule(int(threads_per_block), int(cus), int(max_threads),
+                                       int(max_pool), eff.ctypes.data_as(ctypes.c_void_p),
+                                       len(eff), out.ctypes.data_as(ctypes.c_void_p)),
+           "fsp_adaptive_schedule")
+    return [int(x) for x in out]
 
 
 def policy_samples(inst: Instance, max_samples: int, sample_prob: float, seed: int = 0,

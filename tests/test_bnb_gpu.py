@@ -240,3 +240,29 @@ def test_prefilter_reaches_the_brute_force_optimum(fsp, orc, rule):
                                        **({"fixed_pool": 50} if kind == "autotuned" else {}))
             assert res.status == 0 and res.makespan == opt
             check_schedule(orc, p, res)
+
+
+def test_adaptive_pool_trajectory_follows_algorithm_1(fsp, tmp_path):
+    """Algorithm 1 inside a real search: the per-batch log gives the pool size
+    in force and the efficiency measured; the first size is 256 threads x
+    #compute units, every size doubles the previous one while the doubling
+    lasts, and replaying the logged efficiencies through the schedule
+    (fsp_adaptive_schedule, pinned on the CPU) gives the logged sizes."""
+    import json
+    inst = fsp.Instance(I.instance(20, 10, 4519))
+    log = tmp_path / "adaptive.jsonl"
+    res = fsp.branch_and_bound(inst, "adaptive", time_limit=3.0, log_path=str(log))
+    rows = [json.loads(line) for line in open(log)]
+    say(f"adaptive 20x10: {len(rows)} batches, status {res.status}")
+    assert len(rows) >= 6
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    max_threads = cus * torch.cuda.get_device_properties(0).max_threads_per_multi_processor
+    targets = [r["pool_target"] for r in rows]
+    effs = [r["eff"] for r in rows]
+    assert targets[0] == 256 * cus
+    k = 1
+    while k < len(targets) and targets[k] == 2 * targets[k - 1]:
+        k += 1
+    assert targets[k - 1] * 2 > max_threads or k == len(targets)
+    assert fsp.adaptive_schedule(effs, cus, max_threads) == targets
+    assert res.final_pool == targets[-1]
