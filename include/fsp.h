@@ -44,6 +44,8 @@ extern "C" {
 #define FSP_ENOMEM (-2)       /* device or host allocation failed           */
 #define FSP_EDEVICE (-3)      /* a HIP call failed                          */
 #define FSP_EUNSUPPORTED (-4) /* valid input outside what this library serves */
+#define FSP_ESCRATCH (-5)     /* pool beyond the fixed scratch of
+                                 fsp_bound_pool_noalloc                     */
 
 /* Bound written for a malformed node: depth > n, a job id >= n, or a job
  * scheduled twice. */
@@ -99,6 +101,7 @@ enum { FSP_PATH_REGISTER = 0, FSP_PATH_PACKED = 1, FSP_PATH_MASKS = 2,
        FSP_PATH_REGISTER64 = 3 };
 int fsp_instance_path(const fsp_instance *inst, int32_t *path);
 
+
 /* ---- pool bounding (Sec. III: one launch bounds a whole pool) --------- */
 
 /* A pool of nodes in device memory.  Record i starts at data + i*stride:
@@ -128,6 +131,29 @@ typedef struct {
  */
 int fsp_bound_pool(const fsp_nodes *nodes, int64_t count, int32_t *lb_out,
                    void *stream);
+
+/*
+ * fsp_bound_pool_noalloc -- fsp_bound_pool for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): same arguments, same bounds, but it never calls
+ * hipMalloc, hipFree or any other allocating routine.  The job-mask walk of
+ * instances with n > 64 takes its scratch from a fixed device array of
+ * 32 MiB that the library holds on every device it runs on until the process
+ * ends (found with hipGetSymbolAddress on the first call per device); up to
+ * 64 jobs no scratch is needed and any count is served.  A pool of more than
+ * fsp_noalloc_max_count(n) nodes returns FSP_ESCRATCH before any device work
+ * is queued.  All calls on one device share the array: calls that overlap on
+ * one device (different streams, or host threads, without ordering between
+ * them) race on it and give undefined bounds; calls ordered on one stream are
+ * safe.  Nothing in the array needs clearing between calls (every slot is
+ * written before it is read).
+ */
+int fsp_bound_pool_noalloc(const fsp_nodes *nodes, int64_t count, int32_t *lb_out,
+                           void *stream);
+
+/* Largest pool fsp_bound_pool_noalloc serves for n jobs (INT64_MAX when no
+ * scratch is needed, i.e. n <= 64; 0 for n outside 1..255). */
+int64_t fsp_noalloc_max_count(int32_t n);
 
 /*
  * fsp_bound_pool_one_machine -- lb_out[i] = the one-machine bound of record

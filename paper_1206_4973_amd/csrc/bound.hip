@@ -278,14 +278,18 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
   const size_t lds = lds_bytes(a.I.n, a.I.mp, a.I.npad, a.I.ppc, form == kFormMasks);
 
   // device attributes and per-kernel occupancy are queried once per
-  // (device, kernel, LDS size) and cached for this thread
+  // (device, kernel, LDS size) and cached for this thread, in a fixed table
+  // (no host allocation on the launch path; a full table is refilled from
+  // its start)
   struct Occ {
     int dev;
     BoundFn fn;
     size_t lds;
     int per_cu;
   };
-  static thread_local std::vector<Occ> occ_cache;
+  constexpr int kOccSlots = 64;
+  static thread_local Occ occ_cache[kOccSlots];
+  static thread_local int occ_used = 0, occ_next = 0;
   static thread_local int cached_dev = -1, cached_cus = 0;
   int dev = 0;
   FSP_HIP_TRY(hipGetDevice(&dev));
@@ -295,15 +299,19 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
     cached_dev = dev;
   }
   int per_cu = -1;
-  for (const Occ &o : occ_cache)
+  for (int i = 0; i < occ_used; ++i) {
+    const Occ &o = occ_cache[i];
     if (o.dev == dev && o.fn == fn && o.lds == lds) per_cu = o.per_cu;
+  }
   if (per_cu < 0) {
     FSP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds));
     FSP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu, reinterpret_cast<const void *>(fn), kBlock, lds));
-    occ_cache.push_back({dev, fn, lds, per_cu});
+    occ_cache[occ_next] = {dev, fn, lds, per_cu};
+    occ_next = (occ_next + 1) % kOccSlots;
+    if (occ_used < kOccSlots) ++occ_used;
   }
   if (per_cu < 1) return FSP_EUNSUPPORTED;
   int64_t grid = (int64_t)per_cu * cached_cus;
@@ -314,6 +322,68 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
 }
 
 }  // namespace fspi
+
+// ---- bounding without allocation ------------------------------------------
+// The job-mask walk (n > 64) needs scratch that grows with the pool.  For
+// callers that cannot allocate, fsp_bound_pool_noalloc takes it from this
+// fixed array instead: every device the library runs on holds one copy for
+// the life of the process.  In host code `scratch` is only a stand-in for the
+// symbol; its device address, per device, comes from hipGetSymbolAddress on
+// the first call made with that device current.
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device.
+int noalloc_scratch(void **out) {
+  int dev = 0;
+  FSP_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return FSP_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    FSP_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return FSP_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FSP_OK;
+}
+
+}  // namespace
+
+extern "C" int64_t fsp_noalloc_max_count(int32_t n) {
+  if (n < 1 || n > kMaxJobs) return 0;
+  if (!uses_job_masks(n)) return INT64_MAX;
+  // whole tiles of kBlock nodes, each kBlock / 64 wave slots
+  const int64_t per_tile = (int64_t)(kBlock / 64) * mask_slot_bytes(n);
+  return (int64_t)(kNoAllocScratchBytes / (size_t)per_tile) * kBlock;
+}
+
+extern "C" int fsp_bound_pool_noalloc(const fsp_nodes *nodes, int64_t count,
+                                      int32_t *lb_out, void *stream) {
+  if (!nodes || !nodes->inst || count < 0) return FSP_EINVAL;
+  if (count == 0) return FSP_OK;
+  if (!nodes->data || !lb_out) return FSP_EINVAL;
+  if (nodes->stride < nodes->inst->n + 1) return FSP_EINVAL;
+  const fsp_instance *inst = nodes->inst;
+  void *ptr = nullptr;
+  if (uses_job_masks(inst->n)) {
+    if (count > fsp_noalloc_max_count(inst->n) ||
+        bound_scratch_bytes(inst->n, count) > kNoAllocScratchBytes)
+      return FSP_ESCRATCH;
+    const int rc = noalloc_scratch(&ptr);
+    if (rc != FSP_OK) return rc;
+  }
+  // with scratch given (or none needed) the launch allocates nothing
+  return fspi::launch_bound(inst, nodes->data, nodes->stride, count, lb_out,
+                            reinterpret_cast<hipStream_t>(stream), nullptr, ptr);
+}
 
 extern "C" int fsp_bound_pool_one_machine(const fsp_nodes *nodes, int64_t count,
                                           int32_t *lb_out, void *stream) {

@@ -198,6 +198,8 @@ const char *fsp_status_string(int32_t status) {
     case FSP_ENOMEM: return "out of memory";
     case FSP_EDEVICE: return "HIP device error";
     case FSP_EUNSUPPORTED: return "unsupported input for this library";
+    case FSP_ESCRATCH:
+      return "pool larger than the fixed scratch of the no-allocation entry point";
     default: return "unknown status";
   }
 }

@@ -22,6 +22,7 @@ FSP_EINVAL = -1
 FSP_ENOMEM = -2
 FSP_EDEVICE = -3
 FSP_EUNSUPPORTED = -4
+FSP_ESCRATCH = -5
 FSP_LB_INVALID = -1
 
 _lib = None
@@ -92,6 +93,10 @@ def lib() -> ctypes.CDLL:
     L.fsp_instance_info.restype = ctypes.c_int
     L.fsp_bound_pool_one_machine.argtypes = [ctypes.POINTER(_Nodes), i64, P, P]
     L.fsp_bound_pool_one_machine.restype = ctypes.c_int
+    L.fsp_bound_pool_noalloc.argtypes = [ctypes.POINTER(_Nodes), i64, P, P]
+    L.fsp_bound_pool_noalloc.restype = ctypes.c_int
+    L.fsp_noalloc_max_count.argtypes = [i32]
+    L.fsp_noalloc_max_count.restype = i64
     L.fsp_instance_path.argtypes = [P, P]
     L.fsp_instance_path.restype = ctypes.c_int
     L.fsp_bound_pool.argtypes = [ctypes.POINTER(_Nodes), i64, P, P]
@@ -212,6 +217,18 @@ class Instance:
 
         Asynchronous on ``stream`` (default: torch's current stream)."""
         return _bound_call(self, "fsp_bound_pool", nodes, out, stream)
+
+    def bound_pool_noalloc(self, nodes: torch.Tensor, out: torch.Tensor,
+                           stream=None) -> torch.Tensor:
+        """fsp_bound_pool without any device allocation (fsp_bound_pool_noalloc):
+        ``out`` must be given; pools above ``noalloc_max_count`` raise."""
+        if out is None:
+            raise ValueError("bound_pool_noalloc needs a caller-provided out tensor")
+        return _bound_call(self, "fsp_bound_pool_noalloc", nodes, out, stream)
+
+    @property
+    def noalloc_max_count(self) -> int:
+        return int(lib().fsp_noalloc_max_count(self.n))
 
     def bound_pool_one_machine(self, nodes: torch.Tensor, out: torch.Tensor | None = None,
                                stream=None) -> torch.Tensor:
