@@ -8,7 +8,13 @@ in Johnson order, max), through the C ABI.
 
 Prints one JSON line with the throughput, the roofline of the bounding kernel
 (algorithmic integer operations per launch over its measured duration, against
-the INT32 vector peak) and the CPU oracle timed on a sample of the same pool.
+the vector peak of the arithmetic the kernel runs: packed 16-bit, two
+operations per lane per clock, when the instance takes the two-nodes-per-lane
+form), the same pool on the one-node-per-lane 32-bit form, a sweep of pool
+sizes 2^16..2^22, the CPU oracle timed on a sample of the same pool (one core
+and all host cores), and the branch-and-bound legs: time to a proven optimum
+on 50 held-out 20x10 instances (plain adaptive vs batched vs batched +
+learned) and a time-limited search of the 20x20 instance from NEH.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
@@ -27,10 +33,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "bounded subproblems/sec (n=20,m=20) + B&B time-to-optimum, learned vs plain"
 
-# MI355X: 256 compute units x 4 SIMDs x 16 lanes, one 32-bit integer
-# operation per lane per clock at 2.4 GHz.
+# MI355X: 256 compute units x 4 SIMDs x 16 lanes at 2.4 GHz.  A 32-bit
+# integer instruction does one operation per lane per clock; a packed 16-bit
+# instruction (v_pk_*) does two.
 CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
 INT32_PEAK_TOPS = CUS * SIMDS * LANES * CLOCK / 1e12  # 39.3
+PK16_PEAK_TOPS = 2 * INT32_PEAK_TOPS  # 78.6
 
 
 def algorithmic_ops(depths: np.ndarray, n: int, m: int) -> int:
@@ -63,22 +71,33 @@ def measured_traffic() -> float | None:
         return None
 
 
-def cpu_baseline(p, pool, target_s: float = 15.0) -> dict:
+def _oracle_rate(p, pool, threads: int, target_s: float):
+    """(nodes/s, sample size, seconds) of the oracle on the first nodes of
+    `pool`, sized from a short probe to take about target_s seconds."""
     from oracle import oracle as O
+    probe = pool[:max(256, 512 * threads)]
+    t0 = time.perf_counter()
+    O.bound_pool(p, probe, nthreads=threads)
+    per_node = (time.perf_counter() - t0) / len(probe)
+    k = int(min(len(pool), max(len(probe), target_s / max(per_node, 1e-9))))
+    t0 = time.perf_counter()
+    O.bound_pool(p, pool[:k], nthreads=threads)
+    dt = time.perf_counter() - t0
+    return k / dt, k, dt
+
+
+def cpu_baseline(p, pool, target_s: float = 10.0, one_core_s: float = 5.0) -> dict:
+    """The oracle on all host cores (the reported baseline) and on one core
+    (the paper's CPU baseline is a sequential search on one core)."""
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    probe = pool[:4096]
-    t0 = time.perf_counter()
-    O.bound_pool(p, probe, nthreads=cores)
-    dt = time.perf_counter() - t0
-    per_node = dt / len(probe)
-    k = int(min(len(pool), max(8192, target_s / max(per_node, 1e-9))))
-    sample = pool[:k]
-    t0 = time.perf_counter()
-    O.bound_pool(p, sample, nthreads=cores)
-    dt = time.perf_counter() - t0
-    return {"value": k / dt, "unit": "nodes/s", "cores": cores, "kind": "oracle",
+    rate, k, dt = _oracle_rate(p, pool, cores, target_s)
+    rate1, k1, dt1 = _oracle_rate(p, pool, 1, one_core_s)
+    return {"value": rate, "unit": "nodes/s", "cores": cores, "kind": "oracle",
             "sample": f"first {k} nodes of the benchmark pool, {cores} threads, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "one_core": {"value": rate1, "unit": "nodes/s", "cores": 1,
+                         "sample": f"first {k1} nodes of the benchmark pool, one thread, "
+                                   f"{dt1:.1f} s"}}
 
 
 # Held-out 20x10 instances: every seed of 4500..4549 (the policy network was
@@ -193,6 +212,71 @@ def timed(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
+def pool_sweep(inst, nodes, out, depths, n, m, stream, peak, lo=16, hi=22) -> list:
+    """The first 2^k nodes of the benchmark pool, k = lo..hi (the synthetic
+    analogue of the paper's sweep of pool sizes): kernel time per launch
+    (HIP events on the launch stream), nodes/s and the roofline fraction."""
+    rows = []
+    for k in range(lo, hi + 1):
+        c = 1 << k
+        if c > nodes.shape[0]:
+            break
+        sub, o = nodes[:c], out[:c]
+        steps = max(5, min(200, (1 << 25) // c))
+        t = timed(lambda: inst.bound_pool(sub, o, stream=stream), steps, 2, stream)
+        ops = algorithmic_ops(depths[:c], n, m)
+        rows.append({"log2_pool": k, "nodes": c, "steps": steps, "kernel_ms": t * 1e3,
+                     "nodes_per_s": c / t, "achieved_TOPs": ops / t / 1e12,
+                     "frac": ops / t / 1e12 / peak})
+        progress(f"sweep 2^{k}: {t * 1e3:.3f} ms, {c / t / 1e9:.2f} G nodes/s")
+    return rows
+
+
+def timed_searches(inst, kinds, time_limit, model=None, prefilter=False, log_dir=None,
+                   tag="") -> dict:
+    """Searches of one instance from the NEH schedule with a time limit, one
+    per kind; each reports the best UB, the smallest pending bound (a lower
+    bound on the optimum), the gap and nodes per second."""
+    from paper_1206_4973_amd import fsp
+    rec = {}
+    for kind in kinds:
+        kw = {"model": model} if kind == "learned" else {}
+        if kind == "learned" and model is None:
+            continue
+        if log_dir:
+            os.makedirs(log_dir, exist_ok=True)
+            kw["log_path"] = os.path.join(log_dir, f"{tag}_{kind}.jsonl")
+        r = fsp.branch_and_bound(inst, kind, time_limit=time_limit, prefilter=prefilter, **kw)
+        progress(f"{tag} {kind}: UB {r.makespan}, open bound {r.open_lb}, "
+                 f"{r.nodes_bounded} nodes in {r.t_total_s:.1f} s")
+        rec[kind] = {"best_ub": r.makespan, "open_lb": r.open_lb,
+                     "gap": (r.makespan - r.open_lb) / r.makespan,
+                     "proven": r.status == 0, "t_total_s": r.t_total_s,
+                     "nodes": r.nodes_bounded,
+                     "nodes_per_s": r.nodes_bounded / max(r.t_search_s, 1e-9),
+                     "t_found_s": r.t_found_s, "pool": r.final_pool}
+    return rec
+
+
+def bnb20_leg(time_limit, kinds=None) -> dict:
+    """The 20x20 benchmark instance (seed 2000): full searches from the NEH
+    upper bound with the paper's adaptive pool size (Algorithm 1), the
+    batched search with the autotuned pool, and the batched + learned search
+    (20-machine network), each with a time limit; a search that proves the
+    optimum reports it, one that does not reports its gap."""
+    from paper_1206_4973_amd import fsp, inputs, train_policy
+    model_path = os.path.join(ROOT, "paper_1206_4973_amd", "policy_m20.npz")
+    model = train_policy.load(model_path) if os.path.exists(model_path) else None
+    inst = fsp.Instance(inputs.instance(20, 20, 2000))
+    neh_ub, _ = fsp.neh(inst)
+    fsp.autotune_pool(inst)  # per-shape tuning, cached; not part of a run
+    out = {"instance": "20x20, seed 2000", "neh_ub": neh_ub, "time_limit_s": time_limit}
+    out.update(timed_searches(inst, kinds or ["adaptive", "autotuned", "learned"],
+                              time_limit, model, tag="bnb 20x20"))
+    inst.close()
+    return out
+
+
 def batch_workload(steps, warmup) -> dict:
     """64 instances (n in {20,50,100} x m in {5,10,20}, times uniform [1,99],
     seeds 3000+i), each with a pool of 2^e nodes, e uniform in 10..18 (depth
@@ -261,21 +345,9 @@ def large_workload(steps, warmup, bnb_time, prefilter=False, shapes=None, kinds=
                                  "nodes_per_s": len(pool) / t,
                                  "frac": ops / t / 1e12 / INT32_PEAK_TOPS}}
         del nodes, lb
-        run = ["adaptive", "autotuned"] + (["learned"] if model is not None else [])
-        for kind in [k for k in run if not kinds or k in kinds]:
-            kw = {"model": model} if kind == "learned" else {}
-            if log_dir:
-                os.makedirs(log_dir, exist_ok=True)
-                kw["log_path"] = os.path.join(log_dir, f"{n}x{m}_{kind}.jsonl")
-            r = fsp.branch_and_bound(inst, kind, time_limit=bnb_time, prefilter=prefilter,
-                                     **kw)
-            progress(f"large {n}x{m} {kind}: UB {r.makespan}, open bound {r.open_lb}, "
-                     f"{r.nodes_bounded} nodes in {r.t_total_s:.1f} s")
-            rec[kind] = {"best_ub": r.makespan, "open_lb": r.open_lb,
-                         "gap": (r.makespan - r.open_lb) / r.makespan,
-                         "proven": r.status == 0, "nodes": r.nodes_bounded,
-                         "nodes_per_s": r.nodes_bounded / max(r.t_search_s, 1e-9),
-                         "t_found_s": r.t_found_s, "pool": r.final_pool}
+        run = [k for k in ("adaptive", "autotuned", "learned") if not kinds or k in kinds]
+        rec.update(timed_searches(inst, run, bnb_time, model, prefilter, log_dir,
+                                  tag=f"{n}x{m}"))
         out[f"{n}x{m}"] = rec
         inst.close()
     return out
@@ -333,6 +405,8 @@ def main() -> int:
                          "bnb: only the B&B time-to-optimum leg")
     ap.add_argument("--bnb-limit", type=float, default=BNB_TIME_LIMIT,
                     help="time limit of each held-out 20x10 search (s)")
+    ap.add_argument("--bnb20-limit", type=float, default=8.0,
+                    help="time limit of each search of the 20x20 instance (s)")
     ap.add_argument("--bnb-seeds", type=int, default=0,
                     help="with --workload bnb: only the first K held-out seeds")
     ap.add_argument("--bnb-time", type=float, default=60.0,
@@ -393,6 +467,8 @@ def main() -> int:
     out = torch.empty(count, dtype=torch.int32, device="cuda")
     ops = algorithmic_ops(pool[:, 0], n, m)
     stream = torch.cuda.current_stream()
+    packed = inst.bound_path == "packed"
+    peak = PK16_PEAK_TOPS if packed else INT32_PEAK_TOPS
 
     for _ in range(args.warmup):
         inst.bound_pool(nodes, out, stream=stream)
@@ -413,6 +489,17 @@ def main() -> int:
     ms_per_step = wall / args.steps * 1e3
     value = count / (wall / args.steps)
     achieved = ops / kernel_s / 1e12
+    progress(f"pool 20x20 2^{args.log2_pool}: {kernel_s * 1e3:.3f} ms per launch "
+             f"({inst.bound_path} form)")
+
+    # the same pool on the one-node-per-lane 32-bit form
+    inst32 = fsp.Instance(p, packed=False)
+    t32 = timed(lambda: inst32.bound_pool(nodes, out, stream=stream), args.steps,
+                args.warmup, stream)
+    inst32.close()
+    progress(f"pool 20x20 2^{args.log2_pool} on the 32-bit form: {t32 * 1e3:.3f} ms")
+    sweep = pool_sweep(inst, nodes, out, pool[:, 0], n, m, stream, peak,
+                       hi=args.log2_pool)
     res = {
         "metric": METRIC,
         "value": value,
@@ -424,7 +511,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "int16x2" if packed else "int32",
         "data": "synthetic",
         "config": {
             "workload": "pool bounding: 20 jobs x 20 machines, times uniform [1,99] "
@@ -434,9 +521,12 @@ def main() -> int:
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
-            "peak": INT32_PEAK_TOPS,
+            "peak": peak,
             "unit": "TOP/s",
-            "frac": achieved / INT32_PEAK_TOPS,
+            "frac": achieved / peak,
+            "peak_basis": ("packed 16-bit vector ops: 256 CUs x 64 lanes x 2 per clock x "
+                           "2.4 GHz" if packed else
+                           "32-bit vector integer ops: 256 CUs x 64 lanes x 2.4 GHz"),
             "traffic": measured_traffic(),
             "kernel": {"packed": f"bound_kernel_p16<{m}> (two nodes per lane, 16-bit)",
                        "register": f"bound_kernel<{m}> (one node per lane)",
@@ -444,11 +534,20 @@ def main() -> int:
             "kernel_ms": kernel_s * 1e3,
             "algorithmic_ops_per_launch": ops,
         },
+        "int32_register_form": {
+            "kernel": f"bound_kernel<{m}> (one node per lane, 32-bit)",
+            "kernel_ms": t32 * 1e3, "nodes_per_s": count / t32,
+            "achieved_TOPs": ops / t32 / 1e12, "peak_TOPs": INT32_PEAK_TOPS,
+            "frac": ops / t32 / 1e12 / INT32_PEAK_TOPS,
+        },
+        "pool_sweep": sweep,
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(p, pool)
+        progress("cpu baseline done")
     if not args.no_bnb:
         res["bnb_time_to_optimum"] = bnb_leg(HELD_OUT_SEEDS, args.bnb_limit)
+        res["bnb_20x20"] = bnb20_leg(args.bnb20_limit)
     print(json.dumps(res), flush=True)
     return 0
 

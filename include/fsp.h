@@ -76,6 +76,19 @@ typedef struct fsp_instance fsp_instance;
 int fsp_load_instance(const int32_t *p_host, int32_t n, int32_t m,
                       fsp_instance **out);
 
+/* Load flags of fsp_load_instance_ex.  FSP_LOAD_ONE_NODE_PER_LANE keeps an
+ * instance that would take the packed two-nodes-per-lane form (see
+ * fsp_instance_path) on the one-node-per-lane 32-bit register form; the
+ * bounds are identical, only the arithmetic differs (for comparing the two
+ * forms on one pool). */
+#define FSP_LOAD_ONE_NODE_PER_LANE 1
+
+/* fsp_load_instance with load flags (0 or FSP_LOAD_* or-ed together; any
+ * other bit is FSP_EINVAL).  fsp_load_instance(p, n, m, out) is
+ * fsp_load_instance_ex(p, n, m, 0, out). */
+int fsp_load_instance_ex(const int32_t *p_host, int32_t n, int32_t m,
+                         int32_t flags, fsp_instance **out);
+
 /* Release the instance and its device tables (NULL is a no-op).  The caller
  * must have finished all stream work that uses it. */
 int fsp_free_instance(fsp_instance *inst);

@@ -206,9 +206,15 @@ const char *fsp_status_string(int32_t status) {
 
 int fsp_load_instance(const int32_t *p_host, int32_t n, int32_t m,
                       fsp_instance **out) {
+  return fsp_load_instance_ex(p_host, n, m, 0, out);
+}
+
+int fsp_load_instance_ex(const int32_t *p_host, int32_t n, int32_t m,
+                         int32_t flags, fsp_instance **out) {
   if (!out) return FSP_EINVAL;
   *out = nullptr;
   if (!p_host || n < 1 || m < 2) return FSP_EINVAL;
+  if (flags & ~FSP_LOAD_ONE_NODE_PER_LANE) return FSP_EINVAL;
   if (n > kMaxJobs || m > kMaxMachines) return FSP_EUNSUPPORTED;
   int64_t total = 0;
   for (int j = 0; j < n; ++j) {
@@ -232,7 +238,7 @@ int fsp_load_instance(const int32_t *p_host, int32_t n, int32_t m,
   in->P = npairs(m);
   in->npad = round_up(n, 4);
   in->wide = n > 32 ? 1 : 0;
-  in->p16 = (n <= 32 && total <= 32767) ? 1 : 0;
+  in->p16 = (n <= 32 && total <= 32767 && !(flags & FSP_LOAD_ONE_NODE_PER_LANE)) ? 1 : 0;
   in->p_host.assign(p_host, p_host + (size_t)n * m);
   if (hipGetDevice(&in->device) != hipSuccess) {
     delete in;

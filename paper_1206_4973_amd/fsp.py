@@ -28,6 +28,9 @@ FSP_LB_INVALID = -1
 _lib = None
 
 
+LOAD_ONE_NODE_PER_LANE = 1  # FSP_LOAD_ONE_NODE_PER_LANE
+
+
 class FspError(RuntimeError):
     def __init__(self, rc: int, what: str):
         self.rc = rc
@@ -87,6 +90,8 @@ def lib() -> ctypes.CDLL:
     L.fsp_status_string.restype = ctypes.c_char_p
     L.fsp_load_instance.argtypes = [P, i32, i32, ctypes.POINTER(P)]
     L.fsp_load_instance.restype = ctypes.c_int
+    L.fsp_load_instance_ex.argtypes = [P, i32, i32, i32, ctypes.POINTER(P)]
+    L.fsp_load_instance_ex.restype = ctypes.c_int
     L.fsp_free_instance.argtypes = [P]
     L.fsp_free_instance.restype = ctypes.c_int
     L.fsp_instance_info.argtypes = [P, P, P, P]
@@ -167,9 +172,11 @@ def _stream_handle(stream) -> ctypes.c_void_p:
 
 
 class Instance:
-    """An instance loaded on the current device (fsp_load_instance)."""
+    """An instance loaded on the current device (fsp_load_instance_ex).
+    packed=False keeps an instance that qualifies for the two-nodes-per-lane
+    16-bit form on the one-node-per-lane 32-bit form (same bounds)."""
 
-    def __init__(self, p):
+    def __init__(self, p, packed: bool = True):
         if isinstance(p, torch.Tensor):
             p = p.detach().cpu().numpy()
         p = np.ascontiguousarray(p, dtype=np.int32)
@@ -178,8 +185,9 @@ class Instance:
         self.p = p
         self.n, self.m = int(p.shape[0]), int(p.shape[1])
         h = ctypes.c_void_p()
-        _check(lib().fsp_load_instance(p.ctypes.data_as(ctypes.c_void_p), self.n, self.m,
-                                       ctypes.byref(h)), "fsp_load_instance")
+        flags = 0 if packed else LOAD_ONE_NODE_PER_LANE
+        _check(lib().fsp_load_instance_ex(p.ctypes.data_as(ctypes.c_void_p), self.n, self.m,
+                                          flags, ctypes.byref(h)), "fsp_load_instance_ex")
         self._h = h
         dev = ctypes.c_int32()
         _check(lib().fsp_instance_info(h, None, None, ctypes.byref(dev)), "fsp_instance_info")

@@ -92,3 +92,16 @@ def test_other_entry_points_reject_null(L):
     L.fsp_bound_pool_one_machine.argtypes = [ctypes.c_void_p, ctypes.c_int64,
                                              ctypes.c_void_p, ctypes.c_void_p]
     assert L.fsp_bound_pool_one_machine(None, 10, None, None) == -1
+
+
+def test_load_flags_checked_before_device_work(L):
+    """fsp_load_instance_ex rejects unknown flag bits with FSP_EINVAL before it
+    touches a device (so this runs without a GPU) and leaves *out NULL."""
+    L.fsp_load_instance_ex.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
+    p = np.ones((4, 3), np.int32)
+    for flags in (2, 4, -1, 1 << 30):
+        h = ctypes.c_void_p(1)
+        rc = L.fsp_load_instance_ex(p.ctypes.data_as(ctypes.c_void_p), 4, 3, flags,
+                                    ctypes.byref(h))
+        assert rc == -1 and not h.value

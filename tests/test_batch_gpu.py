@@ -12,6 +12,12 @@ from paper_1206_4973_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 
+def host_threads() -> int:
+    """Host threads for the oracle (the CPU share of one GPU, at most 16)."""
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
@@ -90,8 +96,8 @@ def test_graph_replay_sees_new_node_contents(fsp, orc):
 
 def test_batching_config_64_instances(fsp, orc):
     """64 instances, n in {20,50,100} x m in {5,10,20}, pools of 2^e nodes with e
-    uniform in 10..18: every segment equals its single-pool launch; a sample of
-    each segment equals the oracle."""
+    uniform in 10..18 (about 3.1 M nodes): every node of every segment equals
+    the oracle, and every segment equals its single-pool launch."""
     shapes = [(n, m) for n in (20, 50, 100) for m in (5, 10, 20)]
     rng = np.random.default_rng(3000)
     exps = [int(e) for e in rng.integers(10, 19, size=64)]
@@ -112,7 +118,9 @@ def test_batching_config_64_instances(fsp, orc):
         ref = inst.bound_pool(nodes)
         torch.cuda.synchronize()
         assert np.array_equal(got, ref.cpu().numpy()), i
-        idx = np.unique(np.concatenate([rng.integers(0, len(pool), size=48),
-                                        [0, len(pool) - 1]]))
-        assert np.array_equal(got[idx], orc.bound_pool(p, pool[idx], nthreads=8)), i
+        want = orc.bound_pool(p, pool, nthreads=host_threads())
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, (i, bad[:10], got[bad[:10]], want[bad[:10]])
+        if i % 8 == 7:
+            say(f"  segments 0..{i} equal the oracle")
     b.close()

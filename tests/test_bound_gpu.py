@@ -1,10 +1,12 @@
 """Parity of the HIP pool-bounding kernel with the CPU oracle, through the C ABI.
 
 Bounds are integers: every comparison is bit-exact.  Small pools span several
-256-node tiles and a ragged tail and are compared element by element; the
-full-size pools (2^22 nodes, the size the benchmark times) are compared on a
-random sample of nodes plus properties that hold for every node.
+256-node tiles and a ragged tail and are compared element by element; so are
+the benchmarked 20x20 pool of 2^22 nodes (on both the packed and the 32-bit
+form) and a 50x20 pool of 2^20 nodes.  The 200x20 pool of 2^22 nodes is
+compared on a random sample plus a property that holds for every node.
 """
+import os
 import sys
 
 import numpy as np
@@ -158,32 +160,134 @@ def test_branching_shaped_pool(fsp, orc):
     assert np.array_equal(gpu_bounds(fsp, inst, pool), orc.bound_pool(p, pool, 8))
 
 
-FULL = [(20, 20, 2000, 1, 19), (50, 20, 5000, 1, 49), (200, 20, 5001, 1, 199)]
+def host_threads() -> int:
+    """Host threads for the oracle (the CPU share of one GPU, at most 16)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
-@pytest.mark.parametrize("n,m,seed,dlo,dhi", FULL, ids=["20x20", "50x20", "200x20"])
-def test_full_size_pool_sampled(fsp, orc, n, m, seed, dlo, dhi):
-    """2^22-node pools (one GPU's share): a random sample is compared with the
-    oracle node by node; every node must bound at least the root's bound
-    (the bound never decreases along a branch) and none may be invalid."""
+_ORACLE_CACHE = {}
+
+
+def oracle_full(orc, key, p, pool):
+    """The oracle's bounds of a whole pool, computed once per module."""
+    if key not in _ORACLE_CACHE:
+        say(f"  oracle on all {len(pool)} nodes, {host_threads()} threads")
+        _ORACLE_CACHE[key] = orc.bound_pool(p, pool, nthreads=host_threads())
+    return _ORACLE_CACHE[key]
+
+
+EVERY = [(20, 20, 2000, 22), (50, 20, 5000, 20)]
+
+
+@pytest.mark.parametrize("n,m,seed,log2", EVERY, ids=["20x20_2p22", "50x20_2p20"])
+def test_full_size_pool_every_node(fsp, orc, n, m, seed, log2):
+    """The benchmarked 20x20 pool of 2^22 nodes (packed form, the launch the
+    benchmark times) and a 50x20 pool of 2^20 nodes (64-bit register form):
+    every node equals the oracle."""
+    count = 1 << log2
+    say(f"full size n={n} m={m}: generating {count} nodes")
+    p = I.instance(n, m, seed)
+    pool = I.random_pool(n, count, 1, n - 1, seed + 500000)
+    inst = fsp.Instance(p)
+    say(f"  bounding on the GPU ({inst.bound_path} form)")
+    got = gpu_bounds(fsp, inst, pool)
+    want = oracle_full(orc, (n, m, seed, log2), p, pool)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad[:10], got[bad[:10]], want[bad[:10]])
+
+
+def test_full_size_pool_register_form(fsp, orc):
+    """The same 2^22-node 20x20 pool on the one-node-per-lane 32-bit form
+    (the packed form switched off at load): every node equals the oracle."""
+    n, m, seed, log2 = 20, 20, 2000, 22
+    p = I.instance(n, m, seed)
+    pool = I.random_pool(n, 1 << log2, 1, n - 1, seed + 500000)
+    inst = fsp.Instance(p, packed=False)
+    assert inst.bound_path == "register"
+    say("full size 20x20 on the register form")
+    got = gpu_bounds(fsp, inst, pool)
+    want = oracle_full(orc, (n, m, seed, log2), p, pool)
+    assert np.array_equal(got, want)
+
+
+def test_full_size_pool_sampled_200x20(fsp, orc):
+    """200x20, 2^22 nodes (job-mask form): the oracle is too slow for every
+    node, so 2048 random nodes and the last 37 are compared with it; every
+    node bounds at least the root (the bound never decreases along a
+    branch) and none is invalid."""
+    n, m, seed = 200, 20, 5001
     count = 1 << 22
     say(f"full size n={n} m={m}: generating {count} nodes")
     p = I.instance(n, m, seed)
-    pool = I.random_pool(n, count, dlo, dhi, seed + 500000)
+    pool = I.random_pool(n, count, 1, n - 1, seed + 500000)
     inst = fsp.Instance(p)
     say("  bounding on the GPU")
     got = gpu_bounds(fsp, inst, pool)
     rng = np.random.default_rng(seed)
-    k = 4096 if n <= 50 else 512
-    idx = np.sort(rng.choice(count, size=k, replace=False))
-    say(f"  oracle on {k} sampled nodes")
-    want = orc.bound_pool(p, pool[idx], nthreads=8)
+    idx = np.sort(rng.choice(count, size=2048, replace=False))
+    idx = np.unique(np.concatenate([idx, np.arange(count - 37, count)]))
+    say(f"  oracle on {len(idx)} nodes")
+    want = orc.bound_pool(p, pool[idx], nthreads=host_threads())
     assert np.array_equal(got[idx], want)
-    root = orc.lower_bound(p, [])
-    assert got.min() >= root
-    # the last records of the pool
-    tail = np.arange(count - 37, count)
-    assert np.array_equal(got[tail], orc.bound_pool(p, pool[tail], nthreads=8))
+    assert got.min() >= orc.lower_bound(p, [])
+
+
+def _hip():
+    """torch's HIP runtime (already loaded: same SONAME)."""
+    import ctypes
+    h = ctypes.CDLL("libamdhip64.so.7")
+    h.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    h.hipFree.argtypes = [ctypes.c_void_p]
+    h.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    h.hipDeviceSynchronize.argtypes = []
+    return h
+
+
+RAGGED = [(20, 20, True), (20, 20, False), (50, 20, True), (100, 10, True)]
+
+
+@pytest.mark.parametrize("n,m,packed", RAGGED,
+                         ids=["20x20_packed", "20x20_register", "50x20", "100x10"])
+def test_ragged_tail_in_exact_allocation(fsp, orc, n, m, packed):
+    """A pool whose last tile is ragged (count not a multiple of the 512-node
+    packed tile nor of the 256-node tile), in a buffer of exactly count *
+    stride bytes from hipMalloc (where the stride allows it, a whole number
+    of 4 KiB pages, so the pool ends where the mapped memory ends), bounded
+    through the C ABI with raw device pointers: every node equals the
+    oracle, and no lane past the end reads a record (a regression test of the
+    packed form's record loads)."""
+    import ctypes
+    import math
+    stride = ((n + 1) + 15) // 16 * 16
+    whole_pages = 4096 // math.gcd(stride, 4096)  # smallest count filling whole pages
+    count = 3 * 512 + (whole_pages if whole_pages < 256 else 77)
+    assert count % 512 != 0 and count % 256 != 0
+    p = I.instance(n, m, 6100 + n + m)
+    pool = np.ascontiguousarray(I.random_pool(n, count, 0, n, 6200 + n + m))
+    assert pool.shape == (count, stride)
+    inst = fsp.Instance(p, packed=packed)
+    say(f"exact allocation n={n} m={m} ({inst.bound_path}): {count} nodes, "
+        f"{count * stride} bytes")
+    hip = _hip()
+    d_nodes, d_lb = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(d_nodes), count * stride) == 0
+    assert hip.hipMalloc(ctypes.byref(d_lb), count * 4) == 0
+    try:
+        assert hip.hipMemcpy(d_nodes, pool.ctypes.data_as(ctypes.c_void_p),
+                             count * stride, 1) == 0  # host to device
+        desc = fsp._Nodes()
+        desc.inst = inst.handle.value
+        desc.data = d_nodes.value
+        desc.stride = stride
+        rc = fsp.lib().fsp_bound_pool(ctypes.byref(desc), count, d_lb, None)
+        assert rc == 0, fsp.status_string(rc)
+        assert hip.hipDeviceSynchronize() == 0
+        got = np.empty(count, np.int32)
+        assert hip.hipMemcpy(got.ctypes.data_as(ctypes.c_void_p), d_lb, count * 4, 2) == 0
+    finally:
+        hip.hipFree(d_nodes)
+        hip.hipFree(d_lb)
+    assert np.array_equal(got, orc.bound_pool(p, pool, nthreads=host_threads()))
 
 
 @pytest.mark.parametrize("n,m,total,big", [(20, 20, 32767, 0), (20, 20, 32768, 0),
