@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock, 4) void bound_kernel_p16(const BoundParams 
     ntiles = (count + 2 * kBlock - 1) / (2 * kBlock);
   }
   if ((int64_t)blockIdx.x >= ntiles) return;
-  const LdsView L = carve<false>(smem, a.I);
+  const LdsView L = carve_p16(smem, a.I);
   stage_p16_rows(a.I, L);
   __syncthreads();
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
@@ -179,6 +179,8 @@ InstView inst_view(const fsp_instance *inst, size_t table_budget) {
   v.tot = inst->d_tot;
   v.rec = inst->d_rec;
   v.joff = inst->d_joff;
+  v.xy16 = inst->d_xy16;
+  v.job16 = inst->d_job16;
   v.slot_bytes = uses_job_masks(inst->n) ? mask_slot_bytes(inst->n) : 0;
   v.n = inst->n;
   v.mp = inst->mp;
@@ -267,7 +269,6 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
   a.I = inst_view(inst, wide ? kTableBudgetWide : kTableBudgetNarrow);
   BoundFn fn;
   if (p16) {
-    a.I.rec = inst->d_rec16;  // same size as the 32-bit table
     fn = inst->m >= 2 && inst->m <= kMaxMachines
              ? p16_kernel(inst->m, std::make_integer_sequence<int, kMaxMachines - 1>())
              : nullptr;
@@ -275,7 +276,8 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
     fn = kernel_for(inst->m, form, a.I.nchunks > 1);
   }
   if (!fn) return FSP_EUNSUPPORTED;
-  const size_t lds = lds_bytes(a.I.n, a.I.mp, a.I.npad, a.I.ppc, form == kFormMasks);
+  const size_t lds = p16 ? lds_bytes_p16(a.I.n, a.I.mp, a.I.npad, a.I.P)
+                        : lds_bytes(a.I.n, a.I.mp, a.I.npad, a.I.ppc, form == kFormMasks);
 
   // device attributes and per-kernel occupancy are queried once per
   // (device, kernel, LDS size) and cached for this thread, in a fixed table

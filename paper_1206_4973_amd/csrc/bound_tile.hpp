@@ -16,6 +16,8 @@ struct InstView {
   const int32_t *__restrict__ tot;  // [mp]
   const Rec *__restrict__ rec;       // [P][npad] {x, y} per table position
   const uint32_t *__restrict__ joff; // [P][npad] 8 * job id per position
+  const uint32_t *__restrict__ xy16;  // packed form: [P][npad] x | y << 16
+  const uint32_t *__restrict__ job16; // packed form: [P][npad] job id
   int n, mp, npad, P;
   int ppc;         // pairs per LDS chunk
   int nchunks;     // chunks of the pair table
@@ -603,58 +605,152 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
 //      of the method then lies in [0, 32767], and z + x in [-32767, 32767]) --
 //
 // The lane holds node A in the low and node B in the high 16 bits of every
-// state value.  The unscheduled sets are interleaved into one 64-bit word
-// W = {A jobs 0..15, B jobs 0..15, A jobs 16..31, B jobs 16..31} (16 bits
-// each), so that (W >> s) with s = (job & 15) + 32 (job >> 4) has A's bit in
-// bit 0 and B's bit in bit 16.  One position then costs
-//   al = (W >> s) & 0x10001                     (v_lshrrev_b64, v_and_b32)
-//   t  = z + al * x,  u = al * y               (v_pk_mad_u16, v_pk_mul_lo_u16;
-//        x and y are the halves of one record word, broadcast by op_sel)
-//   z  = max(t, u)                              (v_pk_max_i16)
-// i.e. 5 instructions for two nodes instead of 8.
-__device__ __forceinline__ uint32_t step_p16(uint64_t W, uint32_t bits, uint32_t xy,
-                                             uint32_t s, uint32_t z) {
-  const uint32_t al = (uint32_t)(W >> s) & bits;
-  uint32_t t, u, r;
-  asm("v_pk_mad_u16 %0, %1, %2, %3 op_sel_hi:[1,0,1]"
-      : "=v"(t) : "v"(al), "v"(xy), "v"(z));
-  asm("v_pk_mul_lo_u16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,1]"
-      : "=v"(u) : "v"(al), "v"(xy));
-  asm("v_pk_max_i16 %0, %1, %2" : "=v"(r) : "v"(t), "v"(u));
-  return r;
+// state value.  Before the walk, each lane builds one register per job,
+//   al[j] = (job j unscheduled in A) | (job j unscheduled in B) << 16,
+// in 32 VGPRs pinned at v96..v127.  The table position's job id is
+// wave-uniform and comes from a scalar load; with the VGPR index mode on
+// (s_set_gpr_idx_on), the job id is added to the register number of the
+// first source operand, so the multiplier al[job] is read directly by the
+// arithmetic.  One position then costs
+//   t = z + al * x,  u = al * y       (v_pk_mad_u16, v_pk_mul_lo_u16; x and
+//       y are the halves of one table word, broadcast by op_sel)
+//   z = max(t, u)                     (v_pk_max_i16)
+// i.e. 3 vector instructions for two nodes (plus scalar instructions that
+// set the index, issued beside them).  al = 0 leaves z unchanged (z >= 0).
+typedef unsigned int u32x32 __attribute__((ext_vector_type(32)));
+
+// One position of two chains: pair A with the job in SGPR JA and the word in
+// VGPR XA, pair B with JB and XB.  The caller saves M0 (the index) before and
+// restores it after.
+#define FSP_P16_STEP2(JA, XA, JB, XB)                                  \
+  "s_set_gpr_idx_on " JA ", gpr_idx(SRC0)\n\t"                        \
+  "v_pk_mad_u16 %[tA], v96, " XA ", %[zA] op_sel_hi:[1,0,1]\n\t"      \
+  "v_pk_mul_lo_u16 %[uA], v96, " XA " op_sel:[0,1] op_sel_hi:[1,1]\n\t" \
+  "s_set_gpr_idx_idx " JB "\n\t"                                      \
+  "v_pk_mad_u16 %[tB], v96, " XB ", %[zB] op_sel_hi:[1,0,1]\n\t"      \
+  "v_pk_mul_lo_u16 %[uB], v96, " XB " op_sel:[0,1] op_sel_hi:[1,1]\n\t" \
+  "s_set_gpr_idx_off\n\t"                                             \
+  "v_pk_max_i16 %[zA], %[tA], %[uA]\n\t"                              \
+  "v_pk_max_i16 %[zB], %[tB], %[uB]\n\t"
+
+#define FSP_P16_STEP1(JA, XA)                                          \
+  "s_set_gpr_idx_on " JA ", gpr_idx(SRC0)\n\t"                        \
+  "v_pk_mad_u16 %[tA], v96, " XA ", %[zA] op_sel_hi:[1,0,1]\n\t"      \
+  "v_pk_mul_lo_u16 %[uA], v96, " XA " op_sel:[0,1] op_sel_hi:[1,1]\n\t" \
+  "s_set_gpr_idx_off\n\t"                                             \
+  "v_pk_max_i16 %[zA], %[tA], %[uA]\n\t"
+
+// LDS byte offset of a pointer into the workgroup's LDS.
+__device__ __forceinline__ uint32_t lds_offset(const char *p) {
+  return (uint32_t)(uintptr_t)((__attribute__((address_space(3))) const char *)p);
 }
 
-__device__ __forceinline__ uint32_t walk1_p16(const char *rp_raw, int npad,
-                                              uint64_t W, uint32_t bits, uint32_t Z) {
-  const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);  // 2 records
-  for (int i = 0; i < npad / 4; ++i) {
-    const int4 r0 = rp[2 * i], r1 = rp[2 * i + 1];
-    Z = step_p16(W, bits, r0.x, r0.y, Z);
-    Z = step_p16(W, bits, r0.z, r0.w, Z);
-    Z = step_p16(W, bits, r1.x, r1.y, Z);
-    Z = step_p16(W, bits, r1.z, r1.w, Z);
-  }
+// Two pairs walked together over `groups` groups of four positions.  Their
+// tables are interleaved four positions at a time (four words of the first
+// pair, then four of the second): the xy words in LDS at byte offset `lds`,
+// the job ids in global memory at `jobs` (scalar loads).  The loop is double
+// buffered: group g + 1 is requested (job ids into s[88:95], words into
+// v[88:95], or s[80:87] / v[80:87]) before group g is computed, and waited for
+// after it, so the loads of one group overlap the arithmetic of the other.
+// The request one group past the end stays inside both tables (the job table
+// has a spare group; in LDS the rows of p follow the xy table).  Every load
+// is waited for inside the statement.
+__device__ __forceinline__ void walk2_p16(uint32_t lds, const uint32_t *jobs, int groups,
+                                          const u32x32 &AL, uint32_t &ZA,
+                                          uint32_t &ZB) {
+  uint32_t tA, uA, tB, uB, sv, soff, scnt;
+  const uint64_t jp = reinterpret_cast<uint64_t>(jobs);
+  asm volatile(
+      "s_mov_b32 %[sv], m0\n\t"
+      "s_mov_b32 %[soff], 0\n\t"
+      "s_mov_b32 %[scnt], %[ng]\n\t"
+      "s_load_dwordx8 s[80:87], %[jp], %[soff]\n\t"
+      "ds_read_b128 v[80:83], %[va]\n\t"
+      "ds_read_b128 v[84:87], %[va] offset:16\n\t"
+      "s_waitcnt lgkmcnt(0)\n"
+      "1:\n\t"
+      "s_add_u32 %[soff], %[soff], 32\n\t"
+      "s_load_dwordx8 s[88:95], %[jp], %[soff]\n\t"
+      "ds_read_b128 v[88:91], %[va] offset:32\n\t"
+      "ds_read_b128 v[92:95], %[va] offset:48\n\t"
+      FSP_P16_STEP2("s80", "v80", "s84", "v84")
+      FSP_P16_STEP2("s81", "v81", "s85", "v85")
+      FSP_P16_STEP2("s82", "v82", "s86", "v86")
+      FSP_P16_STEP2("s83", "v83", "s87", "v87")
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "s_sub_u32 %[scnt], %[scnt], 1\n\t"
+      "s_cmp_eq_u32 %[scnt], 0\n\t"
+      "s_cbranch_scc1 2f\n\t"
+      "s_add_u32 %[soff], %[soff], 32\n\t"
+      "s_load_dwordx8 s[80:87], %[jp], %[soff]\n\t"
+      "ds_read_b128 v[80:83], %[va] offset:64\n\t"
+      "ds_read_b128 v[84:87], %[va] offset:80\n\t"
+      FSP_P16_STEP2("s88", "v88", "s92", "v92")
+      FSP_P16_STEP2("s89", "v89", "s93", "v93")
+      FSP_P16_STEP2("s90", "v90", "s94", "v94")
+      FSP_P16_STEP2("s91", "v91", "s95", "v95")
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "v_add_u32 %[va], 64, %[va]\n\t"
+      "s_sub_u32 %[scnt], %[scnt], 1\n\t"
+      "s_cmp_eq_u32 %[scnt], 0\n\t"
+      "s_cbranch_scc0 1b\n"
+      "2:\n\t"
+      "s_mov_b32 m0, %[sv]"
+      : [zA] "+v"(ZA), [zB] "+v"(ZB), [tA] "=&v"(tA), [uA] "=&v"(uA),
+        [tB] "=&v"(tB), [uB] "=&v"(uB), [sv] "=&s"(sv), [soff] "=&s"(soff),
+        [scnt] "=&s"(scnt), [va] "+v"(lds)
+      : [jp] "s"(jp), [ng] "s"(groups), [al] "{v[96:127]}"(AL)
+      : "v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87", "v88", "v89", "v90",
+        "v91", "v92", "v93", "v94", "v95", "s80", "s81", "s82", "s83", "s84", "s85",
+        "s86", "s87", "s88", "s89", "s90", "s91", "s92", "s93", "s94", "s95", "scc",
+        "memory");
+}
+
+// One pair alone (the last pair of a row with an odd number of pairs): four
+// words and four job ids per group, double buffered as walk2_p16.
+__device__ __forceinline__ uint32_t walk1_p16(uint32_t lds, const uint32_t *jobs, int groups,
+                                              const u32x32 &AL, uint32_t Z) {
+  uint32_t tA, uA, sv, soff, scnt;
+  const uint64_t jp = reinterpret_cast<uint64_t>(jobs);
+  asm volatile(
+      "s_mov_b32 %[sv], m0\n\t"
+      "s_mov_b32 %[soff], 0\n\t"
+      "s_mov_b32 %[scnt], %[ng]\n\t"
+      "s_load_dwordx4 s[80:83], %[jp], %[soff]\n\t"
+      "ds_read_b128 v[80:83], %[va]\n\t"
+      "s_waitcnt lgkmcnt(0)\n"
+      "1:\n\t"
+      "s_add_u32 %[soff], %[soff], 16\n\t"
+      "s_load_dwordx4 s[88:91], %[jp], %[soff]\n\t"
+      "ds_read_b128 v[88:91], %[va] offset:16\n\t"
+      FSP_P16_STEP1("s80", "v80")
+      FSP_P16_STEP1("s81", "v81")
+      FSP_P16_STEP1("s82", "v82")
+      FSP_P16_STEP1("s83", "v83")
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "s_sub_u32 %[scnt], %[scnt], 1\n\t"
+      "s_cmp_eq_u32 %[scnt], 0\n\t"
+      "s_cbranch_scc1 2f\n\t"
+      "s_add_u32 %[soff], %[soff], 16\n\t"
+      "s_load_dwordx4 s[80:83], %[jp], %[soff]\n\t"
+      "ds_read_b128 v[80:83], %[va] offset:32\n\t"
+      FSP_P16_STEP1("s88", "v88")
+      FSP_P16_STEP1("s89", "v89")
+      FSP_P16_STEP1("s90", "v90")
+      FSP_P16_STEP1("s91", "v91")
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "v_add_u32 %[va], 32, %[va]\n\t"
+      "s_sub_u32 %[scnt], %[scnt], 1\n\t"
+      "s_cmp_eq_u32 %[scnt], 0\n\t"
+      "s_cbranch_scc0 1b\n"
+      "2:\n\t"
+      "s_mov_b32 m0, %[sv]"
+      : [zA] "+v"(Z), [tA] "=&v"(tA), [uA] "=&v"(uA), [sv] "=&s"(sv),
+        [soff] "=&s"(soff), [scnt] "=&s"(scnt), [va] "+v"(lds)
+      : [jp] "s"(jp), [ng] "s"(groups), [al] "{v[96:127]}"(AL)
+      : "v80", "v81", "v82", "v83", "v88", "v89", "v90", "v91", "s80", "s81", "s82",
+        "s83", "s88", "s89", "s90", "s91", "scc", "memory");
   return Z;
-}
-
-// Two pairs walked together; their tables are interleaved four positions at
-// a time (four of the first pair, four of the second, ...), so both are read
-// from one address.
-__device__ __forceinline__ void walk2_p16(const char *rp_raw, int npad, uint64_t W,
-                                          uint32_t bits, uint32_t &ZA, uint32_t &ZB) {
-  const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);
-  for (int i = 0; i < npad / 4; ++i) {
-    const int4 a0 = rp[4 * i], a1 = rp[4 * i + 1];
-    const int4 b0 = rp[4 * i + 2], b1 = rp[4 * i + 3];
-    ZA = step_p16(W, bits, a0.x, a0.y, ZA);
-    ZB = step_p16(W, bits, b0.x, b0.y, ZB);
-    ZA = step_p16(W, bits, a0.z, a0.w, ZA);
-    ZB = step_p16(W, bits, b0.z, b0.w, ZB);
-    ZA = step_p16(W, bits, a1.x, a1.y, ZA);
-    ZB = step_p16(W, bits, b1.x, b1.y, ZB);
-    ZA = step_p16(W, bits, a1.z, a1.w, ZA);
-    ZB = step_p16(W, bits, b1.z, b1.w, ZB);
-  }
 }
 
 __device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
@@ -671,19 +767,19 @@ __device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
                                                       __builtin_bit_cast(u16x2, b)));
 }
 
-// Every pair (the whole table is in LDS: n <= 32).  Returns the packed max
-// over pairs of the pair bounds of nodes A and B.
+// Every pair (the whole xy table is in LDS: n <= 32; the job table is read
+// from global memory by scalar loads at the same offsets).  Returns the
+// packed max over pairs of the pair bounds of nodes A and B.
 template <int M>
-__device__ __forceinline__ uint32_t pair_sweep_p16(const char *s_rec, int npad,
-                                                   uint64_t W,
+__device__ __forceinline__ uint32_t pair_sweep_p16(const char *s_xy, const uint32_t *jt,
+                                                   int npad, const u32x32 &AL,
                                                    const uint32_t (&R)[M],
                                                    const uint32_t (&T)[M],
                                                    const uint32_t (&Q)[M]) {
-  int pb = npad * (int)sizeof(Rec);
-  asm volatile("" : "+s"(pb));
-  // the bit mask in an SGPR gives the masking instruction its short encoding
-  uint32_t bits;
-  asm volatile("s_mov_b32 %0, 0x10001" : "=s"(bits));
+  // words of one pair, in both tables; groups of four positions per pair
+  int pw = npad, groups = npad / 4;
+  asm volatile("" : "+s"(pw), "+s"(groups));
+  const uint32_t lds0 = lds_offset(s_xy);
   int off = 0;
   uint32_t LB = 0;
 #pragma unroll
@@ -692,18 +788,18 @@ __device__ __forceinline__ uint32_t pair_sweep_p16(const char *s_rec, int npad,
     for (int l = k + 1; l < M; l += 2) {
       if (l + 1 < M) {
         uint32_t ZA = pk_sub(R[l], R[k]), ZB = pk_sub(R[l + 1], R[k]);
-        walk2_p16(s_rec + off, npad, W, bits, ZA, ZB);
+        walk2_p16(lds0 + 4 * off, jt + off, groups, AL, ZA, ZB);
         // T + Q + z wraps in 16 bits only on the way: the sum is a bound of
         // the method, at most the total work
         LB = pk_max(LB, pk_max(pk_add(pk_add(T[k], Q[l]), ZA),
                                pk_add(pk_add(T[k], Q[l + 1]), ZB)));
         asm volatile("" : "+v"(LB));
-        off += 2 * pb;
+        off += 2 * pw;
       } else {
-        uint32_t Z = walk1_p16(s_rec + off, npad, W, bits, pk_sub(R[l], R[k]));
+        uint32_t Z = walk1_p16(lds0 + 4 * off, jt + off, groups, AL, pk_sub(R[l], R[k]));
         LB = pk_max(LB, pk_add(pk_add(T[k], Q[l]), Z));
         asm volatile("" : "+v"(LB));
-        off += pb;
+        off += pw;
       }
     }
   }
@@ -880,9 +976,6 @@ __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView 
   bool badA, badB;
   node_state_p16<M>(I, reinterpret_cast<const uint32_t *>(L.s_p), nodes, stride,
                     aligned, ia, ib, la, lbv, UA, UB, badA, badB, last, R, T, Q);
-  const uint64_t W =
-      (uint64_t)((UA & 0xffffu) | (UB << 16)) |
-      ((uint64_t)((UA >> 16) | (UB & 0xffff0000u)) << 32);
   // one-machine bounds of both nodes (see bound_nodes)
   bool skip = false;
   uint32_t LB1 = 0;
@@ -899,7 +992,15 @@ __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView 
   }
 #pragma unroll
   for (int k = 0; k < M; ++k) asm volatile("" : "+v"(R[k]), "+v"(T[k]), "+v"(Q[k]));
-  const uint32_t LB = skip ? LB1 : pair_sweep_p16<M>(L.s_rec, I.npad, W, R, T, Q);
+  uint32_t LB = LB1;
+  if (!skip) {
+    // the per-job multipliers of both nodes (jobs >= n are never named)
+    u32x32 AL;
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+      AL[j] = ((UA >> j) & 1u) | (((UB >> j) & 1u) << 16);
+    LB = pair_sweep_p16<M>(L.s_rec, I.job16, I.npad, AL, R, T, Q);
+  }
   if (la) {
     int lb = UA == 0u ? (int)(last & 0xffffu) : (int)(LB & 0xffffu);
     lb_out[ia] = badA ? FSP_LB_INVALID : lb;
@@ -910,10 +1011,25 @@ __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView 
   }
 }
 
-// Stage the packed rows of p for node_state_p16: s_p16[j][t] = p[j][2t] |
-// p[j][2t + 1] << 16 for j < n and t < mp / 2; zeros elsewhere (row n and
-// the pitch padding).  It takes the region of the 32-bit rows of the other
-// narrow kernels, which lds_bytes sizes for both.
+// LDS of one workgroup of the packed kernel: the xy table (one word per
+// position), then the packed rows of p plus a row of zeros.
+__host__ __device__ inline size_t lds_bytes_p16(int n, int mp, int npad, int P) {
+  const size_t b = (size_t)P * npad * 4 + (size_t)(n + 1) * p16_row_words(mp) * 4;
+  return (b + 15) & ~size_t(15);
+}
+
+// LDS view of the packed kernel (see lds_bytes_p16).
+__device__ __forceinline__ LdsView carve_p16(char *smem, const InstView I) {
+  LdsView L;
+  L.s_rec = smem;
+  L.s_p = reinterpret_cast<int32_t *>(smem + (size_t)I.P * I.npad * 4);
+  L.s_words = nullptr;
+  return L;
+}
+
+// Stage the packed kernel's LDS: the xy table, and the packed rows of p for
+// node_state_p16: s_p16[j][t] = p[j][2t] | p[j][2t + 1] << 16 for j < n and
+// t < mp / 2; zeros elsewhere (row n and the pitch padding).
 __device__ __forceinline__ void stage_p16_rows(const InstView I, const LdsView &L) {
   const int h = p16_row_words(I.mp);
   uint32_t *dst = reinterpret_cast<uint32_t *>(L.s_p);
@@ -925,7 +1041,8 @@ __device__ __forceinline__ void stage_p16_rows(const InstView I, const LdsView &
           ((uint32_t)I.p[j * I.mp + 2 * t + 1] << 16);
     dst[i] = v;
   }
-  if (I.nchunks == 1) stage_chunk(I, L.s_rec, 0);
+  uint32_t *xy = reinterpret_cast<uint32_t *>(L.s_rec);
+  for (int i = threadIdx.x; i < I.P * I.npad; i += kBlock) xy[i] = I.xy16[i];
 }
 
 // InstView of a loaded instance with the pair table split into LDS chunks of

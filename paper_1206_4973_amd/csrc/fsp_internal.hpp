@@ -47,6 +47,9 @@ inline size_t joff_bytes(int P, int npad) {
   return ((size_t)P * npad + 4) * sizeof(uint32_t);
 }
 inline int npairs(int m) { return m * (m - 1) / 2; }
+// Words of the packed job table: [P][npad] plus one group of eight that the
+// walk may request (and not use) past the last pair.
+inline size_t p16_job_words(int P, int npad) { return (size_t)P * npad + 8; }
 
 }  // namespace fspi
 
@@ -57,11 +60,15 @@ struct fsp_instance {
   int32_t *d_p = nullptr, *d_H = nullptr, *d_Q = nullptr, *d_tot = nullptr;
   uint32_t *d_Hp = nullptr, *d_Qp = nullptr;  // H, Q as packed 16-bit pairs
   fspi::Rec *d_rec = nullptr;  // [P][npad]
-  // Packed 16-bit table for two nodes per lane (p16 = 1: n <= 32 and total
-  // work <= 32767, so every quantity of the bound fits in 16 bits):
-  //   {x | y << 16 with x = b - a, y = lag + b;  s = (job & 15) + 32 (job >> 4)}
+  // Packed 16-bit tables for two nodes per lane (p16 = 1: n <= 32 and total
+  // work <= 32767, so every quantity of the bound fits in 16 bits), one
+  // 32-bit word per table position, couples of pairs interleaved:
+  //   xy16  x | y << 16 with x = b - a, y = lag + b   (staged in LDS)
+  //   job16 the position's job id                    (read by scalar loads;
+  //         p16_job_words(P, npad) words: one spare group past the end)
   int p16 = 0;
-  fspi::Rec *d_rec16 = nullptr;  // [P][npad], couples of pairs interleaved
+  uint32_t *d_xy16 = nullptr;
+  uint32_t *d_job16 = nullptr;
   uint32_t *d_joff = nullptr;  // [P][npad] 8 * job id per table position
   std::vector<int32_t> p_host;  // [n][m], for host-side set-up work (NEH)
 };

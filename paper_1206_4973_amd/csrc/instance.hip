@@ -58,7 +58,7 @@ __global__ void stage_totals(const int32_t *__restrict__ p, int n, int mp,
 __global__ __launch_bounds__(256) void stage_pairs(
     const int32_t *__restrict__ p, int n, int m, int mp, int npad,
     Rec *__restrict__ rec_out, uint32_t *__restrict__ joff_out,
-    Rec *__restrict__ rec16_out) {
+    uint32_t *__restrict__ xy16_out, uint32_t *__restrict__ job16_out) {
   __shared__ int sA[256], sB[256];
   const int pi = blockIdx.x;
   // (k,l) of pair pi in lexicographic order
@@ -108,12 +108,13 @@ __global__ __launch_bounds__(256) void stage_pairs(
   const size_t slot = (size_t)pi * npad + pos;
   rec_out[slot] = make_int2(x, y);
   joff_out[slot] = 8u * (uint32_t)(j < n ? j : n);
-  if (rec16_out) {
-    // padding: x = y = 0 leaves the packed state unchanged whatever s selects
-    int xy = 0, s = 0;
+  if (xy16_out) {
+    // padding: x = y = 0 leaves the packed state unchanged whatever job the
+    // position names (job 0, a valid index)
+    uint32_t xy = 0, job = 0;
     if (j < n) {
-      xy = (int)(((uint32_t)(b - a) & 0xffffu) | ((uint32_t)(lag + b) << 16));
-      s = (j & 15) + 32 * (j >> 4);
+      xy = ((uint32_t)(b - a) & 0xffffu) | ((uint32_t)(lag + b) << 16);
+      job = (uint32_t)j;
     }
     // The packed walk takes the pairs of a row two at a time, (k, k+1) with
     // (k, k+2), (k, k+3) with (k, k+4), ..., the last one alone when the row
@@ -125,7 +126,8 @@ __global__ __launch_bounds__(256) void stage_pairs(
       const size_t base = (size_t)(pi - (i & 1)) * npad;
       slot16 = base + (size_t)(pos / 4) * 8 + (i & 1) * 4 + (pos & 3);
     }
-    rec16_out[slot16] = make_int2(xy, s);
+    xy16_out[slot16] = xy;
+    job16_out[slot16] = job;
   }
 }
 
@@ -136,14 +138,15 @@ void free_device(fsp_instance *in) {
   if (in->d_tot) (void)hipFree(in->d_tot);
   if (in->d_rec) (void)hipFree(in->d_rec);
   if (in->d_joff) (void)hipFree(in->d_joff);
-  if (in->d_rec16) (void)hipFree(in->d_rec16);
+  if (in->d_xy16) (void)hipFree(in->d_xy16);
+  if (in->d_job16) (void)hipFree(in->d_job16);
   if (in->d_Hp) (void)hipFree(in->d_Hp);
   if (in->d_Qp) (void)hipFree(in->d_Qp);
   in->d_Hp = in->d_Qp = nullptr;
   in->d_p = in->d_H = in->d_Q = in->d_tot = nullptr;
   in->d_rec = nullptr;
   in->d_joff = nullptr;
-  in->d_rec16 = nullptr;
+  in->d_xy16 = in->d_job16 = nullptr;
 }
 
 int build_tables(fsp_instance *in, const int32_t *p_host) {
@@ -155,8 +158,9 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
       hipMalloc(&in->d_tot, mp * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&in->d_rec, (size_t)in->P * in->npad * sizeof(Rec)) != hipSuccess ||
       hipMalloc(&in->d_joff, joff_bytes(in->P, in->npad)) != hipSuccess ||
-      (in->p16 && hipMalloc(&in->d_rec16, (size_t)in->P * in->npad * sizeof(Rec)) !=
-                      hipSuccess) ||
+      (in->p16 && (hipMalloc(&in->d_xy16, (size_t)in->P * in->npad * 4) != hipSuccess ||
+                   hipMalloc(&in->d_job16, p16_job_words(in->P, in->npad) * 4) !=
+                       hipSuccess)) ||
       hipMalloc(&in->d_Hp, mat / 2) != hipSuccess ||
       hipMalloc(&in->d_Qp, mat / 2) != hipSuccess)
     return FSP_ENOMEM;
@@ -172,6 +176,10 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
   if (rc == FSP_OK &&
       hipMemset(in->d_joff, 0, joff_bytes(in->P, in->npad)) != hipSuccess)
     rc = FSP_EDEVICE;
+  // likewise the packed job table's spare group (job 0: a valid index)
+  if (rc == FSP_OK && in->p16 &&
+      hipMemset(in->d_job16, 0, p16_job_words(in->P, in->npad) * 4) != hipSuccess)
+    rc = FSP_EDEVICE;
   if (rc == FSP_OK) {
     hipLaunchKernelGGL(stage_rows, dim3((n + 63) / 64), dim3(64), 0, s, d_in,
                        n, m, mp, in->d_p, in->d_H, in->d_Q, in->d_Hp, in->d_Qp);
@@ -179,7 +187,7 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
                        in->d_tot);
     hipLaunchKernelGGL(stage_pairs, dim3(in->P), dim3(256), 0, s, in->d_p, n,
                        m, mp, in->npad, in->d_rec, in->d_joff,
-                       in->d_rec16);
+                       in->d_xy16, in->d_job16);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
       rc = FSP_EDEVICE;
   }
