@@ -393,6 +393,9 @@ def main() -> int:
     ap.add_argument("--log2-pool", type=int, default=22)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-bnb", action="store_true", help="skip the B&B time-to-optimum leg")
+    ap.add_argument("--pool-only", action="store_true",
+                    help="only the timed launches of the benchmark pool (no 32-bit form, no "
+                         "sweep, no oracle, no B&B): the run that profiles use")
     ap.add_argument("--bnb-kind", default=None, choices=["adaptive", "autotuned", "learned"],
                     help="with --workload bnb: run only this kind")
     ap.add_argument("--prefilter", action="store_true",
@@ -491,15 +494,19 @@ def main() -> int:
     achieved = ops / kernel_s / 1e12
     progress(f"pool 20x20 2^{args.log2_pool}: {kernel_s * 1e3:.3f} ms per launch "
              f"({inst.bound_path} form)")
+    if args.pool_only:
+        args.no_cpu = args.no_bnb = True
 
-    # the same pool on the one-node-per-lane 32-bit form
-    inst32 = fsp.Instance(p, packed=False)
-    t32 = timed(lambda: inst32.bound_pool(nodes, out, stream=stream), args.steps,
-                args.warmup, stream)
-    inst32.close()
-    progress(f"pool 20x20 2^{args.log2_pool} on the 32-bit form: {t32 * 1e3:.3f} ms")
-    sweep = pool_sweep(inst, nodes, out, pool[:, 0], n, m, stream, peak,
-                       hi=args.log2_pool)
+    t32, sweep = None, None
+    if not args.pool_only:
+        # the same pool on the one-node-per-lane 32-bit form
+        inst32 = fsp.Instance(p, packed=False)
+        t32 = timed(lambda: inst32.bound_pool(nodes, out, stream=stream), args.steps,
+                    args.warmup, stream)
+        inst32.close()
+        progress(f"pool 20x20 2^{args.log2_pool} on the 32-bit form: {t32 * 1e3:.3f} ms")
+        sweep = pool_sweep(inst, nodes, out, pool[:, 0], n, m, stream, peak,
+                           hi=args.log2_pool)
     res = {
         "metric": METRIC,
         "value": value,
@@ -534,14 +541,15 @@ def main() -> int:
             "kernel_ms": kernel_s * 1e3,
             "algorithmic_ops_per_launch": ops,
         },
-        "int32_register_form": {
+    }
+    if t32 is not None:
+        res["int32_register_form"] = {
             "kernel": f"bound_kernel<{m}> (one node per lane, 32-bit)",
             "kernel_ms": t32 * 1e3, "nodes_per_s": count / t32,
             "achieved_TOPs": ops / t32 / 1e12, "peak_TOPs": INT32_PEAK_TOPS,
             "frac": ops / t32 / 1e12 / INT32_PEAK_TOPS,
-        },
-        "pool_sweep": sweep,
-    }
+        }
+        res["pool_sweep"] = sweep
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(p, pool)
         progress("cpu baseline done")
