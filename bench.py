@@ -171,7 +171,8 @@ def bnb_leg(seeds, time_limit, only=None, prefilter=False, kinds=None) -> dict:
             row[kind] = {"makespan": r.makespan, "proven": r.status == 0,
                          "t_proof_s": r.t_total_s, "t_found_s": r.t_found_s,
                          "t_search_s": r.t_search_s, "nodes": r.nodes_bounded,
-                         "pool": r.final_pool}
+                         "pools": r.pools, "pool": r.final_pool,
+                         "proof_pools": r.proof_pools}
         inst.close()
         rows.append(row)
     out = {"instances": f"20x10, seeds {seeds[0]}..{seeds[-1]} ({len(seeds)} held out)",
@@ -254,7 +255,8 @@ def timed_searches(inst, kinds, time_limit, model=None, prefilter=False, log_dir
                      "proven": r.status == 0, "t_total_s": r.t_total_s,
                      "nodes": r.nodes_bounded,
                      "nodes_per_s": r.nodes_bounded / max(r.t_search_s, 1e-9),
-                     "t_found_s": r.t_found_s, "pool": r.final_pool}
+                     "t_found_s": r.t_found_s, "pool": r.final_pool,
+                     "proof_pools": r.proof_pools}
     return rec
 
 

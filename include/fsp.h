@@ -291,7 +291,8 @@ typedef struct {
                          the nodes still pending after a time limit (status
                          1), else the makespan; gap = (makespan - open_lb) /
                          makespan                                           */
-  int32_t reserved;
+  int32_t proof_pools; /* FSP_POOL_LEARNED: 1 if the network's estimates
+                         switched the search to proof pools (see below)    */
 } fsp_result;
 
 /*
@@ -308,10 +309,16 @@ typedef struct {
  * of the size fsp_autotune_pool picks for this shape; the nb_iterations
  * iterations of a batch are captured once in a hipGraph and replayed.
  * FSP_POOL_LEARNED: as FSP_POOL_AUTOTUNED, and policy->model (an fsp_model
- * with 2 + 2 min(m, 15) inputs) orders each depth: when a pool takes only
- * part of the pending nodes of a depth, it takes those with the smallest
- * estimated completion (bound + predicted gap).  The exact bound still
- * decides every elimination, so the optimum does not depend on the model.
+ * with 2 + 2 min(m, 15) inputs) orders the pools and sets their size.  While
+ * the smallest estimated completion (bound + predicted gap) among the pending
+ * nodes is below UB, a pool that takes only part of a depth takes its nodes
+ * with the smallest estimates, with the autotuned number of children; once
+ * that smallest estimate reaches UB (the network expects no pending node to
+ * beat UB: what is left is a proof, in which order does not matter), pools
+ * take the largest size the buffers hold (policy->max_pool, or the device's
+ * resident threads) and the network is no longer run (proof_pools = 1).  The
+ * exact bound still decides every elimination, so the optimum does not
+ * depend on the model.
  */
 int fsp_branch_and_bound(const fsp_instance *inst,
                          const fsp_pool_policy *policy, int32_t ub_in,

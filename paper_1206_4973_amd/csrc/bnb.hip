@@ -342,6 +342,23 @@ __global__ void open_lb_kernel(const int32_t *__restrict__ blb,
   }
 }
 
+// smallest estimate (est = bound / scale + predicted gap, >= 0) among the
+// pending nodes, as float bits: for non-negative floats the bit patterns
+// order like the values, so an integer atomic min serves
+__global__ void min_est_kernel(const float *__restrict__ bscore,
+                               const int32_t *__restrict__ bcount, int n, int64_t cap,
+                               int32_t *__restrict__ out) {
+  for (int d = 0; d < n; ++d) {
+    const int c = bcount[d];
+    int best = 0x7fffffff;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c;
+         i += (int64_t)gridDim.x * blockDim.x)
+      best = min(best, __float_as_int(fmaxf(bscore[(int64_t)d * cap + i], 0.f)));
+    for (int off = 32; off > 0; off >>= 1) best = min(best, __shfl_down(best, off));
+    if ((threadIdx.x & 63) == 0 && best != 0x7fffffff) atomicMin(out, best);
+  }
+}
+
 // seed: place the root in bucket 0 if it can beat UB; count its bound
 __global__ void seed_kernel(BnbDesc *D, const int32_t *root_lb,
                             uint8_t *bnodes, int32_t *blb, int32_t *bcount,
@@ -424,6 +441,8 @@ int BnbState::init(const fsp_instance *inst_, int64_t max_pool, int rule_) {
       hipMalloc(&desc, sizeof(BnbDesc)) != hipSuccess ||
       hipMalloc(&best_perm, 256) != hipSuccess ||
       hipMalloc(&target_dev, sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&min_est, sizeof(int32_t)) != hipSuccess ||
+      hipHostMalloc(&host_min_est, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(&host_desc, sizeof(BnbDesc), hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc(&host_target, sizeof(int64_t), hipHostMallocDefault) !=
@@ -471,12 +490,15 @@ void BnbState::release() {
   if (stream) (void)hipStreamSynchronize(stream);
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
+  if (exec_plain) (void)hipGraphExecDestroy(exec_plain);
+  if (graph_plain) (void)hipGraphDestroy(graph_plain);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (void *p : {(void *)bnodes, (void *)blb, (void *)bcount, (void *)pool, (void *)pool_lb, slots,
                   (void *)desc, (void *)best_perm, (void *)target_dev, (void *)bscore,
                   (void *)tnodes, (void *)tlb, (void *)tscore, (void *)hist, X,
-                  (void *)log_nodes, (void *)log_lb})
+                  (void *)log_nodes, (void *)log_lb, (void *)min_est})
     if (p) (void)hipFree(p);
+  if (host_min_est) (void)hipHostFree(host_min_est);
   if (host_desc) (void)hipHostFree(host_desc);
   if (host_target) (void)hipHostFree(host_target);
   if (stream) (void)hipStreamDestroy(stream);
@@ -510,7 +532,17 @@ int BnbState::set_target(int64_t target) {
   return FSP_OK;
 }
 
-int BnbState::enqueue_iteration(hipStream_t s) {
+// One iteration; use_model = false leaves out the learned ordering's
+// kernels (the branch kernel then takes the top of the depth, LIFO).
+int BnbState::enqueue_iteration(hipStream_t s, bool use_model) {
+  const fsp_model *saved = model;
+  if (!use_model) model = nullptr;
+  const int rc = enqueue_iteration_impl(s);
+  model = saved;
+  return rc;
+}
+
+int BnbState::enqueue_iteration_impl(hipStream_t s) {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(64), 0, s, desc, bcount,
                      pool, best_perm, n, stride, target_dev, 0);
   FSP_HIP_TRY(hipGetLastError());
@@ -555,8 +587,46 @@ int BnbState::capture(int iters) {
   return FSP_OK;
 }
 
-int BnbState::replay() {
-  FSP_HIP_TRY(hipGraphLaunch(exec, stream));
+// The same iterations without the learned ordering's kernels (captured on
+// first use).
+int BnbState::capture_plain(int iters) {
+  if (exec_plain) return FSP_OK;
+  if (!cap_stream)
+    FSP_HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+  FSP_HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = FSP_OK;
+  for (int i = 0; i < iters && rc == FSP_OK; ++i) rc = enqueue_iteration(cap_stream, false);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cap_stream, &g);
+  if (rc != FSP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return FSP_EDEVICE;
+  graph_plain = g;
+  FSP_HIP_TRY(hipGraphInstantiate(&exec_plain, graph_plain, nullptr, nullptr, 0));
+  return FSP_OK;
+}
+
+int BnbState::replay(bool plain) {
+  FSP_HIP_TRY(hipGraphLaunch(plain ? exec_plain : exec, stream));
+  return FSP_OK;
+}
+
+// Smallest estimate among the pending nodes (learned ordering only);
+// synchronises the stream.
+int BnbState::pending_min_estimate(float *out) {
+  *host_min_est = 0x7fffffff;
+  FSP_HIP_TRY(hipMemcpyAsync(min_est, host_min_est, sizeof(int32_t), hipMemcpyHostToDevice,
+                             stream));
+  hipLaunchKernelGGL(min_est_kernel, dim3(grid), dim3(256), 0, stream, bscore, bcount, n, cap,
+                     min_est);
+  FSP_HIP_TRY(hipGetLastError());
+  FSP_HIP_TRY(hipMemcpyAsync(host_min_est, min_est, sizeof(int32_t), hipMemcpyDeviceToHost,
+                             stream));
+  FSP_HIP_TRY(hipStreamSynchronize(stream));
+  const int32_t bits = *host_min_est;
+  *out = bits == 0x7fffffff ? INFINITY : __builtin_bit_cast(float, bits);
   return FSP_OK;
 }
 
@@ -770,13 +840,19 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
   double t_found = 0.0;
   int64_t last_bounded = 1;
   int64_t target = 0;
+  // The learned kind's pool size: while the network estimates that some
+  // pending node may still complete below UB, pools take the best-estimated
+  // nodes of the deepest depth, `fixed` children; once its smallest pending
+  // estimate reaches UB, the search is a proof, where order does not matter:
+  // pools of the largest size the buffers hold, without the network.
+  bool proof = false;
   const double t_loop0 = elapsed();
   while (true) {
-    target = kind == FSP_POOL_ADAPTIVE ? ap.current : fixed;
+    target = kind == FSP_POOL_ADAPTIVE ? ap.current : (proof ? max_pool : fixed);
     if ((rc = S.set_target(target)) != FSP_OK) break;
     const double t0 = elapsed();
     if (graphed) {
-      rc = S.replay();
+      rc = S.replay(proof);
     } else {
       for (int it = 0; it < nb_iter && rc == FSP_OK; ++it) rc = S.enqueue_iteration(S.stream);
     }
@@ -797,9 +873,10 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
       std::fprintf(log,
                    "{\"t\": %.6f, \"pool_target\": %lld, \"nodes_bounded\": %lld, "
                    "\"batch_nodes\": %lld, \"eff\": %.17g, \"ub\": %d, \"pools\": %lld, "
-                   "\"done\": %d}\n",
+                   "\"done\": %d, \"proof\": %d}\n",
                    t1, (long long)target, (long long)h.nodes_bounded,
-                   (long long)batch_nodes, eff, h.ub, (long long)h.pools, h.done);
+                   (long long)batch_nodes, eff, h.ub, (long long)h.pools, h.done,
+                   proof ? 1 : 0);
     if (h.overflow) {
       rc = FSP_ENOMEM;
       break;
@@ -812,6 +889,15 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
       break;
     }
     if (kind == FSP_POOL_ADAPTIVE && t1 > t0) ap.observe(eff);
+    if (model && !proof) {
+      // estimates are completions in units of the NEH makespan
+      float me = 0.f;
+      if ((rc = S.pending_min_estimate(&me)) != FSP_OK) break;
+      if ((double)me * (double)neh >= (double)h.ub) {
+        proof = true;
+        if ((rc = S.capture_plain(nb_iter)) != FSP_OK) break;
+      }
+    }
     // clear the "improved" flag for the next batch
     if (h.improved &&
         hipMemsetAsync(&S.desc->improved, 0, sizeof(int32_t), S.stream) != hipSuccess) {
@@ -882,6 +968,7 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
   out->open_lb = status == 1 && open_lb != 0x7fffffff && open_lb >= 0
                      ? std::min<int32_t>(open_lb, h.ub)
                      : h.ub;
+  out->proof_pools = proof ? 1 : 0;
   S.release();
   return FSP_OK;
 }

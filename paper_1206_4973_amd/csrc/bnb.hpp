@@ -133,10 +133,13 @@ struct BnbState {
   uint8_t *log_nodes = nullptr;  // [log_cap][stride]
   int32_t *log_lb = nullptr;
 
-  // captured iterations
+  // captured iterations (with the learned ordering: graph / exec include the
+  // network's kernels, graph_plain / exec_plain do not)
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr, graph_plain = nullptr;
+  hipGraphExec_t exec = nullptr, exec_plain = nullptr;
+  int32_t *min_est = nullptr;       // device: smallest pending estimate (float bits)
+  int32_t *host_min_est = nullptr;  // pinned copy
 
   int init(const fsp_instance *inst, int64_t max_pool, int rule);
   int init_model(const fsp_model *model, float inv_scale);
@@ -144,9 +147,12 @@ struct BnbState {
   void release();
   int start(int32_t ub0, const std::vector<uint8_t> &perm0);
   int set_target(int64_t target);
-  int enqueue_iteration(hipStream_t s);
+  int enqueue_iteration(hipStream_t s, bool use_model = true);
+  int enqueue_iteration_impl(hipStream_t s);
   int capture(int iters);
-  int replay();
+  int capture_plain(int iters);
+  int replay(bool plain = false);
+  int pending_min_estimate(float *out);
   int commit();
   int read_desc();
 };

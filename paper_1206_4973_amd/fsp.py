@@ -72,7 +72,7 @@ class _Result(ctypes.Structure):
                 ("leaves", ctypes.c_int64), ("pools", ctypes.c_int64),
                 ("t_found_s", ctypes.c_double), ("t_total_s", ctypes.c_double),
                 ("final_pool", ctypes.c_int64), ("t_search_s", ctypes.c_double),
-                ("open_lb", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("open_lb", ctypes.c_int32), ("proof_pools", ctypes.c_int32)]
 
 
 def lib() -> ctypes.CDLL:
@@ -274,7 +274,7 @@ class Result:
     def __repr__(self):
         keys = ("makespan", "found", "status", "root_lb", "nodes_bounded", "nodes_branched",
                 "nodes_pruned", "leaves", "pools", "t_found_s", "t_total_s", "t_search_s",
-                "final_pool", "open_lb")
+                "final_pool", "open_lb", "proof_pools")
         return "Result(" + ", ".join(f"{k}={getattr(self, k)}" for k in keys) + ")"
 
 
