@@ -8,15 +8,19 @@
 //
 // Pending nodes live in one bucket per depth (records + their bounds), in
 // HBM.  Selection takes the last K nodes of the deepest non-empty bucket
-// (LIFO inside a bucket).  Because the children of depth-d parents all go to
-// bucket d+1, and bucket d is only branched when every deeper bucket is empty,
-// a bucket never receives more than one pool of children while it is
-// non-empty, which bounds its size by the largest pool.
+// (LIFO inside a bucket); the batched kinds then continue with the next
+// shallower non-empty buckets, taking each whole until the pool is full
+// (deepest pending nodes first, at most kMaxSeg depths, the last one in
+// part).  The children of depth-d parents all go to bucket d+1, and a bucket
+// receives children only when it is empty (every depth below the deepest
+// taken one is empty, and every taken depth but the last is emptied), so a
+// bucket never holds more than one pool of children, which bounds its size
+// by the largest pool.
 //
 // One iteration = four launches, all sized from a device descriptor so that
 // the sequence can be queued back-to-back (or captured once and replayed):
-//   plan    1 thread: commit the best leaf of the previous pool, pick the
-//           depth and the number of parents, or flag the search as done;
+//   plan    1 wave: commit the best leaf of the previous pool, pick the
+//           depths and the number of parents, or flag the search as done;
 //   branch  one lane per (parent, child slot): a parent whose bound can no
 //           longer beat UB is eliminated (lazy re-check, Sec. II.A); the others
 //           append their unscheduled jobs in ascending id (Sec. II.B: one son
@@ -53,15 +57,19 @@ __device__ __forceinline__ bool keeps(int rule, int lb, int ub) {
 
 // ---- plan ------------------------------------------------------------------
 // Plan the next pool, one wave: commit the best leaf of the previous pool,
-// then take the deepest non-empty depth and as many of its nodes (from the
-// top) as make about `target` children (at least one).  The wave reads 64
-// bucket counts per load, so finding the deepest non-empty depth costs one
-// memory round trip up to 64 jobs.
+// then take parents deepest first: from the deepest non-empty depth as many
+// nodes (from the top) as make about `target` children (at least one); with
+// `multi`, a depth taken whole is followed by the next shallower non-empty
+// depth, and so on (at most kMaxSeg depths), until the target is reached.
+// The wave reads 64 bucket counts per load; every lane then walks the
+// counts in step (uniform values).  Every bucket that receives children is
+// empty when the pool is planned: a depth taken whole is emptied, and the
+// depth below the deepest taken one was empty.
 __global__ __launch_bounds__(64) void plan_kernel(BnbDesc *D, int32_t *bcount,
                                                   const uint8_t *pool, uint8_t *best_perm,
                                                   int n, int stride,
                                                   const int64_t *target_dev,
-                                                  int commit_only) {
+                                                  int commit_only, int multi) {
   const int lane = (int)threadIdx.x;
   int done = 0;
   if (lane == 0) {
@@ -86,32 +94,50 @@ __global__ __launch_bounds__(64) void plan_kernel(BnbDesc *D, int32_t *bcount,
   }
   done = __shfl(done, 0);
   if (commit_only || done) return;
-  int d = -1, c = 0;
-  for (int base = ((n - 1) / 64) * 64; base >= 0 && d < 0; base -= 64) {
+  const int64_t target = *target_dev;
+  int nseg = 0, last_d = -1, last_k = 0, last_c = 0;
+  int64_t children = 0;
+  bool stop = false;
+  for (int base = ((n - 1) / 64) * 64; base >= 0 && !stop; base -= 64) {
     const int idx = base + lane;
     const int cnt = idx < n ? bcount[idx] : 0;
-    const uint64_t mask = __ballot(cnt > 0);
-    if (mask) {
+    uint64_t mask = __ballot(cnt > 0);
+    while (mask && !stop) {
       const int hi = 63 - __builtin_clzll(mask);
-      d = base + hi;
-      c = __shfl(cnt, hi);
+      mask &= ~(1ull << hi);
+      const int d = base + hi, c = __shfl(cnt, hi), u = n - d;
+      int64_t k = (target - children) / u;
+      if (nseg == 0 && k < 1) k = 1;
+      if (k < 1) {
+        stop = true;
+        break;
+      }
+      if (k > c) k = c;
+      if (lane == 0) {
+        D->seg_depth[nseg] = d;
+        D->seg_base[nseg] = c - (int)k;
+        D->seg_off[nseg] = (int)children;
+        bcount[d] = c - (int)k;
+      }
+      children += k * u;
+      ++nseg;
+      last_d = d;
+      last_k = (int)k;
+      last_c = c;
+      if (!multi || k < c || nseg == kMaxSeg) stop = true;
     }
   }
   if (lane != 0) return;
-  if (d < 0) {
+  if (nseg == 0) {
     D->done = 1;
     return;
   }
-  const int u = n - d;
-  const int64_t target = *target_dev;
-  int64_t k = target / u;
-  if (k < 1) k = 1;
-  if (k > c) k = c;
-  D->depth = d;
-  D->parents = (int)k;
-  D->sel_count = c;
-  D->parent_base = c - (int)k;
-  bcount[d] = c - (int)k;
+  D->nseg = nseg;
+  D->seg_off[nseg] = (int)children;
+  D->depth = last_d;
+  D->parents = last_k;
+  D->sel_count = last_c;
+  D->parent_base = last_c - last_k;
   D->active = 1;
   D->pools += 1;
 }
@@ -134,26 +160,33 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
     const float *__restrict__ tscore, float *__restrict__ bscore,
     int32_t *__restrict__ hist, int learned) {
   if (!D->active) return;
-  const int d = D->depth, u = n - d, K = D->parents, base = D->parent_base;
+  const int K = D->parents, base = D->parent_base, nseg = D->nseg;
   const int ub = D->ub;
+  // the last segment is read from the selection scratch when the learned
+  // ordering took part of its depth
   const bool sel = learned && K < D->sel_count;
-  const uint8_t *par_nodes = sel ? tnodes : bnodes + (int64_t)d * cap * stride;
-  const int32_t *par_lb = sel ? tlb : blb + (int64_t)d * cap;
-  const int total = K * u;  // K <= cap and u <= 255: fits 32 bits
+  const int total = D->seg_off[nseg];  // <= target + n: fits 32 bits
   const int gsz = gridDim.x * blockDim.x;
-  const int last_chunk = (1 + d) >> 4;  // chunk holding the new job's byte
   __shared__ int s_cnt[kThreads / 64 + 1];
   int branched = 0, pruned = 0;
   // iterate so that every thread of the grid takes part in each round
   for (int r0 = blockIdx.x * blockDim.x; r0 < total; r0 += gsz) {
     const int slot = r0 + threadIdx.x;
     const bool in = slot < total;
-    int p = 0, c = 0;
-    bool live = false;
+    int p = 0, c = 0, d = 0;
+    bool live = false, from_sel = false;
     if (in) {
-      const int q = slot / u;
-      c = slot - q * u;
-      p = base + q;
+      int s = 0;
+#pragma unroll
+      for (int t = 1; t < kMaxSeg; ++t)
+        if (t < nseg && slot >= D->seg_off[t]) s = t;
+      d = D->seg_depth[s];
+      const int u = n - d, r = slot - D->seg_off[s];
+      const int q = r / u;
+      c = r - q * u;
+      p = D->seg_base[s] + q;
+      from_sel = sel && s == nseg - 1;
+      const int32_t *par_lb = from_sel ? tlb : blb + (int64_t)d * cap;
       live = keeps(rule, par_lb[p], ub);
       if (c == 0) {
         branched += live ? 1 : 0;
@@ -162,10 +195,8 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
     }
     const int pos = block_slot(live, &D->children, s_cnt);
     if (!live) continue;
-    // opaque per round: otherwise the per-byte tests against d below are
-    // hoisted out of the loop, one scalar register pair each
-    int dd = d, lc = last_chunk;
-    asm volatile("" : "+s"(dd), "+s"(lc));
+    const int dd = d, lc = (1 + d) >> 4;  // chunk holding the new job's byte
+    const uint8_t *par_nodes = from_sel ? tnodes : bnodes + (int64_t)d * cap * stride;
     const uint4 *src = reinterpret_cast<const uint4 *>(par_nodes + (int64_t)p * stride);
     uint4 *dst = reinterpret_cast<uint4 *>(pool + (size_t)pos * stride);
     if (n <= 32) {
@@ -239,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void branch_kernel(
   block_total(&D->nodes_branched, branched, s_cnt);
   block_total(&D->nodes_pruned, pruned, s_cnt);
   if (!sel) return;
-  const int64_t at0 = (int64_t)d * cap;
+  const int64_t at0 = (int64_t)D->depth * cap;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < base; i += gsz) {
     const uint4 *src = reinterpret_cast<const uint4 *>(tnodes + (int64_t)i * stride);
     uint4 *dst = reinterpret_cast<uint4 *>(bnodes + (at0 + i) * stride);
@@ -270,7 +301,9 @@ __global__ __launch_bounds__(kThreads) void prune_kernel(
     uint8_t *__restrict__ log_nodes, int32_t *__restrict__ log_lb) {
   if (!D->active) return;
   const int total = D->children;
-  const int d1 = D->depth + 1;
+  const int nseg = D->nseg;
+  // only the deepest segment's children can be complete schedules
+  const bool complete = D->seg_depth[0] + 1 == n;
   const int ub = D->ub;
   if (blockIdx.x == 0 && threadIdx.x == 0)
     atomicAdd(reinterpret_cast<unsigned long long *>(&D->nodes_bounded),
@@ -282,11 +315,12 @@ __global__ __launch_bounds__(kThreads) void prune_kernel(
     const int i = r0 + threadIdx.x;
     const bool in = i < total;
     const int lb = in ? pool_lb[i] : 0;
+    const int d1 = in ? (int)pool[(size_t)i * stride] : 0;  // the child's depth
     const bool leaf = in && d1 == n;
     const bool keep = in && !leaf && keeps(rule, lb, ub);
     leaves += leaf ? 1 : 0;
     pruned += (in && !keep && !(leaf && lb < ub)) ? 1 : 0;
-    if (d1 == n) {
+    if (complete) {
       // the wave's smallest (makespan, index) key, then one atomic per wave
       uint64_t key = (leaf && lb < ub) ? (((uint64_t)(uint32_t)lb << 32) | (uint64_t)i)
                                        : ~0ull;
@@ -298,7 +332,15 @@ __global__ __launch_bounds__(kThreads) void prune_kernel(
         atomicMin(reinterpret_cast<unsigned long long *>(&D->best_key),
                   (unsigned long long)key);
     }
-    const int pos = block_slot(keep, &bcount[d1], s_cnt);
+    // compaction into the bucket of each segment's children (uniform loop)
+    int pos = 0;
+    for (int sg = 0; sg < nseg; ++sg) {
+      const int ds1 = D->seg_depth[sg] + 1;
+      if (ds1 >= n) continue;
+      const bool mine = keep && d1 == ds1;
+      const int ps = block_slot(mine, &bcount[ds1], s_cnt);
+      if (mine) pos = ps;
+    }
     if (!keep) continue;
     if (log_cap > 0 &&
         sample_hash(((uint64_t)D->pools << 32) ^ (uint64_t)i ^ ((uint64_t)log_seed << 16)) <
@@ -467,7 +509,8 @@ int BnbState::init_model(const fsp_model *model_, float inv_scale_) {
       hipMalloc(&tlb, (size_t)cap * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&tscore, (size_t)cap * sizeof(float)) != hipSuccess ||
       hipMalloc(&hist, 4096 * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&X, (size_t)cap * 32 * 2) != hipSuccess)
+      hipMalloc(&X, (size_t)cap * 32 * 2) != hipSuccess ||
+      hipMalloc(&rowdst, (size_t)cap * sizeof(int64_t)) != hipSuccess)
     return FSP_ENOMEM;
   FSP_HIP_TRY(hipMemsetAsync(hist, 0, 4096 * sizeof(int32_t), stream));
   // the root (bucket 0) is alone: any score will do
@@ -496,6 +539,7 @@ void BnbState::release() {
   for (void *p : {(void *)bnodes, (void *)blb, (void *)bcount, (void *)pool, (void *)pool_lb, slots,
                   (void *)desc, (void *)best_perm, (void *)target_dev, (void *)bscore,
                   (void *)tnodes, (void *)tlb, (void *)tscore, (void *)hist, X,
+                  (void *)rowdst,
                   (void *)log_nodes, (void *)log_lb, (void *)min_est})
     if (p) (void)hipFree(p);
   if (host_min_est) (void)hipHostFree(host_min_est);
@@ -544,7 +588,7 @@ int BnbState::enqueue_iteration(hipStream_t s, bool use_model) {
 
 int BnbState::enqueue_iteration_impl(hipStream_t s) {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(64), 0, s, desc, bcount,
-                     pool, best_perm, n, stride, target_dev, 0);
+                     pool, best_perm, n, stride, target_dev, 0, multi);
   FSP_HIP_TRY(hipGetLastError());
   int rc;
   if (model && (rc = policy_enqueue_select(*this, s, grid)) != FSP_OK) return rc;
@@ -632,7 +676,7 @@ int BnbState::pending_min_estimate(float *out) {
 
 int BnbState::commit() {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(64), 0, stream, desc, bcount,
-                     pool, best_perm, n, stride, target_dev, 1);
+                     pool, best_perm, n, stride, target_dev, 1, multi);
   FSP_HIP_TRY(hipGetLastError());
   return FSP_OK;
 }
@@ -821,6 +865,9 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
   BnbState S;
   int rc = S.init(inst, max_pool, policy->prune_rule);
   S.prefilter = policy->prefilter == 1 ? 1 : 0;
+  // the batched kinds fill each pool from several depths, deepest first; the
+  // paper's adaptive kind and fixed pools take one depth per pool
+  S.multi = kind == FSP_POOL_AUTOTUNED || kind == FSP_POOL_LEARNED ? 1 : 0;
   if (rc == FSP_OK && model) rc = S.init_model(model, 1.0f / (float)neh);
   if (rc == FSP_OK && samples) rc = S.init_log(samples->cap, samples->prob, samples->seed);
   if (rc == FSP_OK) rc = S.start(ub0, perm0);

@@ -76,11 +76,17 @@ __device__ __forceinline__ void wave_total(int64_t *counter, int v) {
 // once per batch of pools.
 // bins of the histogram of scores that the best-K selection builds
 constexpr int kSelBins = 4096;
+// depths one pool may take parents from
+constexpr int kMaxSeg = 8;
 
 struct BnbDesc {
   int32_t active;       // the current iteration has parents
-  int32_t depth;        // parent depth of the current pool
-  int32_t parents;      // parents taken from the bucket
+  // The pool's parents come from up to kMaxSeg depths, deepest first: every
+  // depth but the last is taken whole; depth, parents, parent_base and
+  // sel_count describe the last (shallowest) one, the only one a pool may
+  // take in part (and so the one the learned ordering selects in).
+  int32_t depth;        // parent depth of the last segment
+  int32_t parents;      // parents taken from it
   int32_t parent_base;  // index of the first taken parent in its bucket
   int32_t children;     // children written by branch (pool size)
   int32_t ub;           // best makespan known (UB)
@@ -93,6 +99,10 @@ struct BnbDesc {
   int32_t sel_lo, sel_hi, sel_tie;  // best-K selection slot counters
   int32_t feat_count;   // nodes scored after the last prune
   int32_t log_count;    // training samples logged (may exceed the capacity)
+  int32_t nseg;         // depth segments of the current pool
+  int32_t seg_depth[kMaxSeg];  // parent depth of each segment, deepest first
+  int32_t seg_base[kMaxSeg];   // first taken parent's index in its bucket
+  int32_t seg_off[kMaxSeg + 1];  // child-slot offsets: sum of parents x (n - depth)
   int64_t nodes_bounded, nodes_branched, nodes_pruned, leaves, pools;
   uint64_t best_key;    // (makespan << 32) | pool index, best leaf of a pool
 };
@@ -101,6 +111,7 @@ struct BnbState {
   const fsp_instance *inst = nullptr;
   int n = 0, stride = 0, rule = 0, cus = 0;
   int prefilter = 0;  // one-machine pre-filter in the bounding launches
+  int multi = 0;      // pools take parents from several depths (deepest first)
   int64_t cap = 0;  // records per bucket and in the pool buffer
   uint8_t *bnodes = nullptr;   // [n][cap][stride]
   int32_t *blb = nullptr;      // [n][cap]
@@ -125,6 +136,7 @@ struct BnbState {
   float *tscore = nullptr;
   int32_t *hist = nullptr;    // selection histogram (kept zeroed)
   void *X = nullptr;          // [cap][32] bf16 features
+  int64_t *rowdst = nullptr;  // [cap] bucket slot (depth * cap + index) of feature row r
 
   // training samples (log_cap > 0)
   int64_t log_cap = 0;
@@ -171,11 +183,10 @@ int policy_in_features(int m);
 int model_forward_dev(const fsp_model *m, const void *x, const int32_t *n_dev, int64_t max_n,
                       float *y, hipStream_t s);
 // Forward pass whose epilogue writes the learned ordering's estimate instead
-// of the outputs: row r is node r of depth d = *depth_dev + 1, and
-// est[d * rows_per_depth + r] = lb[d * rows_per_depth + r] * inv_scale + y0.
+// of the outputs: row r is the node at bucket slot i = rowdst[r], and
+// est[i] = lb[i] * inv_scale + y0.
 struct ScoreEpilogue {
-  const int32_t *depth_dev;
-  int64_t rows_per_depth;
+  const int64_t *rowdst;
   const int32_t *lb;
   float *est;
   float inv_scale;

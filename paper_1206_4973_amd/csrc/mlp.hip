@@ -144,7 +144,6 @@ __global__ __launch_bounds__(256) void forward_kernel(
     int nout, const fspi::ScoreEpilogue sc) {
   if (n_dev) N = *n_dev;  // row count produced on the device
   if (N <= 0) return;
-  const int64_t sbase = sc.est ? (int64_t)(*sc.depth_dev + 1) * sc.rows_per_depth : 0;
   const int l = lane_id(), g = l >> 4, c = l & 15;
   const int wave = threadIdx.x >> 6;
   // A operands: lane (g, c) holds out feature 16 mt + c, K elements 8g .. 8g+7
@@ -195,7 +194,10 @@ __global__ __launch_bounds__(256) void forward_kernel(
     for (int kt = 0; kt < kH / 32; ++kt) y = mma(w3[kt], h2[kt], y);
     if (row < N) {
       if (sc.est) {
-        if (g == 0) sc.est[sbase + row] = (float)sc.lb[sbase + row] * sc.inv_scale + y[0];
+        if (g == 0) {
+          const int64_t at = sc.rowdst[row];
+          sc.est[at] = (float)sc.lb[at] * sc.inv_scale + y[0];
+        }
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i)

@@ -103,22 +103,36 @@ __device__ __forceinline__ void node_features(const uint8_t *rec, int lb,
   }
 }
 
-// features of the nodes of bucket `depth + 1`
+// features of the nodes that the last prune added: the buckets one below
+// each depth segment of the pool (each was empty before that prune), rows
+// in segment order; rowdst[r] is the bucket slot of row r
 template <int M>
 __global__ __launch_bounds__(256) void features_kernel(
     BnbDesc *D, const int32_t *__restrict__ bcount, const uint8_t *__restrict__ bnodes,
     const int32_t *__restrict__ blb, int64_t cap, int stride,
     const int32_t *__restrict__ p, const int32_t *__restrict__ tot, int n, int mp,
-    float inv_scale, __bf16 *__restrict__ X) {
-  const bool act = D->active && D->depth + 1 < n;
-  const int d1 = D->depth + 1;
-  const int count = act ? bcount[d1] : 0;
+    float inv_scale, __bf16 *__restrict__ X, int64_t *__restrict__ rowdst) {
+  const int nseg = D->active ? D->nseg : 0;
+  int off[kMaxSeg + 1], dep[kMaxSeg];
+  off[0] = 0;
+#pragma unroll
+  for (int s = 0; s < kMaxSeg; ++s) {
+    const int d1 = s < nseg ? D->seg_depth[s] + 1 : n;
+    dep[s] = d1;
+    off[s + 1] = off[s] + (d1 < n ? bcount[d1] : 0);
+  }
+  const int count = off[kMaxSeg];
   if (blockIdx.x == 0 && threadIdx.x == 0) D->feat_count = count;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += gridDim.x * blockDim.x) {
-    const int64_t at = (int64_t)d1 * cap + i;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < count;
+       r += gridDim.x * blockDim.x) {
+    int s = 0;
+#pragma unroll
+    for (int t = 1; t < kMaxSeg; ++t)
+      if (r >= off[t]) s = t;
+    const int64_t at = (int64_t)dep[s] * cap + (r - off[s]);
     node_features<M>(bnodes + at * stride, blb[at], p, tot, n, mp, inv_scale,
-                     X + (int64_t)i * kFeat);
+                     X + (int64_t)r * kFeat);
+    rowdst[r] = at;
   }
 }
 
@@ -360,10 +374,10 @@ int policy_enqueue_score(BnbState &S, hipStream_t s, int grid) {
   FeatBucketFn fn = bucket_fn(in->m, std::make_integer_sequence<int, kMaxMachines - 1>());
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, S.desc, S.bcount, S.bnodes, S.blb, S.cap,
                      S.stride, in->d_p, in->d_tot, in->n, in->mp, S.inv_scale,
-                     reinterpret_cast<__bf16 *>(S.X));
+                     reinterpret_cast<__bf16 *>(S.X), S.rowdst);
   FSP_HIP_TRY(hipGetLastError());
   // the forward pass writes est = bound / s + predicted gap itself
-  const ScoreEpilogue sc{&S.desc->depth, S.cap, S.blb, S.bscore, S.inv_scale};
+  const ScoreEpilogue sc{S.rowdst, S.blb, S.bscore, S.inv_scale};
   return model_forward_score_dev(S.model, S.X, &S.desc->feat_count, S.cap, sc, s);
 }
 
