@@ -311,14 +311,21 @@ typedef struct {
  * FSP_POOL_LEARNED: as FSP_POOL_AUTOTUNED, and policy->model (an fsp_model
  * with 2 + 2 min(m, 15) inputs) orders the pools and sets their size.  While
  * the smallest estimated completion (bound + predicted gap) among the pending
- * nodes is below UB, a pool that takes only part of a depth takes its nodes
- * with the smallest estimates, with the autotuned number of children; once
- * that smallest estimate reaches UB (the network expects no pending node to
- * beat UB: what is left is a proof, in which order does not matter), pools
- * take the largest size the buffers hold (policy->max_pool, or the device's
- * resident threads) and the network is no longer run (proof_pools = 1).  The
- * exact bound still decides every elimination, so the optimum does not
- * depend on the model.
+ * nodes is below UB, the search dives: pools of a sixteenth of the autotuned
+ * (or fixed_pool) number of children, doubled after every batch of
+ * nb_iterations pools that does not improve UB (reset by an improvement),
+ * and a pool that takes only part of a depth takes its nodes with the
+ * smallest estimates; once that smallest
+ * estimate reaches UB (the network expects no pending node to beat UB: what
+ * is left is a proof, in which order does not matter), pools take the
+ * largest size the buffers hold (policy->max_pool, or the device's resident
+ * threads) and the network is no longer run (proof_pools = 1).  The exact
+ * bound still decides every elimination, so the optimum does not depend on
+ * the model.
+ * FSP_POOL_AUTOTUNED and FSP_POOL_LEARNED fill a pool from several depths,
+ * deepest first (a depth taken whole is followed by the next shallower one,
+ * at most eight); FSP_POOL_FIXED and FSP_POOL_ADAPTIVE take one depth per
+ * pool.
  */
 int fsp_branch_and_bound(const fsp_instance *inst,
                          const fsp_pool_policy *policy, int32_t ub_in,
