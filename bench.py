@@ -288,33 +288,54 @@ def batch_workload(steps, warmup) -> dict:
     shapes = [(n, m) for n in (20, 50, 100) for m in (5, 10, 20)]
     rng = np.random.default_rng(3000)
     exps = [int(e) for e in rng.integers(10, 19, size=64)]
-    items, ops, nodes = [], 0, 0
+    items, ops, nodes, seg_ops = [], 0, 0, []
     for i in range(64):
         n, m = shapes[i % 9]
         pool = inputs.random_pool(n, 1 << exps[i], 1, n - 1, 3000 + 500000 + i)
         items.append((fsp.Instance(inputs.instance(n, m, 3000 + i)),
                       torch.from_numpy(pool).cuda(), None))
-        ops += algorithmic_ops(pool[:, 0], n, m)
+        seg_ops.append(algorithmic_ops(pool[:, 0], n, m))
+        ops += seg_ops[-1]
         nodes += len(pool)
     stream = torch.cuda.current_stream()
-    b = fsp.Batch(items)
+    t0 = time.perf_counter()
+    b = fsp.Batch(items, autotune=True)
+    t_plan = time.perf_counter() - t0
     t_batch = timed(lambda: b.replay(stream), steps, warmup, stream)
+    progress(f"batch, autotuned: {t_batch * 1e3:.3f} ms (planned in {t_plan:.2f} s)")
+    b_def = fsp.Batch([(i, nd, None) for i, nd, _ in items])
+    t_def = timed(lambda: b_def.replay(stream), steps, warmup, stream)
+    b_one = fsp.Batch([(i, nd, None) for i, nd, _ in items], packed=False)
+    t_one = timed(lambda: b_one.replay(stream), steps, warmup, stream)
     outs = [torch.empty(x[1].shape[0], dtype=torch.int32, device="cuda") for x in items]
 
     def separate():
         for (inst, nd, _), o in zip(items, outs):
             inst.bound_pool(nd, o, stream=stream)
     t_sep = timed(separate, steps, warmup, stream)
-    same = all(torch.equal(a, c) for a, c in zip(b.outs, outs))
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, c) and torch.equal(a, d) and torch.equal(a, e)
+               for a, c, d, e in zip(b.outs, outs, b_def.outs, b_one.outs))
+    paths, bpc = b.paths()
+    # the packed segments count their work against the packed peak, the
+    # others against the 32-bit peak: the launch's peak is the work-weighted
+    # mean of the two
+    ops_pk = sum(o for o, pth in zip(seg_ops, paths) if pth == "packed")
+    peak = ops / (ops_pk / PK16_PEAK_TOPS + (ops - ops_pk) / INT32_PEAK_TOPS)
     achieved = ops / t_batch / 1e12
+    form_count = {k: paths.count(k) for k in sorted(set(p for p in paths if p))}
     return {"workload": "batch: 64 instances, n in {20,50,100} x m in {5,10,20}, "
                         "pools 2^10..2^18 (seed 3000)",
             "nodes": nodes, "steps": steps, "warmup": warmup, "batch_info": b.info(),
+            "autotuned": {"forms": form_count, "blocks_per_cu": bpc, "plan_s": t_plan},
             "one_launch": {"ms": t_batch * 1e3, "nodes_per_s": nodes / t_batch,
-                           "achieved_TOPs": achieved, "frac": achieved / INT32_PEAK_TOPS},
-            "separate_launches": {"ms": t_sep * 1e3, "nodes_per_s": nodes / t_sep,
-                                  "frac": ops / t_sep / 1e12 / INT32_PEAK_TOPS},
-            "identical_bounds": bool(same), "peak_TOPs": INT32_PEAK_TOPS}
+                           "achieved_TOPs": achieved, "peak_TOPs": peak,
+                           "frac": achieved / peak},
+            "one_launch_default_plan": {"ms": t_def * 1e3, "nodes_per_s": nodes / t_def},
+            "one_launch_one_node_per_lane": {"ms": t_one * 1e3, "nodes_per_s": nodes / t_one,
+                                             "frac_int32": ops / t_one / 1e12 / INT32_PEAK_TOPS},
+            "separate_launches": {"ms": t_sep * 1e3, "nodes_per_s": nodes / t_sep},
+            "identical_bounds": bool(same)}
 
 
 def large_workload(steps, warmup, bnb_time, prefilter=False, shapes=None, kinds=None,

@@ -192,11 +192,27 @@ typedef struct {
   int32_t *lb_out;
 } fsp_segment;
 
-/* Launch shape of a batch (NULL or 0 fields: the defaults, i.e. as many
- * workgroups per compute unit as fit). */
+/* Launch shape of a batch (a NULL config, or all fields 0: the defaults).
+ *   blocks_per_cu     workgroups per compute unit; 0: as many as fit (or the
+ *                     autotuner's pick).
+ *   autotune          1: before planning, time the candidate walk forms of
+ *                     each (n, m) shape on the batch's own segments of that
+ *                     shape (packed or 32-bit for n <= 32, 64-bit register or
+ *                     job masks for 33..64 jobs), then the workgroups per CU
+ *                     on the whole batch, and keep the fastest; the picks
+ *                     are cached per device and shape (forms) and per batch
+ *                     signature (workgroups per CU), so later batches of the
+ *                     same shapes plan without timing.  Timing launches the
+ *                     batch: its lb_out buffers are written.  0: every
+ *                     segment takes its shape's default form (the fastest in
+ *                     single-pool measurements, as fsp_instance_path).
+ *   one_node_per_lane 1: never the packed two-nodes-per-lane form.
+ * Other values are FSP_EINVAL. */
 typedef struct {
   int32_t blocks_per_cu;
-  int32_t reserved[3];
+  int32_t autotune;
+  int32_t one_node_per_lane;
+  int32_t reserved;
 } fsp_batch_config;
 
 typedef struct fsp_batch fsp_batch;
@@ -207,9 +223,10 @@ typedef struct fsp_batch fsp_batch;
  * table (instances, device pointers, counts) is copied to the device; the
  * node buffers themselves are read at launch time, so their contents may
  * change between launches.  Segments of 5, 10 or 20 machines share the one
- * persistent kernel; any other machine count is bounded by single-pool
- * launches queued right after it.  Synchronous.  Release with fsp_batch_free
- * once no queued launch uses it.
+ * persistent kernel, each in its walk form (two nodes per lane for n <= 32
+ * with small times, see fsp_instance_path); any other machine count is
+ * bounded by single-pool launches queued right after it.  Synchronous.
+ * Release with fsp_batch_free once no queued launch uses it.
  */
 int fsp_batch_create(const fsp_segment *segs, int32_t nsegs,
                      const fsp_batch_config *cfg, fsp_batch **out);
@@ -221,10 +238,18 @@ int fsp_batch_launch(fsp_batch *b, void *stream);
  * call and replayed on every call (on `stream`). */
 int fsp_batch_replay(fsp_batch *b, void *stream);
 
-/* Tiles of 256 nodes, persistent grid size, segments in the batch kernel and
- * segments bounded by single-pool launches (any pointer may be NULL). */
+/* Tiles (256 nodes, or 512 in the packed form), persistent grid size,
+ * segments in the batch kernel and segments bounded by single-pool launches
+ * (any pointer may be NULL). */
 int fsp_batch_info(const fsp_batch *b, int64_t *tiles, int32_t *grid,
                    int32_t *kernel_segments, int32_t *fallback_segments);
+
+/* The walk form (FSP_PATH_*) each of the nsegs segments given to
+ * fsp_batch_create takes (-1: empty segment, or bounded by a single-pool
+ * launch, which takes fsp_instance_path), and the workgroups per CU of the
+ * batch kernel.  nsegs must equal the count given at creation. */
+int fsp_batch_paths(const fsp_batch *b, int32_t *paths, int32_t nsegs,
+                    int32_t *blocks_per_cu);
 
 int fsp_batch_free(fsp_batch *b);
 

@@ -510,7 +510,7 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
                                             const Prefilter pf = Prefilter()) {
   constexpr bool WIDE = FORM == kFormMasks;
   const int tid = threadIdx.x;
-  const int n = I.n, mp = I.mp, npad = I.npad;
+  const int n = I.n, npad = I.npad;
   char *s_rec = L.s_rec;
   const int32_t *s_p = L.s_p;
   uint32_t *words_lane = WIDE ? L.s_words + tid : nullptr;

@@ -49,7 +49,8 @@ class _Segment(ctypes.Structure):
 
 
 class _BatchConfig(ctypes.Structure):
-    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("one_node_per_lane", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 POOL_KINDS = {"fixed": 0, "adaptive": 1, "autotuned": 2, "learned": 3}
@@ -120,6 +121,8 @@ def lib() -> ctypes.CDLL:
     L.fsp_batch_replay.restype = ctypes.c_int
     L.fsp_batch_info.argtypes = [P, P, P, P, P]
     L.fsp_batch_info.restype = ctypes.c_int
+    L.fsp_batch_paths.argtypes = [P, P, i32, P]
+    L.fsp_batch_paths.restype = ctypes.c_int
     L.fsp_batch_free.argtypes = [P]
     L.fsp_batch_free.restype = ctypes.c_int
     L.fsp_bound_batch.argtypes = [ctypes.POINTER(_Segment), i32, P]
@@ -385,11 +388,15 @@ class Batch:
     int32 [count] device tensor or None).  The tensors must stay alive (and
     keep their storage) as long as the batch is used."""
 
-    def __init__(self, items, blocks_per_cu: int = 0):
+    def __init__(self, items, blocks_per_cu: int = 0, autotune: bool = False,
+                 packed: bool = True):
         self._keep = [(i, n) for i, n, _ in items]
+        self.nsegs = len(items)
         segs, self.outs = _segments(items)
         cfg = _BatchConfig()
         cfg.blocks_per_cu = int(blocks_per_cu)
+        cfg.autotune = 1 if autotune else 0
+        cfg.one_node_per_lane = 0 if packed else 1
         h = ctypes.c_void_p()
         _check(lib().fsp_batch_create(segs, len(items), ctypes.byref(cfg), ctypes.byref(h)),
                "fsp_batch_create")
@@ -410,6 +417,15 @@ class Batch:
                                     ctypes.byref(ks), ctypes.byref(fs)), "fsp_batch_info")
         return {"tiles": tiles.value, "grid": grid.value, "kernel_segments": ks.value,
                 "fallback_segments": fs.value}
+
+    def paths(self):
+        """(walk form name of every segment, or None; workgroups per CU)."""
+        arr = (ctypes.c_int32 * max(1, self.nsegs))()
+        bpc = ctypes.c_int32()
+        _check(lib().fsp_batch_paths(self._h, arr, self.nsegs, ctypes.byref(bpc)),
+               "fsp_batch_paths")
+        names = {0: "register", 1: "packed", 2: "masks", 3: "register64"}
+        return [names.get(arr[i]) for i in range(self.nsegs)], bpc.value
 
     def close(self):
         if getattr(self, "_h", None) is not None:

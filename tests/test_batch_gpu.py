@@ -67,6 +67,63 @@ def test_mixed_batch_matches_oracle_and_single_launches(fsp, orc):
     b.close()
 
 
+def test_forms_in_one_launch(fsp, orc):
+    """Packed, 32-bit, 64-bit-register and job-mask segments in one launch
+    (the same 20-job shape both packed and, with large times, 32-bit), with
+    ragged tails of both tile sizes: every node equals the oracle, and the
+    batch reports the form each segment took."""
+    rng = np.random.default_rng(11)
+    big = rng.integers(1500, 3000, size=(20, 10)).astype(np.int32)  # total > 32767
+    cases = [(I.instance(20, 10, 3501), 1537), (big, 999), (I.instance(20, 20, 3502), 513),
+             (I.instance(50, 10, 3503), 700), (I.instance(100, 5, 3504), 900),
+             (I.instance(20, 5, 3505), 511)]
+    items, host = [], []
+    for i, (p, cnt) in enumerate(cases):
+        n = p.shape[0]
+        pool = I.random_pool(n, cnt, 0, n, 3600 + i)
+        items.append((fsp.Instance(p), torch.from_numpy(pool).cuda(), None))
+        host.append((p, pool))
+    b = fsp.Batch(items)
+    paths, bpc = b.paths()
+    say("paths", paths, "blocks per CU", bpc)
+    assert paths == ["packed", "register", "packed", "register64", "masks", "packed"]
+    outs = b.launch()
+    torch.cuda.synchronize()
+    for out, (p, pool) in zip(outs, host):
+        assert np.array_equal(out.cpu().numpy(), orc.bound_pool(p, pool, nthreads=8))
+    b.close()
+    one = fsp.Batch(items, packed=False)
+    assert one.paths()[0][0] == "register" and one.paths()[0][2] == "register"
+    outs1 = one.launch()
+    torch.cuda.synchronize()
+    for o1, (p, pool) in zip(outs1, host):
+        assert np.array_equal(o1.cpu().numpy(), orc.bound_pool(p, pool, nthreads=8))
+    one.close()
+
+
+def test_autotuned_batch_matches_oracle_and_caches(fsp, orc):
+    """An autotuned batch (forms per shape and workgroups per CU timed on its
+    own segments) bounds every node as the oracle does; a second batch of
+    the same shapes takes the cached picks."""
+    import time
+    shapes = [(20, 10), (20, 20), (50, 20), (33, 5), (100, 10)]
+    items, host = mixed_batch(fsp, lambda i: 3000 + 777 * i, 3700, shapes)
+    t0 = time.perf_counter()
+    b = fsp.Batch(items, autotune=True)
+    t1 = time.perf_counter()
+    paths, bpc = b.paths()
+    say("autotuned paths", paths, "blocks per CU", bpc, f"planned in {t1 - t0:.3f} s")
+    assert all(x is not None for x in paths) and bpc >= 1
+    outs = b.replay()
+    torch.cuda.synchronize()
+    for out, (p, pool) in zip(outs, host):
+        assert np.array_equal(out.cpu().numpy(), orc.bound_pool(p, pool, nthreads=8))
+    b2 = fsp.Batch(items, autotune=True)
+    assert b2.paths() == (paths, bpc)
+    b.close()
+    b2.close()
+
+
 def test_one_shot_and_empty_segments(fsp, orc):
     items, host = mixed_batch(fsp, lambda i: [0, 700, 0][i], 3200, [(20, 20), (50, 10), (9, 5)])
     outs = fsp.bound_batch(items)
