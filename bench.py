@@ -142,7 +142,8 @@ def paired_summary(rows, base, kind, limit):
     }
 
 
-def bnb_leg(seeds, time_limit, only=None, prefilter=False, kinds=None) -> dict:
+def bnb_leg(seeds, time_limit, only=None, prefilter=False, kinds=None,
+            host_threads=0) -> dict:
     """Time to a proven optimum on held-out 20x10 instances: plain adaptive
     (the paper's Algorithm 1, launch by launch) vs batched (graph-replayed
     iterations, autotuned pool) vs batched + learned ordering and pool size.
@@ -165,18 +166,19 @@ def bnb_leg(seeds, time_limit, only=None, prefilter=False, kinds=None) -> dict:
         for kind in kinds:
             kw = {"model": model} if kind == "learned" else {}
             r = fsp.branch_and_bound(inst, kind, time_limit=time_limit,
-                                     prefilter=prefilter, **kw)
+                                     prefilter=prefilter, host_threads=host_threads, **kw)
             progress(f"bnb seed {s} {kind}: {r.makespan} "
                      f"{'proven' if r.status == 0 else 'censored'} in {r.t_total_s:.3f} s")
             row[kind] = {"makespan": r.makespan, "proven": r.status == 0,
                          "t_proof_s": r.t_total_s, "t_found_s": r.t_found_s,
                          "t_search_s": r.t_search_s, "nodes": r.nodes_bounded,
                          "pools": r.pools, "pool": r.final_pool,
-                         "proof_pools": r.proof_pools}
+                         "proof_pools": r.proof_pools, "host_nodes": r.host_nodes}
         inst.close()
         rows.append(row)
     out = {"instances": f"20x10, seeds {seeds[0]}..{seeds[-1]} ({len(seeds)} held out)",
            "time_limit_s": time_limit, "kinds": kinds, "one_machine_prefilter": prefilter,
+           "host_threads": host_threads,
            "leg_wall_s": time.perf_counter() - t_leg}
     # an exact search proves the same optimum whatever its kind: compare the
     # makespans of the kinds that proved it
@@ -435,6 +437,9 @@ def main() -> int:
                     help="time limit of each search of the 20x20 instance (s)")
     ap.add_argument("--bnb-seeds", type=int, default=0,
                     help="with --workload bnb: only the first K held-out seeds")
+    ap.add_argument("--host-threads", type=int, default=0,
+                    help="with --workload bnb: hybrid search, this many CPU threads "
+                         "exploring subtrees beside the device")
     ap.add_argument("--bnb-time", type=float, default=60.0,
                     help="time limit of each search of the large workload (s)")
     ap.add_argument("--large-shapes", default=None,
@@ -481,7 +486,8 @@ def main() -> int:
         return 0
     if args.workload == "bnb":
         seeds = HELD_OUT_SEEDS[:args.bnb_seeds] if args.bnb_seeds else HELD_OUT_SEEDS
-        print(json.dumps(bnb_leg(seeds, args.bnb_limit, args.bnb_kind, args.prefilter)),
+        print(json.dumps(bnb_leg(seeds, args.bnb_limit, args.bnb_kind, args.prefilter,
+                                 host_threads=args.host_threads)),
               flush=True)
         return 0
     n, m, seed = 20, 20, 2000

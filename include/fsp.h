@@ -108,8 +108,7 @@ int fsp_instance_info(const fsp_instance *inst, int32_t *n, int32_t *m,
  *                        by scalar loads;
  *   FSP_PATH_REGISTER64  32 < n <= 64: one node per lane, the unscheduled set
  *                        in a 64-bit register pair.
- * The batch kernel uses the one-node-per-lane forms (register, register64,
- * masks). */
+ * A batch may take another allowed form per shape (fsp_batch_paths). */
 enum { FSP_PATH_REGISTER = 0, FSP_PATH_PACKED = 1, FSP_PATH_MASKS = 2,
        FSP_PATH_REGISTER64 = 3 };
 int fsp_instance_path(const fsp_instance *inst, int32_t *path);
@@ -293,6 +292,12 @@ typedef struct {
                              eliminations, same optimum); 0: none          */
   const void *model;      /* FSP_POOL_LEARNED: the policy network          */
   const char *log_path;   /* one JSON line per batch of pools; NULL: none  */
+  int32_t host_threads;   /* hybrid search (Sec. VI, future work): CPU
+                             threads that explore, beside the device, the
+                             subtrees of nodes with at most six unscheduled
+                             jobs taken from the deepest bucket whenever
+                             they are idle, sharing UB with the device at
+                             every batch of pools; 0: none                 */
 } fsp_pool_policy;
 
 typedef struct {
@@ -318,6 +323,8 @@ typedef struct {
                          makespan                                           */
   int32_t proof_pools; /* FSP_POOL_LEARNED: 1 if the network's estimates
                          switched the search to proof pools (see below)    */
+  int64_t host_nodes;  /* of nodes_bounded, those bounded by host threads
+                         (policy->host_threads > 0)                         */
 } fsp_result;
 
 /*

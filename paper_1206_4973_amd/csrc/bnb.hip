@@ -44,6 +44,7 @@
 
 #include "fsp_internal.hpp"
 #include "bnb.hpp"
+#include "host_search.hpp"
 
 using namespace fspi;
 
@@ -809,11 +810,49 @@ int tuned_pool(const fsp_instance *inst, int64_t *pool) {
   return rc;
 }
 
+// One exchange of the hybrid search, between two batches of device pools
+// (the device stream is idle): UB both ways, then, if the host threads are
+// idle, hand them nodes with at most `left` unscheduled jobs from the top of
+// the deepest non-empty bucket.
+int hybrid_exchange(BnbState &S, HostSearch &hs, const BnbDesc &h, int threads, int left,
+                    int chunk, std::vector<int32_t> &hcount, std::vector<uint8_t> &hrec,
+                    std::vector<int32_t> &hlb) {
+  const int n = S.n;
+  const int32_t hub = hs.ub_host.load();
+  if (hub < h.ub) {
+    FSP_HIP_TRY(hipMemcpy(&S.desc->ub, &hub, sizeof(int32_t), hipMemcpyHostToDevice));
+  } else {
+    int32_t cur = hub;
+    while (h.ub < cur && !hs.ub_host.compare_exchange_weak(cur, h.ub)) {
+    }
+  }
+  if (h.done || !hs.idle()) return FSP_OK;
+  FSP_HIP_TRY(hipMemcpy(hcount.data(), S.bcount, (size_t)n * sizeof(int32_t),
+                        hipMemcpyDeviceToHost));
+  int d = n - 1;
+  while (d >= 0 && hcount[d] == 0) --d;
+  if (d < 0 || n - d > left) return FSP_OK;
+  const int c = (int)std::min<int64_t>(hcount[d], S.cap);
+  const int k = std::min(c, chunk * threads);
+  hrec.resize((size_t)k * S.stride);
+  hlb.resize(k);
+  const int64_t at = (int64_t)d * S.cap + (c - k);
+  FSP_HIP_TRY(hipMemcpy(hrec.data(), S.bnodes + at * S.stride, (size_t)k * S.stride,
+                        hipMemcpyDeviceToHost));
+  FSP_HIP_TRY(hipMemcpy(hlb.data(), S.blb + at, (size_t)k * sizeof(int32_t),
+                        hipMemcpyDeviceToHost));
+  const int32_t rest = c - k;
+  FSP_HIP_TRY(hipMemcpy(S.bcount + d, &rest, sizeof(int32_t), hipMemcpyHostToDevice));
+  hs.give(hrec.data(), hlb.data(), k, S.stride);
+  return FSP_OK;
+}
+
 int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_in,
             fsp_result *out, const SampleSpec *samples, RateWindow *window) {
   if (!inst || !policy || !out) return FSP_EINVAL;
   if (policy->prune_rule != FSP_PRUNE_GE && policy->prune_rule != FSP_PRUNE_GT)
     return FSP_EINVAL;
+  if (policy->host_threads < 0 || policy->host_threads > 256) return FSP_EINVAL;
   const int kind = policy->kind;
   if (kind < FSP_POOL_FIXED || kind > FSP_POOL_LEARNED) return FSP_EINVAL;
   if (kind == FSP_POOL_FIXED && policy->fixed_pool < 1) return FSP_EINVAL;
@@ -881,6 +920,16 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
 
   AdaptivePolicy ap;
   ap.init(256, cus, device_threads, max_pool);
+  // hybrid: host threads take nodes with at most kHostLeft unscheduled jobs
+  // from the deepest bucket whenever they are idle (between two batches),
+  // kHostChunk per thread, and search their subtrees on the CPU
+  constexpr int kHostLeft = 6, kHostChunk = 64;
+  const int host_threads = policy->host_threads;
+  HostSearch hs;
+  std::vector<int32_t> hcount(n);
+  std::vector<uint8_t> hrec;
+  std::vector<int32_t> hlb;
+  if (host_threads > 0) hs.start(inst, host_threads, policy->prune_rule, ub0, t_start);
   FILE *log = policy->log_path ? std::fopen(policy->log_path, "w") : nullptr;
 
   int status = 0;
@@ -939,6 +988,9 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
       rc = FSP_ENOMEM;
       break;
     }
+    if (host_threads > 0 && (rc = hybrid_exchange(S, hs, h, host_threads, kHostLeft,
+                                                   kHostChunk, hcount, hrec, hlb)) != FSP_OK)
+      break;
     if (h.done) break;
     const bool stretch = window && window->batches < window->min_batches &&
                          t1 < window->max_s;
@@ -963,6 +1015,12 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
       rc = FSP_EDEVICE;
       break;
     }
+  }
+  if (host_threads > 0) {
+    // the device is done (or out of time): let the host finish its subtrees
+    // (each has at most kHostLeft unscheduled jobs), unless out of time
+    if (rc == FSP_OK && status == 0) hs.wait_idle();
+    hs.stop_threads();
   }
   const double t_loop = elapsed() - t_loop0;
   if (rc == FSP_OK) rc = S.commit();
@@ -1028,6 +1086,22 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
                      ? std::min<int32_t>(open_lb, h.ub)
                      : h.ub;
   out->proof_pools = proof ? 1 : 0;
+  if (host_threads > 0) {
+    out->nodes_bounded += hs.total.bounded;
+    out->nodes_branched += hs.total.branched;
+    out->nodes_pruned += hs.total.pruned;
+    out->leaves += hs.total.leaves;
+    out->host_nodes = hs.total.bounded;
+    if (hs.best < INT32_MAX && hs.best <= out->makespan) {
+      // the best schedule was found by a host thread (a device leaf can only
+      // replace UB when strictly better)
+      out->makespan = hs.best;
+      out->found = hs.best < ub0 ? 1 : out->found;
+      if (user_perm) std::copy(hs.best_perm, hs.best_perm + n, user_perm);
+      out->t_found_s = hs.t_found;
+    }
+    if (status == 1) out->open_lb = std::min(out->open_lb, std::min(hs.open_lb(), out->makespan));
+  }
   S.release();
   return FSP_OK;
 }

@@ -62,7 +62,7 @@ class _Policy(ctypes.Structure):
                 ("fixed_pool", ctypes.c_int64), ("max_pool", ctypes.c_int64),
                 ("time_limit_s", ctypes.c_double), ("prune_rule", ctypes.c_int32),
                 ("prefilter", ctypes.c_int32), ("model", ctypes.c_void_p),
-                ("log_path", ctypes.c_char_p)]
+                ("log_path", ctypes.c_char_p), ("host_threads", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -73,7 +73,8 @@ class _Result(ctypes.Structure):
                 ("leaves", ctypes.c_int64), ("pools", ctypes.c_int64),
                 ("t_found_s", ctypes.c_double), ("t_total_s", ctypes.c_double),
                 ("final_pool", ctypes.c_int64), ("t_search_s", ctypes.c_double),
-                ("open_lb", ctypes.c_int32), ("proof_pools", ctypes.c_int32)]
+                ("open_lb", ctypes.c_int32), ("proof_pools", ctypes.c_int32),
+                ("host_nodes", ctypes.c_int64)]
 
 
 def lib() -> ctypes.CDLL:
@@ -277,14 +278,14 @@ class Result:
     def __repr__(self):
         keys = ("makespan", "found", "status", "root_lb", "nodes_bounded", "nodes_branched",
                 "nodes_pruned", "leaves", "pools", "t_found_s", "t_total_s", "t_search_s",
-                "final_pool", "open_lb", "proof_pools")
+                "final_pool", "open_lb", "proof_pools", "host_nodes")
         return "Result(" + ", ".join(f"{k}={getattr(self, k)}" for k in keys) + ")"
 
 
 def make_policy(kind: str = "adaptive", *, fixed_pool: int = 0, max_pool: int = 0,
                 nb_iterations: int = 10, time_limit: float | None = None,
                 prune_rule: str = "ge", model=None, log_path: str | None = None,
-                prefilter: bool = False) -> _Policy:
+                prefilter: bool = False, host_threads: int = 0) -> _Policy:
     pol = _Policy()
     pol.kind = POOL_KINDS[kind]
     pol.nb_iterations = int(nb_iterations)
@@ -295,6 +296,7 @@ def make_policy(kind: str = "adaptive", *, fixed_pool: int = 0, max_pool: int = 
     pol.prefilter = 1 if prefilter else 0
     pol.model = ctypes.c_void_p(model.handle.value) if model is not None else None
     pol.log_path = log_path.encode() if log_path else None
+    pol.host_threads = int(host_threads)
     return pol
 
 

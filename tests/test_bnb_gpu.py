@@ -107,7 +107,12 @@ def test_critical_tree_counts_equal_oracle(fsp, orc, n, m, seed, rule):
                      ("fixed", {"fixed_pool": 37, "prefilter": True}),
                      ("adaptive", {"prefilter": True}),
                      ("autotuned", {"fixed_pool": 64, "prefilter": True}),
-                     ("learned", {"fixed_pool": 3000, "model": model, "prefilter": True})):
+                     ("learned", {"fixed_pool": 3000, "model": model, "prefilter": True}),
+                     # hybrid: host threads search subtrees handed over by the device
+                     ("fixed", {"fixed_pool": 37, "host_threads": 4}),
+                     ("adaptive", {"host_threads": 3}),
+                     ("autotuned", {"fixed_pool": 64, "host_threads": 4}),
+                     ("learned", {"fixed_pool": 3000, "model": model, "host_threads": 2})):
         res = fsp.branch_and_bound(inst, kind, ub=opt, prune_rule=rule, **kw)
         say(f"{n}x{m} {rule} {kind} {kw}: {res.nodes_bounded} vs {ost.nodes_bounded}")
         assert res.makespan == opt and res.found == 0 and res.status == 0
@@ -266,3 +271,24 @@ def test_adaptive_pool_trajectory_follows_algorithm_1(fsp, tmp_path):
     assert targets[k - 1] * 2 > max_threads or k == len(targets)
     assert fsp.adaptive_schedule(effs, cus, max_threads) == targets
     assert res.final_pool == targets[-1]
+
+
+@pytest.mark.parametrize("kind", ["adaptive", "autotuned", "fixed"])
+def test_hybrid_reaches_the_optimum(fsp, orc, kind):
+    """Host threads exploring subtrees beside the device (the hybrid search):
+    the optimum equals the oracle's, the schedule is valid, and the host did
+    bound nodes."""
+    host_total = 0
+    for n, m, seed in ((12, 6, 61), (14, 7, 63), (15, 6, 64)):
+        p = I.instance(n, m, seed)
+        oc, _, _ = orc.bnb(p)
+        inst = fsp.Instance(p)
+        kw = {"fixed_pool": 50} if kind == "fixed" else {}
+        res = fsp.branch_and_bound(inst, kind, host_threads=4, **kw)
+        say(f"hybrid {kind} {n}x{m}: {res.makespan} vs {oc}, host nodes {res.host_nodes} "
+            f"of {res.nodes_bounded}")
+        assert res.status == 0 and res.makespan == oc
+        check_schedule(orc, p, res)
+        assert 0 <= res.host_nodes <= res.nodes_bounded
+        host_total += res.host_nodes
+    assert host_total > 0
