@@ -10,11 +10,13 @@
 // Forward: layers computed transposed so that each result tile is already
 // the next layer's operand (see forward_kernel); weights and biases stay in
 // registers and each wave streams 16-row tiles.
-// Backward: one workgroup per 64-row tile (4 waves); the forward is recomputed,
-// then dW3, dH2, dW2 = H1^T dZ2, dH1 = dZ2 W2^T, dW1 = X^T dZ1 and dX = dZ1 W1^T
-// are products on the matrix cores; each workgroup accumulates its weight
-// gradients over its tiles and writes one partial; a second kernel sums the
-// partials in a fixed order (deterministic).
+// Backward: one workgroup per 64-row tile (8 waves, each owning a band of 16
+// hidden units); the forward is recomputed, then dW3, dH2, dW2 = H1^T dZ2,
+// dH1 = dZ2 W2^T, dW1 = X^T dZ1, the bias sums (products with a ones
+// operand) and dX = dZ1 W1^T are products on the matrix cores; each
+// workgroup accumulates its weight gradients over its tiles and writes one
+// partial; a second kernel sums the partials in a fixed order
+// (deterministic).
 //
 // MFMA 16x16x32 bf16 fragments (lane l, g = l / 16, c = l % 16):
 //   A (16 x 32): A[c][8g .. 8g+7]      B (32 x 16): B[8g .. 8g+7][c]
@@ -27,6 +29,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "fsp_internal.hpp"
@@ -228,207 +231,258 @@ struct BwdLds {
   bf16 Z1t[kH][kLdRows];     // dZ1 transposed
   bf16 DYt[kOut][kLdRows];   // dY transposed (bf16, padded outputs)
   float dy[kRows][kOut + 1]; // dY fp32 (padded outputs, odd row stride)
+  float w3[kOut][kH];        // W3 as exported (bf16 values), [output][hidden]
 };
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void backward_kernel(
+// Eight waves; wave w owns the band of hidden units [16w, 16w + 16) (column
+// tile w) in every product whose output columns are hidden units: h1, h2,
+// dZ2, dZ1, and the rows of dW2 / dW3, the columns of dW1.  Its weight
+// fragments (W1, W2 and W2^T restricted to the band) are loaded once and
+// stay in registers for the whole launch; only the products whose K runs
+// over all hidden units (h2, dZ1, and dW2's right operand) read other
+// waves' bands, after a barrier.  Two waves share each SIMD, so one issues
+// while the other waits on LDS or on its matrix products.  The next tile's
+// x and dY are loaded into registers while the current tile is computed.
+constexpr int kBwdWaves = 8, kBwdThreads = 64 * kBwdWaves;
+// NOUT: the network's outputs (1 .. kOut), a constant of the instantiation so
+// that the products over outputs are unrolled to their real length.
+template <int NOUT>
+__global__ __launch_bounds__(kBwdThreads) void backward_kernel(
     const bf16 *__restrict__ X, int64_t N, const float *__restrict__ P,
-    const bf16 *__restrict__ E, const float *__restrict__ dY, int nout,
+    const bf16 *__restrict__ E, const float *__restrict__ dY,
     float *__restrict__ dX, float *__restrict__ partial) {
+  constexpr int nout = NOUT;
   extern __shared__ __align__(16) char smem_raw[];
   BwdLds &S = *reinterpret_cast<BwdLds *>(smem_raw);
-  const int tid = threadIdx.x, w = tid >> 6;
-  // per-wave accumulators: dW2 tiles (wave w owns output rows i in [32w, 32w+32)),
-  // dW1 tiles (wave w owns columns i in [32w, 32w+32)), dW3 (wave w rows c in [32w,32w+32))
-  f32x4 gW2[2][8];
-  f32x4 gW1[2][2];
-  f32x4 gW3[2];
-  for (int a = 0; a < 2; ++a) {
-    for (int b = 0; b < 8; ++b) gW2[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int b = 0; b < 2; ++b) gW1[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    gW3[a] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
+  const int col = 16 * w + dcol();  // this lane's hidden unit in D fragments
+  bf16x8 fW2t[kH / 32], fW2n[kH / 32];
+  const bf16x8 fW1 = frag(E + eW1t, kIn, 16 * w, 0);
+  for (int kt = 0; kt < kH / 32; ++kt) {
+    fW2t[kt] = frag(E + eW2t, kH, 16 * w, kt * 32);
+    fW2n[kt] = frag(E + eW2n, kH, 16 * w, kt * 32);
   }
-  float gb1 = 0.f, gb2 = 0.f, gb3 = 0.f;  // thread t < kH: column t
+  const float b1v = P[oB1 + col], b2v = P[oB2 + col];
+  for (int e = tid; e < kOut * kH; e += kBwdThreads) S.w3[e / kH][e % kH] = (float)E[eW3t + e];
+  // padded outputs of dY stay zero
+  for (int e = tid; e < kRows * (kOut + 1); e += kBwdThreads) (&S.dy[0][0])[e] = 0.f;
+  for (int e = tid; e < kOut * kLdRows; e += kBwdThreads) (&S.DYt[0][0])[e] = (bf16)0.f;
+
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 gW2[kH / 16], gW1[kIn / 16], gW3 = zero, gB1 = zero, gB2 = zero;
+  for (int b = 0; b < kH / 16; ++b) gW2[b] = zero;
+  for (int a = 0; a < kIn / 16; ++a) gW1[a] = zero;
+  float gb3 = 0.f;  // threads < 256, (o, q): rows 4q .. 4q + 3 of output o, every tile
+  bf16x8 ones;
+  for (int j = 0; j < 8; ++j) ones[j] = (bf16)1.f;
+
+  // threads < 256 stage the tile: x, bf16 8*(t%4) .. +7 of row t/4; dY,
+  // floats 4t .. 4t+3 of the tile's [kRows][nout] block (rows past N read as
+  // zero)
+  const bool stager = tid < 256;
+  const bool x16 = (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+  bf16x8 xv;
+  float dyv[4];
+  auto load_tile = [&](int64_t base) {
+    const int r = tid >> 2, k0 = 8 * (tid & 3);
+    if (base + r < N) {
+      const bf16 *src = X + (base + r) * kIn + k0;
+      if (x16)
+        xv = *reinterpret_cast<const bf16x8 *>(src);
+      else
+        for (int j = 0; j < 8; ++j) xv[j] = src[j];
+    } else {
+      for (int j = 0; j < 8; ++j) xv[j] = (bf16)0.f;
+    }
+    const int64_t avail = (N - base < kRows ? N - base : kRows) * nout;
+    for (int q = 0; q < 4; ++q) {
+      const int e = 4 * tid + q;
+      dyv[q] = e < avail ? dY[base * nout + e] : 0.f;
+    }
+  };
 
   const int64_t tiles = (N + kRows - 1) / kRows;
+  if (stager && (int64_t)blockIdx.x < tiles) load_tile((int64_t)blockIdx.x * kRows);
   for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-    // opaque per tile: otherwise every weight fragment is loop-invariant and
-    // gets hoisted out of the tile loop into registers of its own
-    asm volatile("" : "+s"(E), "+s"(P));
     const int64_t base = t * kRows;
-    __syncthreads();
-    // load x (rows past N are zero) and dY
-    for (int e = tid; e < kRows * kIn; e += 256) {
-      const int r = e / kIn, k = e % kIn;
-      const bf16 v = base + r < N ? X[(base + r) * kIn + k] : (bf16)0.f;
-      S.Xr[r][k] = v;
-      S.Xt[k][r] = v;
-    }
-    for (int e = tid; e < kRows * kOut; e += 256) {
-      const int r = e / kOut, o = e % kOut;
-      const float v = (base + r < N && o < nout) ? dY[(base + r) * nout + o] : 0.f;
-      S.dy[r][o] = v;
-      S.DYt[o][r] = (bf16)v;
-    }
-    __syncthreads();
-    // h1 = relu(x W1 + b1): wave w rows [16w, 16w+16)
-    {
-      const bf16x8 xa = frag(&S.Xr[0][0], kLdIn, 16 * w, 0);
-      for (int nt = 0; nt < kH / 16; ++nt) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma(xa, frag(E + eW1t, kIn, nt * 16, 0), acc);
-        const int col = nt * 16 + dcol();
-        const float b = P[oB1 + col];
-        bf16x4 t;
-        for (int i = 0; i < 4; ++i) {
-          const bf16 v = (bf16)fmaxf(acc[i] + b, 0.f);
-          S.A1[16 * w + drow(i)][col] = v;
-          t[i] = v;
-        }
-        // rows 16w + 4g .. +3 of the transposed copy in one 8-byte store
-        *reinterpret_cast<bf16x4 *>(&S.H1t[col][16 * w + drow(0)]) = t;
-      }
-    }
-    __syncthreads();
-    // h2 = relu(h1 W2 + b2)
-    for (int nt = 0; nt < kH / 16; ++nt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      for (int kt = 0; kt < kH / 32; ++kt)
-        acc = mma(frag(&S.A1[0][0], kLdH, 16 * w, kt * 32),
-                  frag(E + eW2t, kH, nt * 16, kt * 32), acc);
-      const int col = nt * 16 + dcol();
-      const float b = P[oB2 + col];
-      bf16x4 t;
-      for (int i = 0; i < 4; ++i) t[i] = (bf16)fmaxf(acc[i] + b, 0.f);
-      *reinterpret_cast<bf16x4 *>(&S.H2t[col][16 * w + drow(0)]) = t;
-    }
-    __syncthreads();
-    // dW3[c][o] += sum_r h2[r][c] dY[r][o]: wave w, c-tiles 2w, 2w+1; K = 64 rows
-    for (int a = 0; a < 2; ++a)
-      for (int kt = 0; kt < kRows / 32; ++kt)
-        gW3[a] = mma(frag(&S.H2t[0][0], kLdRows, 32 * w + 16 * a, kt * 32),
-                     frag(&S.DYt[0][0], kLdRows, 0, kt * 32), gW3[a]);
-    // dZ2[r][c] = (sum_o dY[r][o] W3[c][o]) * (h2 > 0)   (VALU: K = nout)
-    // consecutive lanes take consecutive rows of one column c: the transposed
-    // accesses are then contiguous, and W3's row c is one broadcast
-    for (int e = tid; e < kRows * kH; e += 256) {
-      const int r = e % kRows, c = e / kRows;
-      float s = 0.f;
-      for (int o = 0; o < nout; ++o) s += S.dy[r][o] * (float)E[eW3t + o * kH + c];
-      const float g = (float)S.H2t[c][r] > 0.f ? s : 0.f;
-      const bf16 v = (bf16)g;
-      S.Z2r[r][c] = v;
-      S.Z2t[c][r] = v;
-    }
-    __syncthreads();
-    // dW2[i][o] += sum_r h1[r][i] dZ2[r][o]: wave w owns i-tiles 2w, 2w+1
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 8; ++b)
-        for (int kt = 0; kt < kRows / 32; ++kt)
-          gW2[a][b] = mma(frag(&S.H1t[0][0], kLdRows, 32 * w + 16 * a, kt * 32),
-                          frag(&S.Z2t[0][0], kLdRows, 16 * b, kt * 32), gW2[a][b]);
-    // dZ1 = (dZ2 W2^T) * (h1 > 0): wave w rows [16w, 16w+16)
-    {
-      f32x4 acc[kH / 16];
-      for (int nt = 0; nt < kH / 16; ++nt) {
-        acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int kt = 0; kt < kH / 32; ++kt)
-          acc[nt] = mma(frag(&S.Z2r[0][0], kLdH, 16 * w, kt * 32),
-                        frag(E + eW2n, kH, nt * 16, kt * 32), acc[nt]);
-      }
-      __syncthreads();  // every wave is done reading A1 as h1 (layer 2) long ago;
-                        // this barrier orders the masks below after all reads
-      for (int nt = 0; nt < kH / 16; ++nt) {
-        const int col = nt * 16 + dcol();
-        const bf16x4 h = *reinterpret_cast<const bf16x4 *>(&S.H1t[col][16 * w + drow(0)]);
-        bf16x4 t;
-        for (int i = 0; i < 4; ++i) {
-          const float g = (float)h[i] > 0.f ? acc[nt][i] : 0.f;
-          const bf16 v = (bf16)g;
-          S.A1[16 * w + drow(i)][col] = v;  // dZ1 row-major
-          t[i] = v;
-        }
-        *reinterpret_cast<bf16x4 *>(&S.Z1t[col][16 * w + drow(0)]) = t;
-      }
-    }
-    __syncthreads();
-    // dW1[k][i] += sum_r x[r][k] dZ1[r][i]: k-tiles 0,1; wave w owns i-tiles 2w, 2w+1
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b)
-        for (int kt = 0; kt < kRows / 32; ++kt)
-          gW1[a][b] = mma(frag(&S.Xt[0][0], kLdRows, 16 * a, kt * 32),
-                          frag(&S.Z1t[0][0], kLdRows, 32 * w + 16 * b, kt * 32), gW1[a][b]);
-    // dX = dZ1 W1^T: wave w rows [16w, 16w+16), 2 column tiles, K = 128
-    if (dX) {
-      for (int nt = 0; nt < kIn / 16; ++nt) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int kt = 0; kt < kH / 32; ++kt)
-          acc = mma(frag(&S.A1[0][0], kLdH, 16 * w, kt * 32),
-                    frag(E + eW1n, kH, nt * 16, kt * 32), acc);
-        const int col = nt * 16 + dcol();
-        for (int i = 0; i < 4; ++i) {
-          const int64_t r = base + 16 * w + drow(i);
-          if (r < N) dX[r * kIn + col] = acc[i];
+    __syncthreads();  // the previous tile's readers are done
+    if (stager) {
+      const int r = tid >> 2, k0 = 8 * (tid & 3);
+      *reinterpret_cast<bf16x8 *>(&S.Xr[r][k0]) = xv;
+      for (int j = 0; j < 8; ++j) S.Xt[k0 + j][r] = xv[j];
+      for (int q = 0; q < 4; ++q) {
+        const int e = 4 * tid + q;
+        if (e < kRows * nout) {
+          const int r2 = e / nout, o = e % nout;
+          S.dy[r2][o] = dyv[q];
+          S.DYt[o][r2] = (bf16)dyv[q];
         }
       }
     }
-    // bias gradients: column sums, from the row-major copies (consecutive
-    // threads read consecutive columns)
-    if (tid < kH) {
-      float s1 = 0.f, s2 = 0.f;
-      for (int r = 0; r < kRows; ++r) {
-        s1 += (float)S.A1[r][tid];
-        s2 += (float)S.Z2r[r][tid];
-      }
-      gb1 += s1;
-      gb2 += s2;
-    }
-    if (tid < kOut) {
+    __syncthreads();
+    if (stager) {
+      if (t + gridDim.x < tiles) load_tile(base + (int64_t)gridDim.x * kRows);
+      // bias of layer 3: column sums of dY (fp32); thread (o, q) = (tid % 16,
+      // tid / 16) adds rows 4q .. 4q + 3 of output o
+      const int o = tid & 15, q = tid >> 4;
       float s3 = 0.f;
-      for (int r = 0; r < kRows; ++r) s3 += S.dy[r][tid];
+      for (int rr = 0; rr < 4; ++rr) s3 += S.dy[4 * q + rr][o];
       gb3 += s3;
+    }
+
+    // h1 = relu(x W1 + b1) on the band, every row
+    {
+      f32x4 acc[kRows / 16];
+      for (int rt = 0; rt < kRows / 16; ++rt)
+        acc[rt] = mma(frag(&S.Xr[0][0], kLdIn, 16 * rt, 0), fW1, zero);
+      for (int rt = 0; rt < kRows / 16; ++rt) {
+        bf16x4 v4;
+        for (int i = 0; i < 4; ++i) {
+          const bf16 v = (bf16)fmaxf(acc[rt][i] + b1v, 0.f);
+          S.A1[16 * rt + drow(i)][col] = v;
+          v4[i] = v;
+        }
+        *reinterpret_cast<bf16x4 *>(&S.H1t[col][16 * rt + drow(0)]) = v4;
+      }
+    }
+    __syncthreads();  // h1 complete (h2 reads every band)
+    // h2 = relu(h1 W2 + b2) on the band, and from the same registers
+    // dZ2[r][c] = (sum_o dY[r][o] W3[c][o]) * (h2 > 0) (VALU, K = nout)
+    {
+      float w3v[nout];
+#pragma unroll
+      for (int o = 0; o < nout; ++o) w3v[o] = S.w3[o][col];
+      for (int rt = 0; rt < kRows / 16; ++rt) {
+        f32x4 acc = zero;
+        for (int kt = 0; kt < kH / 32; ++kt)
+          acc = mma(frag(&S.A1[0][0], kLdH, 16 * rt, kt * 32), fW2t[kt], acc);
+        bf16x4 h4, z4;
+        for (int i = 0; i < 4; ++i) {
+          const int r = 16 * rt + drow(i);
+          const bf16 h = (bf16)fmaxf(acc[i] + b2v, 0.f);
+          float sum = 0.f;
+#pragma unroll
+          for (int o = 0; o < nout; ++o) sum += S.dy[r][o] * w3v[o];
+          const bf16 z = (bf16)((float)h > 0.f ? sum : 0.f);
+          S.Z2r[r][col] = z;
+          h4[i] = h;
+          z4[i] = z;
+        }
+        *reinterpret_cast<bf16x4 *>(&S.H2t[col][16 * rt + drow(0)]) = h4;
+        *reinterpret_cast<bf16x4 *>(&S.Z2t[col][16 * rt + drow(0)]) = z4;
+      }
+    }
+    // dW3[c][o] += sum_r h2[r][c] dY[r][o] for the band's c, and the bias of
+    // layer 2 as 1^T dZ2 (every row of the result holds the column sums);
+    // K = rows
+    for (int kt = 0; kt < kRows / 32; ++kt) {
+      gW3 = mma(frag(&S.H2t[0][0], kLdRows, 16 * w, kt * 32),
+                frag(&S.DYt[0][0], kLdRows, 0, kt * 32), gW3);
+      gB2 = mma(ones, frag(&S.Z2t[0][0], kLdRows, 16 * w, kt * 32), gB2);
+    }
+    __syncthreads();  // dZ2 complete (dW2 and dZ1 read every band)
+    // dW2[i][o] += sum_r h1[r][i] dZ2[r][o]: rows i of the band, every o
+    for (int kt = 0; kt < kRows / 32; ++kt) {
+      const bf16x8 ha = frag(&S.H1t[0][0], kLdRows, 16 * w, kt * 32);
+      for (int b = 0; b < kH / 16; ++b)
+        gW2[b] = mma(ha, frag(&S.Z2t[0][0], kLdRows, 16 * b, kt * 32), gW2[b]);
+    }
+    // dZ1 = (dZ2 W2^T) * (h1 > 0) on the band; h1 row-major (A1) is no longer
+    // read by any wave (h2 is done everywhere), so dZ1 takes its place
+    for (int rt = 0; rt < kRows / 16; ++rt) {
+      f32x4 acc = zero;
+      for (int kt = 0; kt < kH / 32; ++kt)
+        acc = mma(frag(&S.Z2r[0][0], kLdH, 16 * rt, kt * 32), fW2n[kt], acc);
+      const bf16x4 h = *reinterpret_cast<const bf16x4 *>(&S.H1t[col][16 * rt + drow(0)]);
+      bf16x4 v4;
+      for (int i = 0; i < 4; ++i) {
+        const float g = (float)h[i] > 0.f ? acc[i] : 0.f;
+        const bf16 v = (bf16)g;
+        S.A1[16 * rt + drow(i)][col] = v;
+        v4[i] = v;
+      }
+      *reinterpret_cast<bf16x4 *>(&S.Z1t[col][16 * rt + drow(0)]) = v4;
+    }
+    // dW1[k][i] += sum_r x[r][k] dZ1[r][i]: columns i of the band; bias of
+    // layer 1 as 1^T dZ1
+    for (int kt = 0; kt < kRows / 32; ++kt) {
+      const bf16x8 zb = frag(&S.Z1t[0][0], kLdRows, 16 * w, kt * 32);
+      for (int a = 0; a < kIn / 16; ++a)
+        gW1[a] = mma(frag(&S.Xt[0][0], kLdRows, 16 * a, kt * 32), zb, gW1[a]);
+      gB1 = mma(ones, zb, gB1);
+    }
+    // dX = dZ1 W1^T (optional): wave w takes row tile w / 2, column tile
+    // w % 2; K = 128 over every band
+    if (dX) {
+      __syncthreads();
+      const int rt = w >> 1, nt = w & 1;
+      f32x4 acc = zero;
+      for (int kt = 0; kt < kH / 32; ++kt)
+        acc = mma(frag(&S.A1[0][0], kLdH, 16 * rt, kt * 32),
+                  frag(E + eW1n, kH, nt * 16, kt * 32), acc);
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = base + 16 * rt + drow(i);
+        if (r < N) dX[r * kIn + nt * 16 + dcol()] = acc[i];
+      }
     }
   }
   // write this workgroup's partial gradient
   float *G = partial + (size_t)blockIdx.x * kParams;
-  for (int a = 0; a < 2; ++a) {
-    for (int b = 0; b < 8; ++b) {
-      const int col = 16 * b + dcol();
-      for (int i = 0; i < 4; ++i) {
-        const int row = 32 * w + 16 * a + drow(i);
-        G[oW2 + row * kH + col] = gW2[a][b][i];
-      }
-    }
-    for (int b = 0; b < 2; ++b) {
-      const int col = 32 * w + 16 * b + dcol();
-      for (int i = 0; i < 4; ++i) {
-        const int row = 16 * a + drow(i);
-        G[oW1 + row * kH + col] = gW1[a][b][i];
-      }
-    }
-    {
-      const int col = dcol();
-      for (int i = 0; i < 4; ++i) {
-        const int row = 32 * w + 16 * a + drow(i);
-        G[oW3 + row * kOut + col] = gW3[a][i];
-      }
-    }
+  for (int b = 0; b < kH / 16; ++b)
+    for (int i = 0; i < 4; ++i) G[oW2 + (16 * w + drow(i)) * kH + 16 * b + dcol()] = gW2[b][i];
+  for (int a = 0; a < kIn / 16; ++a)
+    for (int i = 0; i < 4; ++i) G[oW1 + (16 * a + drow(i)) * kH + col] = gW1[a][i];
+  for (int i = 0; i < 4; ++i) G[oW3 + (16 * w + drow(i)) * kOut + dcol()] = gW3[i];
+  if (l < 16) {
+    G[oB1 + col] = gB1[0];
+    G[oB2 + col] = gB2[0];
   }
-  if (tid < kH) {
-    G[oB1 + tid] = gb1;
-    G[oB2 + tid] = gb2;
+  // the sixteen row groups of each output, added in a fixed order
+  __syncthreads();
+  if (stager) (&S.dy[0][0])[tid] = gb3;
+  __syncthreads();
+  if (tid < kOut) {
+    float s3 = 0.f;
+    for (int q = 0; q < 16; ++q) s3 += (&S.dy[0][0])[16 * q + tid];
+    G[oB3 + tid] = s3;
   }
-  if (tid < kOut) G[oB3 + tid] = gb3;
 }
 
-// grad[j] (+)= sum over partials, in workgroup order
-__global__ void reduce_kernel(const float *__restrict__ partial, int nparts,
-                              float *__restrict__ grad, int accumulate) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= kParams) return;
+using BwdFn = void (*)(const bf16 *, int64_t, const float *, const bf16 *, const float *,
+                      float *, float *);
+template <int... Ks>
+BwdFn backward_pick(int nout, std::integer_sequence<int, Ks...>) {
+  constexpr BwdFn table[] = {backward_kernel<Ks + 1>...};
+  return nout >= 1 && nout <= kOut ? table[nout - 1] : nullptr;
+}
+BwdFn backward_for(int nout) {
+  return backward_pick(nout, std::make_integer_sequence<int, kOut>());
+}
+
+// grad[j] (+)= sum over partials, in a fixed order
+// Workgroup of 256 threads per 64 parameters: wave q adds the partials of
+// workgroups [q * chunk, (q + 1) * chunk) in order, then the four wave sums
+// are added in the order q = 0 .. 3 (the same order on every run).
+__global__ __launch_bounds__(256) void reduce_kernel(const float *__restrict__ partial,
+                                                     int nparts, float *__restrict__ grad,
+                                                     int accumulate) {
+  __shared__ float red[4][64];
+  const int jl = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + jl;
+  const int chunk = (nparts + 3) / 4;
+  const int b0 = q * chunk, b1 = min(nparts, b0 + chunk);
   float s = 0.f;
-  for (int b = 0; b < nparts; ++b) s += partial[(size_t)b * kParams + j];
-  grad[j] = accumulate ? grad[j] + s : s;
+  if (j < kParams) {
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) s += partial[(size_t)b * kParams + j];
+  }
+  red[q][jl] = s;
+  __syncthreads();
+  if (q == 0 && j < kParams) {
+    const float t = ((red[0][jl] + red[1][jl]) + red[2][jl]) + red[3][jl];
+    grad[j] = accumulate ? grad[j] + t : t;
+  }
 }
 
 __global__ void adam_kernel(float *__restrict__ P, const float *__restrict__ G,
@@ -660,16 +714,17 @@ int fsp_model_backward(fsp_model *m, const void *x, int64_t n, const float *dy, 
   const int64_t tiles = (n + kRows - 1) / kRows;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, m->nparts));
   const size_t lds = sizeof(BwdLds);
-  static thread_local bool attr_set = false;
-  if (!attr_set) {
-    FSP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(backward_kernel),
+  const BwdFn fn = backward_for(m->outputs);
+  if (!fn) return FSP_EUNSUPPORTED;
+  static thread_local bool attr_set[kOut + 1] = {};
+  if (!attr_set[m->outputs]) {
+    FSP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_set = true;
+    attr_set[m->outputs] = true;
   }
-  hipLaunchKernelGGL(backward_kernel, dim3(grid), dim3(256), lds, s,
-                     reinterpret_cast<const bf16 *>(x), n, m->P, m->E, dy, m->outputs, dx,
-                     m->partial);
-  hipLaunchKernelGGL(reduce_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, m->partial,
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kBwdThreads), lds, s, reinterpret_cast<const bf16 *>(x), n,
+                     m->P, m->E, dy, dx, m->partial);
+  hipLaunchKernelGGL(reduce_kernel, dim3((kParams + 63) / 64), dim3(256), 0, s, m->partial,
                      grid, m->G, accumulate ? 1 : 0);
   FSP_HIP_TRY(hipGetLastError());
   return FSP_OK;
