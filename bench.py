@@ -566,7 +566,8 @@ def main() -> int:
             "traffic": measured_traffic(),
             "kernel": {"packed": f"bound_kernel_p16<{m}> (two nodes per lane, 16-bit)",
                        "register": f"bound_kernel<{m}> (one node per lane)",
-                       "masks": f"bound_kernel<{m}> (job masks)"}[inst.bound_path],
+                       "masks": f"bound_kernel<{m}> (job masks)",
+                       "bytes": f"bound_kernel<{m}> (flag bytes in LDS)"}[inst.bound_path],
             "kernel_ms": kernel_s * 1e3,
             "algorithmic_ops_per_launch": ops,
         },

@@ -80,8 +80,11 @@ int fsp_load_instance(const int32_t *p_host, int32_t n, int32_t m,
  * instance that would take the packed two-nodes-per-lane form (see
  * fsp_instance_path) on the one-node-per-lane 32-bit register form; the
  * bounds are identical, only the arithmetic differs (for comparing the two
- * forms on one pool). */
+ * forms on one pool).  FSP_LOAD_JOB_MASKS puts an instance of more than 64
+ * jobs on the job-mask walk instead of the LDS bytes walk (same bounds; the
+ * job-mask walk needs per-wave scratch, see fsp_bound_pool_noalloc). */
 #define FSP_LOAD_ONE_NODE_PER_LANE 1
+#define FSP_LOAD_JOB_MASKS 2
 
 /* fsp_load_instance with load flags (0 or FSP_LOAD_* or-ed together; any
  * other bit is FSP_EINVAL).  fsp_load_instance(p, n, m, out) is
@@ -104,13 +107,15 @@ int fsp_instance_info(const fsp_instance *inst, int32_t *n, int32_t *m,
  *   FSP_PATH_PACKED      n <= 32 and total work <= 32767: two nodes per lane
  *                        in packed 16-bit arithmetic (every value of the bound
  *                        then fits in 16 bits);
- *   FSP_PATH_MASKS       n > 64: one node per lane, per-wave job masks read
- *                        by scalar loads;
+ *   FSP_PATH_BYTES       n > 64: one node per lane, each lane's unscheduled
+ *                        flags as bytes in LDS;
+ *   FSP_PATH_MASKS       n > 64 when loaded with FSP_LOAD_JOB_MASKS: one node
+ *                        per lane, per-wave job masks read by scalar loads;
  *   FSP_PATH_REGISTER64  32 < n <= 64: one node per lane, the unscheduled set
  *                        in a 64-bit register pair.
  * A batch may take another allowed form per shape (fsp_batch_paths). */
 enum { FSP_PATH_REGISTER = 0, FSP_PATH_PACKED = 1, FSP_PATH_MASKS = 2,
-       FSP_PATH_REGISTER64 = 3 };
+       FSP_PATH_REGISTER64 = 3, FSP_PATH_BYTES = 4 };
 int fsp_instance_path(const fsp_instance *inst, int32_t *path);
 
 
@@ -148,11 +153,12 @@ int fsp_bound_pool(const fsp_nodes *nodes, int64_t count, int32_t *lb_out,
  * fsp_bound_pool_noalloc -- fsp_bound_pool for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc): same arguments, same bounds, but it never calls
- * hipMalloc, hipFree or any other allocating routine.  The job-mask walk of
- * instances with n > 64 takes its scratch from a fixed device array of
- * 32 MiB that the library holds on every device it runs on until the process
- * ends (found with hipGetSymbolAddress on the first call per device); up to
- * 64 jobs no scratch is needed and any count is served.  A pool of more than
+ * hipMalloc, hipFree or any other allocating routine.  The job-mask walk
+ * (instances with n > 64 loaded with FSP_LOAD_JOB_MASKS) takes its scratch
+ * from a fixed device array of 32 MiB that the library holds on every device
+ * it runs on until the process ends (found with hipGetSymbolAddress on the
+ * first call per device); every other walk needs no scratch and any count is
+ * served.  On the job-mask walk, a pool of more than
  * fsp_noalloc_max_count(n) nodes returns FSP_ESCRATCH before any device work
  * is queued.  All calls on one device share the array: calls that overlap on
  * one device (different streams, or host threads, without ordering between
@@ -163,8 +169,9 @@ int fsp_bound_pool(const fsp_nodes *nodes, int64_t count, int32_t *lb_out,
 int fsp_bound_pool_noalloc(const fsp_nodes *nodes, int64_t count, int32_t *lb_out,
                            void *stream);
 
-/* Largest pool fsp_bound_pool_noalloc serves for n jobs (INT64_MAX when no
- * scratch is needed, i.e. n <= 64; 0 for n outside 1..255). */
+/* Largest pool fsp_bound_pool_noalloc serves for an instance of n jobs on
+ * the job-mask walk (INT64_MAX for n <= 64, where that walk is never taken;
+ * 0 for n outside 1..255).  Instances on the other walks take any count. */
 int64_t fsp_noalloc_max_count(int32_t n);
 
 /*

@@ -479,8 +479,8 @@ int BnbState::init(const fsp_instance *inst_, int64_t max_pool, int rule_) {
       hipMalloc(&bcount, (size_t)n * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&pool, (size_t)cap * stride) != hipSuccess ||
       hipMalloc(&pool_lb, (size_t)cap * sizeof(int32_t)) != hipSuccess ||
-      (bound_scratch_bytes(n, cap) > 0 &&
-       hipMalloc(&slots, bound_scratch_bytes(n, cap)) != hipSuccess) ||
+      (walk_scratch_bytes(inst, cap) > 0 &&
+       hipMalloc(&slots, walk_scratch_bytes(inst, cap)) != hipSuccess) ||
       hipMalloc(&desc, sizeof(BnbDesc)) != hipSuccess ||
       hipMalloc(&best_perm, 256) != hipSuccess ||
       hipMalloc(&target_dev, sizeof(int64_t)) != hipSuccess ||

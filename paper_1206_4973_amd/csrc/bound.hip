@@ -77,9 +77,12 @@ struct BoundParams {
   Prefilter pf;
 };
 
+// The bytes walk's LDS (flag rows) leaves room for two workgroups per compute
+// unit, so its kernels may use twice the registers of the other forms.
 template <int M, int FORM, bool CHUNKED>
-__global__ __launch_bounds__(kBlock, 4) void bound_kernel(const BoundParams a) {
-  constexpr bool WIDE = FORM == kFormMasks;
+__global__ __launch_bounds__(kBlock, FORM == kFormBytes ? 2 : 4) void bound_kernel(
+    const BoundParams a) {
+  constexpr bool WIDE = FORM == kFormMasks || FORM == kFormBytes;
   extern __shared__ __align__(16) char smem[];
   int64_t count = a.count, ntiles = a.ntiles;
   if (a.count_dev) {
@@ -89,8 +92,8 @@ __global__ __launch_bounds__(kBlock, 4) void bound_kernel(const BoundParams a) {
   }
   // a workgroup without a tile leaves before staging the tables
   if ((int64_t)blockIdx.x >= ntiles) return;
-  const LdsView L = carve<WIDE>(smem, a.I);
-  stage_instance<WIDE>(a.I, L);
+  const LdsView L = carve<WIDE, FORM == kFormBytes>(smem, a.I);
+  stage_instance<WIDE, FORM == kFormBytes>(a.I, L);
   __syncthreads();
   const size_t tile_bytes = (size_t)(kBlock / 64) * (size_t)a.I.slot_bytes;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
@@ -133,6 +136,8 @@ BoundFn pick(int form, bool chunked) {
   // table of one chunk)
   if (form == kFormReg64) return bound_kernel<M, kFormReg64, true>;
   if (form == kFormReg32) return bound_kernel<M, kFormReg32, false>;
+  if (form == kFormBytes)
+    return chunked ? bound_kernel<M, kFormBytes, true> : bound_kernel<M, kFormBytes, false>;
   return chunked ? bound_kernel<M, kFormMasks, true> : bound_kernel<M, kFormMasks, false>;
 }
 
@@ -166,6 +171,15 @@ BoundFn kernel_for(int m, int form, bool chunked) {
 // on a compute unit next to the job words.
 constexpr size_t kTableBudgetNarrow = 64 * 1024;
 constexpr size_t kTableBudgetWide = 32 * 1024;
+// The bytes walk: the table chunk (8 bytes of record and 4 of flag offset
+// per position) gets what is left of 80 KB (two workgroups per compute
+// unit) next to the job words and the flag rows.
+size_t table_budget_bytes(int n) {
+  const size_t fixed = (size_t)((n + 31) / 32) * kBlock * 4 + alpha_bytes(n) + 32;
+  const size_t per_wg = 80 * 1024;
+  const size_t rest = fixed + 16 * 1024 <= per_wg ? per_wg - fixed : 16 * 1024;
+  return rest * sizeof(Rec) / (sizeof(Rec) + sizeof(uint32_t));
+}
 
 }  // namespace
 
@@ -244,7 +258,7 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
                  const int32_t *count_dev, void *scratch, const Prefilter &pf) {
   if (count == 0) return FSP_OK;
   const bool wide = inst->wide != 0;
-  const size_t need = bound_scratch_bytes(inst->n, count);
+  const size_t need = walk_scratch_bytes(inst, count);
   if (!scratch && need > 0) {
     const int rc = stream_scratch(stream, need, &scratch);
     if (rc != FSP_OK) return rc;
@@ -264,9 +278,16 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
                   ? 1
                   : 0;
   a.lb = lb_out;
-  // n > 32: the 64-bit register form up to 64 jobs, job masks above
-  const int form = !wide ? kFormReg32 : (uses_job_masks(inst->n) ? kFormMasks : kFormReg64);
-  a.I = inst_view(inst, wide ? kTableBudgetWide : kTableBudgetNarrow);
+  // n > 32: the 64-bit register form up to 64 jobs, the bytes walk above
+  // (or the job masks, by load flag)
+  const int form = !wide                        ? kFormReg32
+                   : !uses_job_masks(inst->n)   ? kFormReg64
+                   : takes_mask_walk(inst)      ? kFormMasks
+                                                : kFormBytes;
+  a.I = inst_view(inst, form == kFormBytes ? table_budget_bytes(inst->n)
+                        : wide             ? kTableBudgetWide
+                                           : kTableBudgetNarrow);
+  if (form != kFormMasks) a.I.slot_bytes = 0;
   BoundFn fn;
   if (p16) {
     fn = inst->m >= 2 && inst->m <= kMaxMachines
@@ -277,7 +298,9 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
   }
   if (!fn) return FSP_EUNSUPPORTED;
   const size_t lds = p16 ? lds_bytes_p16(a.I.n, a.I.mp, a.I.npad, a.I.P)
-                        : lds_bytes(a.I.n, a.I.mp, a.I.npad, a.I.ppc, form == kFormMasks);
+                        : lds_bytes(a.I.n, a.I.mp, a.I.npad, a.I.ppc,
+                                    form == kFormMasks || form == kFormBytes,
+                                    form == kFormBytes);
 
   // device attributes and per-kernel occupancy are queried once per
   // (device, kernel, LDS size) and cached for this thread, in a fixed table
@@ -375,7 +398,7 @@ extern "C" int fsp_bound_pool_noalloc(const fsp_nodes *nodes, int64_t count,
   if (nodes->stride < nodes->inst->n + 1) return FSP_EINVAL;
   const fsp_instance *inst = nodes->inst;
   void *ptr = nullptr;
-  if (uses_job_masks(inst->n)) {
+  if (takes_mask_walk(inst)) {
     if (count > fsp_noalloc_max_count(inst->n) ||
         bound_scratch_bytes(inst->n, count) > kNoAllocScratchBytes)
       return FSP_ESCRATCH;

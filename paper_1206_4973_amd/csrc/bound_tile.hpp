@@ -26,11 +26,14 @@ struct InstView {
 
 // LDS of one workgroup for one instance: the table chunk, then (n <= 32)
 // the p matrix for the prefix recurrence, or (n > 32) the unscheduled-job
-// mask of every lane as ceil(n/32) words laid out [word][lane].
+// mask of every lane as ceil(n/32) words laid out [word][lane], and in the
+// bytes form the same flags as bytes, [wave][job 0 .. n][lane].
 struct LdsView {
   char *s_rec;
   int32_t *s_p;       // narrow only
   uint32_t *s_words;  // wide only
+  uint8_t *s_alpha;   // bytes form only
+  uint32_t *s_aoff;   // bytes form only: flag offsets of the chunk's positions
 };
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -40,6 +43,7 @@ enum Form : int {
   kFormReg32 = 0,  // n <= 32: unscheduled set in one register
   kFormMasks = 1,  // n > 32: per-wave job masks read by scalar loads
   kFormReg64 = 2,  // 32 < n <= 64: unscheduled set in a 64-bit register pair
+  kFormBytes = 3,  // n > 32: unscheduled flags of the lanes as bytes in LDS
 };
 
 // Read-only views through the constant address space: loads from these with
@@ -59,11 +63,20 @@ __host__ __device__ constexpr int pair_index(int k, int l) {
 // up to 16 bytes, so that a row is read with 16-byte loads.
 __host__ __device__ constexpr int p16_row_words(int mp) { return (mp / 2 + 3) & ~3; }
 
+// Bytes of the bytes form's flag rows: one byte per lane for jobs 0 .. n,
+// and of its staged flag offsets: one word per position of a chunk and two
+// spare groups of four (the walk requests up to two groups ahead).
+__host__ __device__ inline size_t alpha_bytes(int n) { return (size_t)kBlock * (n + 1); }
+__host__ __device__ inline size_t aoff_bytes(int ppc, int npad) {
+  return ((size_t)ppc * npad + 8) * sizeof(uint32_t);
+}
+
 __host__ __device__ inline size_t lds_bytes(int n, int mp, int npad, int ppc,
-                                            bool wide) {
+                                            bool wide, bool bytes = false) {
   size_t b = (size_t)ppc * npad * sizeof(Rec);
   if (wide)
-    b += (size_t)((n + 31) / 32) * kBlock * 4;
+    b += (size_t)((n + 31) / 32) * kBlock * 4 +
+         (bytes ? alpha_bytes(n) + aoff_bytes(ppc, npad) : 0);
   else {  // 32-bit rows of p, or the packed rows plus a row of zeros
     const int rows32 = n * mp, rows16 = (n + 1) * p16_row_words(mp);
     b += (size_t)(rows32 > rows16 ? rows32 : rows16) * 4;
@@ -71,13 +84,17 @@ __host__ __device__ inline size_t lds_bytes(int n, int mp, int npad, int ppc,
   return (b + 15) & ~size_t(15);
 }
 
-template <bool WIDE>
+template <bool WIDE, bool BYTES = false>
 __device__ __forceinline__ LdsView carve(char *smem, const InstView I) {
   LdsView L;
   L.s_rec = smem;
   char *after = smem + (size_t)I.ppc * I.npad * sizeof(Rec);
+  L.s_aoff = BYTES ? reinterpret_cast<uint32_t *>(after) : nullptr;
+  if (BYTES) after += aoff_bytes(I.ppc, I.npad);
   L.s_p = WIDE ? nullptr : reinterpret_cast<int32_t *>(after);
   L.s_words = WIDE ? reinterpret_cast<uint32_t *>(after) : nullptr;
+  L.s_alpha = BYTES ? reinterpret_cast<uint8_t *>(after + (size_t)((I.n + 31) / 32) * kBlock * 4)
+                    : nullptr;
   return L;
 }
 
@@ -91,14 +108,29 @@ __device__ __forceinline__ void stage_chunk(const InstView I, char *s_rec,
   for (int i = threadIdx.x; i < total; i += kBlock) dst[i] = src[i];
 }
 
+// The bytes form also stages the chunk's flag offsets: 8 * (the mask offset
+// 8 * job) = job * 64, the byte offset of the job's row of flags; the two
+// spare groups name row n (all zero).
+__device__ __forceinline__ void stage_aoff(const InstView I, uint32_t *s_aoff, int chunk) {
+  const int lo = chunk * I.ppc;
+  const int hi = min(I.P, lo + I.ppc);
+  const int total = (hi - lo) * I.npad;
+  const uint32_t *src = I.joff + (size_t)lo * I.npad;
+  for (int i = threadIdx.x; i < total + 8; i += kBlock)
+    s_aoff[i] = i < total ? src[i] * 8u : (uint32_t)I.n * 64u;
+}
+
 // Stage what stays in LDS for the whole instance: p, and the whole pair table
 // when it fits.  The caller synchronises the workgroup afterwards.
-template <bool WIDE>
+template <bool WIDE, bool BYTES = false>
 __device__ __forceinline__ void stage_instance(const InstView I,
                                                const LdsView &L) {
   if (!WIDE)
     for (int i = threadIdx.x; i < I.n * I.mp; i += kBlock) L.s_p[i] = I.p[i];
-  if (I.nchunks == 1) stage_chunk(I, L.s_rec, 0);
+  if (I.nchunks == 1) {
+    stage_chunk(I, L.s_rec, 0);
+    if (BYTES) stage_aoff(I, L.s_aoff, 0);
+  }
 }
 
 // Write the wave's job masks: entry j of the slot is the 64-bit set of lanes
@@ -283,10 +315,199 @@ __device__ __forceinline__ void walk2(const char *ra_raw, const char *rb_raw,
   }
 }
 
+// LDS byte offset of a pointer into the workgroup's LDS.
+__device__ __forceinline__ uint32_t lds_offset(const char *p) {
+  return (uint32_t)(uintptr_t)((__attribute__((address_space(3))) const char *)p);
+}
+
+// ---- n > 32, bytes form: each lane keeps its node's unscheduled flags as
+//      bytes in LDS, laid out [job][lane] in its wave's rows (row n is all
+//      zero and is the one the padding positions name).  A position reads
+//      the lane's byte of its job at job * 64 + lane (the row offsets are
+//      staged in LDS next to the records): 64 consecutive bytes per wave, no
+//      bank conflict.  Then the register form's step: 4 vector instructions
+//      per position (address, v_mad_i32_i24, v_mul_u32_u24, v_max_i32) and
+//      one LDS byte load.  Every load of the walk is an LDS load, so they
+//      complete in order and the walk can run ahead: the records and flags
+//      of the next group of four positions and the offsets of the group
+//      after are requested before the current group is computed. ----
+__device__ __forceinline__ int step_f(uint32_t al, int x, int y, int Z) {
+  const int up = __mul24((int)al, x) + Z;
+  const int lo = (int)__umul24(al, (uint32_t)y);
+  return max(up, lo);
+}
+
+// One pair: npad records at rp_raw and npad flag offsets at op_raw (LDS);
+// the requests past the pair's end stay inside the staged chunk (the next
+// pair's entries, the spare offset groups, the offsets after the records).
+// The index of the next group passes through an empty asm statement every
+// iteration: otherwise the compiler proves that the next group's load is
+// the same as the current group's load one iteration later, and moves it
+// there, next to its use, which undoes the running ahead.
+__device__ __forceinline__ int walk1_b(const char *rp_raw, const char *op_raw,
+                                       const uint8_t *al, int npad, int Z) {
+  const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);
+  const u32x4 *op = reinterpret_cast<const u32x4 *>(op_raw);
+  const u32x4 q = op[0];
+  u32x4 p1 = op[1];
+  int4 r0 = rp[0], r1 = rp[1];
+  uint32_t f0 = al[q.x], f1 = al[q.y], f2 = al[q.z], f3 = al[q.w];
+  for (int i = 0; i < npad / 4; ++i) {
+    int g = i + 1;
+    asm volatile("" : "+s"(g));
+    const int4 *rn = rp + 2 * g;
+    const u32x4 *on = op + g + 1;
+    const int4 n0 = rn[0], n1 = rn[1];
+    const uint32_t g0 = al[p1.x], g1 = al[p1.y], g2 = al[p1.z], g3 = al[p1.w];
+    const u32x4 p2 = on[0];
+    Z = step_f(f0, r0.x, r0.y, Z);
+    Z = step_f(f1, r0.z, r0.w, Z);
+    Z = step_f(f2, r1.x, r1.y, Z);
+    Z = step_f(f3, r1.z, r1.w, Z);
+    r0 = n0;
+    r1 = n1;
+    f0 = g0;
+    f1 = g1;
+    f2 = g2;
+    f3 = g3;
+    p1 = p2;
+  }
+  return Z;
+}
+
+// Two pairs walked together: two independent dependency chains per lane,
+// in one asm loop over groups of four positions.  Two register sets take
+// turns (X = v80..v111, Y = v112..v143; in each, records of pair A at +0 and
+// of pair B at +8, flags of A at +16 and of B at +20, and the flag offsets of
+// the other set's group, A at +24 and B at +28).  A half waits for its set's
+// loads, forms the other set's flag addresses from the offsets it holds,
+// requests the other set's flags, records and the offsets after them, then
+// computes its own group: the requests overlap 24 steps of arithmetic.  All
+// loads are LDS loads (they complete in order), and all are waited for
+// before the statement ends.  The requests past a pair's end (one group of
+// records, two of offsets) stay inside the staged chunk.
+#define FSP_B_STEP2(FA, XA, YA, FB, XB, YB)                \
+  "v_mad_i32_i24 %[tA], " FA ", " XA ", %[zA]\n\t"         \
+  "v_mul_u32_u24 %[uA], " FA ", " YA "\n\t"                \
+  "v_mad_i32_i24 %[tB], " FB ", " XB ", %[zB]\n\t"         \
+  "v_mul_u32_u24 %[uB], " FB ", " YB "\n\t"                \
+  "v_max_i32 %[zA], %[tA], %[uA]\n\t"                      \
+  "v_max_i32 %[zB], %[tB], %[uB]\n\t"
+
+__device__ __forceinline__ void walk2_b(const char *ra_raw, const char *rb_raw,
+                                        const char *oa_raw, const char *ob_raw,
+                                        const uint8_t *al, int npad, int &ZA, int &ZB) {
+  uint32_t ra = lds_offset(ra_raw), rb = lds_offset(rb_raw);
+  uint32_t oa = lds_offset(oa_raw), ob = lds_offset(ob_raw);
+  const uint32_t lane = lds_offset(reinterpret_cast<const char *>(al));
+  int tA, uA, tB, uB;
+  uint32_t cnt = (uint32_t)(npad / 4);  // groups
+  asm volatile(
+      "ds_read_b128 v[104:107], %[oa] offset:0\n\t"
+      "ds_read_b128 v[108:111], %[ob] offset:0\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "v_add_u32 v96, v104, %[lane]\n\t"
+      "v_add_u32 v97, v105, %[lane]\n\t"
+      "v_add_u32 v98, v106, %[lane]\n\t"
+      "v_add_u32 v99, v107, %[lane]\n\t"
+      "v_add_u32 v100, v108, %[lane]\n\t"
+      "v_add_u32 v101, v109, %[lane]\n\t"
+      "v_add_u32 v102, v110, %[lane]\n\t"
+      "v_add_u32 v103, v111, %[lane]\n\t"
+      "ds_read_u8 v96, v96\n\t"
+      "ds_read_u8 v97, v97\n\t"
+      "ds_read_u8 v98, v98\n\t"
+      "ds_read_u8 v99, v99\n\t"
+      "ds_read_u8 v100, v100\n\t"
+      "ds_read_u8 v101, v101\n\t"
+      "ds_read_u8 v102, v102\n\t"
+      "ds_read_u8 v103, v103\n\t"
+      "ds_read_b128 v[80:83], %[ra] offset:0\n\t"
+      "ds_read_b128 v[84:87], %[ra] offset:16\n\t"
+      "ds_read_b128 v[88:91], %[rb] offset:0\n\t"
+      "ds_read_b128 v[92:95], %[rb] offset:16\n\t"
+      "ds_read_b128 v[104:107], %[oa] offset:16\n\t"
+      "ds_read_b128 v[108:111], %[ob] offset:16\n"
+      "1:\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "v_add_u32 v128, v104, %[lane]\n\t"
+      "v_add_u32 v129, v105, %[lane]\n\t"
+      "v_add_u32 v130, v106, %[lane]\n\t"
+      "v_add_u32 v131, v107, %[lane]\n\t"
+      "v_add_u32 v132, v108, %[lane]\n\t"
+      "v_add_u32 v133, v109, %[lane]\n\t"
+      "v_add_u32 v134, v110, %[lane]\n\t"
+      "v_add_u32 v135, v111, %[lane]\n\t"
+      "ds_read_u8 v128, v128\n\t"
+      "ds_read_u8 v129, v129\n\t"
+      "ds_read_u8 v130, v130\n\t"
+      "ds_read_u8 v131, v131\n\t"
+      "ds_read_u8 v132, v132\n\t"
+      "ds_read_u8 v133, v133\n\t"
+      "ds_read_u8 v134, v134\n\t"
+      "ds_read_u8 v135, v135\n\t"
+      "ds_read_b128 v[112:115], %[ra] offset:32\n\t"
+      "ds_read_b128 v[116:119], %[ra] offset:48\n\t"
+      "ds_read_b128 v[120:123], %[rb] offset:32\n\t"
+      "ds_read_b128 v[124:127], %[rb] offset:48\n\t"
+      "ds_read_b128 v[136:139], %[oa] offset:32\n\t"
+      "ds_read_b128 v[140:143], %[ob] offset:32\n\t"
+      FSP_B_STEP2("v96", "v80", "v81", "v100", "v88", "v89")
+      FSP_B_STEP2("v97", "v82", "v83", "v101", "v90", "v91")
+      FSP_B_STEP2("v98", "v84", "v85", "v102", "v92", "v93")
+      FSP_B_STEP2("v99", "v86", "v87", "v103", "v94", "v95")
+      "s_sub_u32 %[cnt], %[cnt], 1\n\t"
+      "s_cmp_eq_u32 %[cnt], 0\n\t"
+      "s_cbranch_scc1 2f\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      "v_add_u32 v96, v136, %[lane]\n\t"
+      "v_add_u32 v97, v137, %[lane]\n\t"
+      "v_add_u32 v98, v138, %[lane]\n\t"
+      "v_add_u32 v99, v139, %[lane]\n\t"
+      "v_add_u32 v100, v140, %[lane]\n\t"
+      "v_add_u32 v101, v141, %[lane]\n\t"
+      "v_add_u32 v102, v142, %[lane]\n\t"
+      "v_add_u32 v103, v143, %[lane]\n\t"
+      "ds_read_u8 v96, v96\n\t"
+      "ds_read_u8 v97, v97\n\t"
+      "ds_read_u8 v98, v98\n\t"
+      "ds_read_u8 v99, v99\n\t"
+      "ds_read_u8 v100, v100\n\t"
+      "ds_read_u8 v101, v101\n\t"
+      "ds_read_u8 v102, v102\n\t"
+      "ds_read_u8 v103, v103\n\t"
+      "ds_read_b128 v[80:83], %[ra] offset:64\n\t"
+      "ds_read_b128 v[84:87], %[ra] offset:80\n\t"
+      "ds_read_b128 v[88:91], %[rb] offset:64\n\t"
+      "ds_read_b128 v[92:95], %[rb] offset:80\n\t"
+      "ds_read_b128 v[104:107], %[oa] offset:48\n\t"
+      "ds_read_b128 v[108:111], %[ob] offset:48\n\t"
+      FSP_B_STEP2("v128", "v112", "v113", "v132", "v120", "v121")
+      FSP_B_STEP2("v129", "v114", "v115", "v133", "v122", "v123")
+      FSP_B_STEP2("v130", "v116", "v117", "v134", "v124", "v125")
+      FSP_B_STEP2("v131", "v118", "v119", "v135", "v126", "v127")
+      "v_add_u32 %[ra], 64, %[ra]\n\t"
+      "v_add_u32 %[rb], 64, %[rb]\n\t"
+      "v_add_u32 %[oa], 32, %[oa]\n\t"
+      "v_add_u32 %[ob], 32, %[ob]\n\t"
+      "s_sub_u32 %[cnt], %[cnt], 1\n\t"
+      "s_cmp_eq_u32 %[cnt], 0\n\t"
+      "s_cbranch_scc0 1b\n"
+      "2:\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : [zA] "+v"(ZA), [zB] "+v"(ZB), [tA] "=&v"(tA), [uA] "=&v"(uA), [tB] "=&v"(tB),
+        [uB] "=&v"(uB), [ra] "+v"(ra), [rb] "+v"(rb), [oa] "+v"(oa), [ob] "+v"(ob),
+        [cnt] "+s"(cnt)
+      : [lane] "v"(lane)
+      : "v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101", "v102", "v103", "v104", "v105", "v106", "v107", "v108", "v109", "v110", "v111", "v112", "v113", "v114", "v115", "v116", "v117", "v118", "v119", "v120", "v121", "v122", "v123", "v124", "v125", "v126", "v127", "v128", "v129", "v130", "v131", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "scc", "memory");
+}
+
 template <int FORM>
 __device__ __forceinline__ int walk1_any(const char *rp, kchar *jp, kchar *ms,
-                                         int npad, uint64_t U, int Z) {
+                                         const uint8_t *al, const char *so, int npad,
+                                         uint64_t U, int Z) {
   if constexpr (FORM == kFormMasks) return walk1(rp, jp, ms, npad, Z);
+  else if constexpr (FORM == kFormBytes) return walk1_b(rp, so, al, npad, Z);
   else if constexpr (FORM == kFormReg64) return walk1_u64(rp, npad, U, Z);
   else return walk1_u(rp, npad, (uint32_t)U, Z);
 }
@@ -299,7 +520,8 @@ __device__ __forceinline__ int walk1_any(const char *rp, kchar *jp, kchar *ms,
 template <int M, int FORM>
 __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
                                           int hi, int npad, uint64_t U,
-                                          kchar *ms, const int (&R256)[M],
+                                          kchar *ms, const uint8_t *al,
+                                          const char *so, const int (&R256)[M],
                                           const int (&T256)[M],
                                           const int (&Q256)[M], int LB256) {
   int pb = npad * (int)sizeof(Rec);
@@ -324,6 +546,8 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
           if constexpr (FORM == kFormMasks)
             walk2(s_rec + off, s_rec + offb, jt + joff, jt + joffb, ms, npad,
                   ZA, ZB);
+          else if constexpr (FORM == kFormBytes)
+            walk2_b(s_rec + off, s_rec + offb, so + joff, so + joffb, al, npad, ZA, ZB);
           else if constexpr (FORM == kFormReg64)
             walk2_u64(s_rec + off, s_rec + offb, npad, U, ZA, ZB);
           else
@@ -335,13 +559,13 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
           asm volatile("" : "+v"(LB256));
         } else {
           if (ina) {
-            int Z = walk1_any<FORM>(s_rec + off, jt + joff, ms, npad, U,
+            int Z = walk1_any<FORM>(s_rec + off, jt + joff, ms, al, so + joff, npad, U,
                                     R256[l] - R256[k]);
             LB256 = max(LB256, T256[k] + Q256[l] + Z);
             asm volatile("" : "+v"(LB256));
           }
           if (inb) {
-            int Z = walk1_any<FORM>(s_rec + offb, jt + joffb, ms, npad, U,
+            int Z = walk1_any<FORM>(s_rec + offb, jt + joffb, ms, al, so + joffb, npad, U,
                                     R256[l + 1] - R256[k]);
             LB256 = max(LB256, T256[k] + Q256[l + 1] + Z);
             asm volatile("" : "+v"(LB256));
@@ -351,7 +575,7 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
         joff += 2 * jb;
       } else {
         if (pa >= lo && pa < hi) {
-          int Z = walk1_any<FORM>(s_rec + off, jt + joff, ms, npad, U,
+          int Z = walk1_any<FORM>(s_rec + off, jt + joff, ms, al, so + joff, npad, U,
                                   R256[l] - R256[k]);
           LB256 = max(LB256, T256[k] + Q256[l] + Z);
           asm volatile("" : "+v"(LB256));
@@ -508,7 +732,7 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
                                             int64_t count, int32_t *lb_out,
                                             char *tile_slots,
                                             const Prefilter pf = Prefilter()) {
-  constexpr bool WIDE = FORM == kFormMasks;
+  constexpr bool WIDE = FORM == kFormMasks || FORM == kFormBytes;
   const int tid = threadIdx.x;
   const int n = I.n, npad = I.npad;
   char *s_rec = L.s_rec;
@@ -554,7 +778,21 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   //         cache starts every dispatch invalidated), so no scalar cache line
   //         can hold an older copy of it. ----
   kchar *ms = nullptr, *jt = nullptr;
-  if constexpr (WIDE) if (!skip) {
+  const uint8_t *al = nullptr;
+  if constexpr (FORM == kFormBytes) {
+    // the lane's flags as bytes: rows 0 .. n-1 from the words, row n zero;
+    // only this lane reads its bytes, so no barrier is needed
+    uint8_t *mine = L.s_alpha + (size_t)(tid >> 6) * (size_t)(n + 1) * 64 + (tid & 63);
+    for (int w = 0; w * 32 < n; ++w) {
+      const uint32_t word = words_lane[w * kBlock];
+      const int jend = min(n, w * 32 + 32);
+      for (int j = w * 32; j < jend; ++j) mine[j * 64] = (uint8_t)((word >> (j & 31)) & 1u);
+    }
+    mine[n * 64] = 0;
+    al = mine;
+  }
+  const char *so = reinterpret_cast<const char *>(L.s_aoff);
+  if constexpr (FORM == kFormMasks) if (!skip) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     uint64_t *slot = reinterpret_cast<uint64_t *>(
         tile_slots + (size_t)wave * (size_t)I.slot_bytes);
@@ -573,12 +811,13 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
     for (int k = 0; k < M; ++k)
       asm volatile("" : "+v"(R256[k]), "+v"(T256[k]), "+v"(Q256[k]));
     if (!skip)
-      LB256 = pair_sweep<M, FORM>(s_rec, jt, 0, M * (M - 1) / 2, npad, U, ms,
+      LB256 = pair_sweep<M, FORM>(s_rec, jt, 0, M * (M - 1) / 2, npad, U, ms, al, so,
                                   R256, T256, Q256, LB256);
   } else {
     for (int chunk = 0; chunk < I.nchunks; ++chunk) {
       __syncthreads();
       stage_chunk(I, s_rec, chunk);
+      if constexpr (FORM == kFormBytes) stage_aoff(I, L.s_aoff, chunk);
       __syncthreads();
       // keep the per-node values from being re-derived per pair outside
       // the chunk loop (which would cost a register per pair)
@@ -590,7 +829,7 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
       // the barriers above are kept when the wave skips its walks
       if (!skip)
         LB256 = pair_sweep<M, FORM>(s_rec, jt + (size_t)lo * npad * 4, lo, hi,
-                                    npad, U, ms, R256, T256, Q256, LB256);
+                                    npad, U, ms, al, so, R256, T256, Q256, LB256);
     }
   }
 
@@ -640,10 +879,6 @@ typedef unsigned int u32x32 __attribute__((ext_vector_type(32)));
   "s_set_gpr_idx_off\n\t"                                             \
   "v_pk_max_i16 %[zA], %[tA], %[uA]\n\t"
 
-// LDS byte offset of a pointer into the workgroup's LDS.
-__device__ __forceinline__ uint32_t lds_offset(const char *p) {
-  return (uint32_t)(uintptr_t)((__attribute__((address_space(3))) const char *)p);
-}
 
 // Two pairs walked together over `groups` groups of four positions.  Their
 // tables are interleaved four positions at a time (four words of the first

@@ -70,8 +70,12 @@ struct fsp_instance {
   uint32_t *d_xy16 = nullptr;
   uint32_t *d_job16 = nullptr;
   uint32_t *d_joff = nullptr;  // [P][npad] 8 * job id per table position
+  // n > 64: 1 when loaded with FSP_LOAD_JOB_MASKS (the job-mask walk, with
+  // its per-wave scratch), 0 for the LDS bytes walk
+  int masks_walk = 0;
   std::vector<int32_t> p_host;  // [n][m], for host-side set-up work (NEH)
 };
+
 
 // Status helpers
 #define FSP_HIP_TRY(expr)                          \
@@ -89,6 +93,14 @@ inline size_t bound_scratch_bytes(int n, int64_t count) {
   if (!uses_job_masks(n)) return 0;
   const int64_t tiles = (count + kBlock - 1) / kBlock;
   return (size_t)tiles * (kBlock / 64) * (size_t)mask_slot_bytes(n);
+}
+// Whether bounding this instance takes the job-mask walk, and the scratch
+// that walk needs for a pool of `count` nodes (0 for every other walk).
+inline bool takes_mask_walk(const fsp_instance *in) {
+  return uses_job_masks(in->n) && in->masks_walk != 0;
+}
+inline size_t walk_scratch_bytes(const fsp_instance *in, int64_t count) {
+  return takes_mask_walk(in) ? bound_scratch_bytes(in->n, count) : 0;
 }
 
 // Launches the pool-bounding kernel (bound.hip).  Validates nothing: the

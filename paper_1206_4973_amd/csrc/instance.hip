@@ -222,7 +222,7 @@ int fsp_load_instance_ex(const int32_t *p_host, int32_t n, int32_t m,
   if (!out) return FSP_EINVAL;
   *out = nullptr;
   if (!p_host || n < 1 || m < 2) return FSP_EINVAL;
-  if (flags & ~FSP_LOAD_ONE_NODE_PER_LANE) return FSP_EINVAL;
+  if (flags & ~(FSP_LOAD_ONE_NODE_PER_LANE | FSP_LOAD_JOB_MASKS)) return FSP_EINVAL;
   if (n > kMaxJobs || m > kMaxMachines) return FSP_EUNSUPPORTED;
   int64_t total = 0;
   for (int j = 0; j < n; ++j) {
@@ -247,6 +247,7 @@ int fsp_load_instance_ex(const int32_t *p_host, int32_t n, int32_t m,
   in->npad = round_up(n, 4);
   in->wide = n > 32 ? 1 : 0;
   in->p16 = (n <= 32 && total <= 32767 && !(flags & FSP_LOAD_ONE_NODE_PER_LANE)) ? 1 : 0;
+  in->masks_walk = (flags & FSP_LOAD_JOB_MASKS) ? 1 : 0;
   in->p_host.assign(p_host, p_host + (size_t)n * m);
   if (hipGetDevice(&in->device) != hipSuccess) {
     delete in;
@@ -281,7 +282,9 @@ int fsp_instance_info(const fsp_instance *inst, int32_t *n, int32_t *m,
 int fsp_instance_path(const fsp_instance *inst, int32_t *path) {
   if (!inst || !path) return FSP_EINVAL;
   if (inst->wide)
-    *path = uses_job_masks(inst->n) ? FSP_PATH_MASKS : FSP_PATH_REGISTER64;
+    *path = !uses_job_masks(inst->n) ? FSP_PATH_REGISTER64
+            : inst->masks_walk      ? FSP_PATH_MASKS
+                                    : FSP_PATH_BYTES;
   else
     *path = inst->p16 ? FSP_PATH_PACKED : FSP_PATH_REGISTER;
   return FSP_OK;

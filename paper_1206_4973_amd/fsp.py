@@ -29,6 +29,7 @@ _lib = None
 
 
 LOAD_ONE_NODE_PER_LANE = 1  # FSP_LOAD_ONE_NODE_PER_LANE
+LOAD_JOB_MASKS = 2  # FSP_LOAD_JOB_MASKS
 
 
 class FspError(RuntimeError):
@@ -180,7 +181,7 @@ class Instance:
     packed=False keeps an instance that qualifies for the two-nodes-per-lane
     16-bit form on the one-node-per-lane 32-bit form (same bounds)."""
 
-    def __init__(self, p, packed: bool = True):
+    def __init__(self, p, packed: bool = True, job_masks: bool = False):
         if isinstance(p, torch.Tensor):
             p = p.detach().cpu().numpy()
         p = np.ascontiguousarray(p, dtype=np.int32)
@@ -189,7 +190,7 @@ class Instance:
         self.p = p
         self.n, self.m = int(p.shape[0]), int(p.shape[1])
         h = ctypes.c_void_p()
-        flags = 0 if packed else LOAD_ONE_NODE_PER_LANE
+        flags = (0 if packed else LOAD_ONE_NODE_PER_LANE) | (LOAD_JOB_MASKS if job_masks else 0)
         _check(lib().fsp_load_instance_ex(p.ctypes.data_as(ctypes.c_void_p), self.n, self.m,
                                           flags, ctypes.byref(h)), "fsp_load_instance_ex")
         self._h = h
@@ -200,11 +201,11 @@ class Instance:
     @property
     def bound_path(self) -> str:
         """Form of the bounding walk used for this instance: "register",
-        "packed" (two nodes per lane, 16-bit), "register64" (33..64 jobs) or
-        "masks" (n > 64)."""
+        "packed" (two nodes per lane, 16-bit), "register64" (33..64 jobs),
+        "bytes" (n > 64) or "masks" (n > 64, loaded with job_masks=True)."""
         v = ctypes.c_int32(0)
         _check(lib().fsp_instance_path(self.handle, ctypes.byref(v)), "fsp_instance_path")
-        return {0: "register", 1: "packed", 2: "masks", 3: "register64"}[v.value]
+        return {0: "register", 1: "packed", 2: "masks", 3: "register64", 4: "bytes"}[v.value]
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -240,6 +241,10 @@ class Instance:
 
     @property
     def noalloc_max_count(self) -> int:
+        """Largest pool bound_pool_noalloc accepts: the fixed scratch limits
+        only the job-mask walk; every other walk takes no scratch."""
+        if self.bound_path != "masks":
+            return (1 << 63) - 1
         return int(lib().fsp_noalloc_max_count(self.n))
 
     def bound_pool_one_machine(self, nodes: torch.Tensor, out: torch.Tensor | None = None,
@@ -426,7 +431,7 @@ class Batch:
         bpc = ctypes.c_int32()
         _check(lib().fsp_batch_paths(self._h, arr, self.nsegs, ctypes.byref(bpc)),
                "fsp_batch_paths")
-        names = {0: "register", 1: "packed", 2: "masks", 3: "register64"}
+        names = {0: "register", 1: "packed", 2: "masks", 3: "register64", 4: "bytes"}
         return [names.get(arr[i]) for i in range(self.nsegs)], bpc.value
 
     def close(self):

@@ -100,7 +100,7 @@ def test_load_flags_checked_before_device_work(L):
     L.fsp_load_instance_ex.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
     p = np.ones((4, 3), np.int32)
-    for flags in (2, 4, -1, 1 << 30):
+    for flags in (4, 8, -1, 1 << 30):
         h = ctypes.c_void_p(1)
         rc = L.fsp_load_instance_ex(p.ctypes.data_as(ctypes.c_void_p), 4, 3, flags,
                                     ctypes.byref(h))

@@ -218,7 +218,7 @@ def test_larger_instances_inside_the_search(fsp, orc, n, m, kind):
     bound."""
     p = I.instance(n, m, 7700 + n + m)
     inst = fsp.Instance(p)
-    assert inst.bound_path == ("register64" if n <= 64 else "masks")
+    assert inst.bound_path == ("register64" if n <= 64 else "bytes")
     say(f"{n}x{m} {kind} with a 1.5 s limit")
     res = fsp.branch_and_bound(inst, kind, time_limit=1.5)
     assert res.status in (0, 1)

@@ -60,11 +60,13 @@ def test_shapes_bit_exact(fsp, orc, n, m):
     p = I.instance(n, m, 7000 + 31 * n + m)
     pool = I.random_pool(n, count, 0, n, 8000 + 31 * n + m)
     say(f"shape n={n} m={m}: {count} nodes")
-    inst = fsp.Instance(p)
-    got = gpu_bounds(fsp, inst, pool)
     want = orc.bound_pool(p, pool, nthreads=8)
-    bad = np.nonzero(got != want)[0]
-    assert bad.size == 0, (bad[:10], got[bad[:10]], want[bad[:10]])
+    # above 64 jobs both walks: the bytes walk (default) and the job masks
+    for masks in ((False, True) if n > 64 else (False,)):
+        inst = fsp.Instance(p, job_masks=masks)
+        got = gpu_bounds(fsp, inst, pool)
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, (inst.bound_path, bad[:10], got[bad[:10]], want[bad[:10]])
 
 
 def test_zero_times_and_ties(fsp, orc):
@@ -211,18 +213,24 @@ def test_full_size_pool_register_form(fsp, orc):
 
 
 def test_full_size_pool_sampled_200x20(fsp, orc):
-    """200x20, 2^22 nodes (job-mask form): the oracle is too slow for every
-    node, so 2048 random nodes and the last 37 are compared with it; every
-    node bounds at least the root (the bound never decreases along a
-    branch) and none is invalid."""
+    """200x20, 2^22 nodes (bytes walk, the default above 64 jobs): the oracle
+    is too slow for every node, so 2048 random nodes and the last 37 are
+    compared with it; every node bounds at least the root (the bound never
+    decreases along a branch) and none is invalid.  The job-mask walk, an
+    independent device path, gives the same bound on every node."""
     n, m, seed = 200, 20, 5001
     count = 1 << 22
     say(f"full size n={n} m={m}: generating {count} nodes")
     p = I.instance(n, m, seed)
     pool = I.random_pool(n, count, 1, n - 1, seed + 500000)
     inst = fsp.Instance(p)
+    assert inst.bound_path == "bytes"
     say("  bounding on the GPU")
     got = gpu_bounds(fsp, inst, pool)
+    masks = fsp.Instance(p, job_masks=True)
+    assert masks.bound_path == "masks"
+    say("  bounding on the GPU, job-mask walk")
+    assert np.array_equal(gpu_bounds(fsp, masks, pool), got)
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(count, size=2048, replace=False))
     idx = np.unique(np.concatenate([idx, np.arange(count - 37, count)]))
@@ -323,12 +331,12 @@ def test_packed_path_limits(fsp, orc, n, m, total, big):
 
 
 def test_concurrent_streams_with_job_mask_scratch(fsp, orc):
-    """Instances above 64 jobs bound with per-wave mask scratch that the
-    library keeps per stream: two streams bounding different pools at the same
-    time, then a larger pool on the first stream (its workspace grows), must
-    all match the oracle."""
+    """Instances above 64 jobs on the job-mask walk bound with per-wave mask
+    scratch that the library keeps per stream: two streams bounding different
+    pools at the same time, then a larger pool on the first stream (its
+    workspace grows), must all match the oracle."""
     p = I.instance(100, 5, 7101)
-    inst = fsp.Instance(p)
+    inst = fsp.Instance(p, job_masks=True)
     assert inst.bound_path == "masks"
     pools = [I.random_pool(100, c, 0, 100, 7200 + c) for c in (3000, 2500, 9000)]
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()

@@ -1,9 +1,9 @@
 """fsp_bound_pool_noalloc, the bounding entry point that allocates nothing,
 through the C ABI: its bounds equal fsp_bound_pool's bit for bit on two calls
 in a row (the second with a smaller pool, so a stale scratch would show), for
-instances that need the fixed scratch (job-mask walk, n > 64) and for those
-that need none; a pool beyond the fixed scratch is refused before any device
-work."""
+instances that need the fixed scratch (the job-mask walk, n > 64, loaded with
+FSP_LOAD_JOB_MASKS) and for those that need none (every other walk); a pool
+beyond the fixed scratch is refused before any device work."""
 import sys
 
 import numpy as np
@@ -14,8 +14,11 @@ from paper_1206_4973_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(100, 20, 30001, 4099), (200, 10, 20480, 2561), (255, 5, 9000, 700),
-         (80, 3, 70000, 513), (20, 20, 5000, 1537), (50, 10, 6000, 300)]
+# (n, m, first pool, second pool, job-mask walk)
+CASES = [(100, 20, 30001, 4099, True), (200, 10, 20480, 2561, True),
+         (255, 5, 9000, 700, True), (80, 3, 70000, 513, True),
+         (200, 10, 20480, 2561, False), (20, 20, 5000, 1537, False),
+         (50, 10, 6000, 300, False)]
 
 
 def say(*a):
@@ -32,11 +35,11 @@ def fsp():
     return F
 
 
-@pytest.mark.parametrize("n,m,first,second", CASES,
-                         ids=[f"{n}x{m}" for n, m, _, _ in CASES])
-def test_noalloc_equals_bound_pool_on_two_calls(fsp, orc, n, m, first, second):
+@pytest.mark.parametrize("n,m,first,second,masks", CASES,
+                         ids=[f"{n}x{m}{'_masks' if k else ''}" for n, m, _, _, k in CASES])
+def test_noalloc_equals_bound_pool_on_two_calls(fsp, orc, n, m, first, second, masks):
     p = I.instance(n, m, 9100 + n + m)
-    inst = fsp.Instance(p)
+    inst = fsp.Instance(p, job_masks=masks)
     assert first <= inst.noalloc_max_count
     stream = torch.cuda.current_stream()
     for call, count in enumerate((first, second)):
@@ -59,7 +62,7 @@ def test_noalloc_equals_bound_pool_on_two_calls(fsp, orc, n, m, first, second):
 
 def test_noalloc_refuses_a_pool_beyond_its_scratch(fsp):
     n, m = 255, 4
-    inst = fsp.Instance(I.instance(n, m, 9300))
+    inst = fsp.Instance(I.instance(n, m, 9300), job_masks=True)
     cap = inst.noalloc_max_count
     assert 0 < cap < 1 << 40
     count = cap + 1
@@ -73,3 +76,5 @@ def test_noalloc_refuses_a_pool_beyond_its_scratch(fsp):
     assert int(out.abs().sum()) == 0  # nothing was queued
     small = fsp.Instance(I.instance(20, 5, 9301))
     assert small.noalloc_max_count == (1 << 63) - 1
+    # the bytes walk (the default above 64 jobs) takes no scratch
+    assert fsp.Instance(I.instance(n, m, 9300)).noalloc_max_count == (1 << 63) - 1
