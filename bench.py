@@ -143,7 +143,7 @@ def paired_summary(rows, base, kind, limit):
 
 
 def bnb_leg(seeds, time_limit, only=None, prefilter=False, kinds=None,
-            host_threads=0) -> dict:
+            host_threads=0, bound_choice=0) -> dict:
     """Time to a proven optimum on held-out 20x10 instances: plain adaptive
     (the paper's Algorithm 1, launch by launch) vs batched (graph-replayed
     iterations, autotuned pool) vs batched + learned ordering and pool size.
@@ -162,11 +162,14 @@ def bnb_leg(seeds, time_limit, only=None, prefilter=False, kinds=None,
     for s in seeds:
         inst = fsp.Instance(inputs.instance(20, 10, s))
         fsp.autotune_pool(inst)  # per-shape tuning, cached; not part of a run
+        if bound_choice:
+            depths = fsp.autotune_bounds(inst)  # likewise
         row = {"seed": s}
         for kind in kinds:
             kw = {"model": model} if kind == "learned" else {}
             r = fsp.branch_and_bound(inst, kind, time_limit=time_limit,
-                                     prefilter=prefilter, host_threads=host_threads, **kw)
+                                     prefilter=prefilter, host_threads=host_threads,
+                                     bound_choice=bound_choice, **kw)
             progress(f"bnb seed {s} {kind}: {r.makespan} "
                      f"{'proven' if r.status == 0 else 'censored'} in {r.t_total_s:.3f} s")
             row[kind] = {"makespan": r.makespan, "proven": r.status == 0,
@@ -177,8 +180,9 @@ def bnb_leg(seeds, time_limit, only=None, prefilter=False, kinds=None,
         inst.close()
         rows.append(row)
     out = {"instances": f"20x10, seeds {seeds[0]}..{seeds[-1]} ({len(seeds)} held out)",
+           "lb1_depths": depths if bound_choice else [],
            "time_limit_s": time_limit, "kinds": kinds, "one_machine_prefilter": prefilter,
-           "host_threads": host_threads,
+           "host_threads": host_threads, "bound_choice": bound_choice,
            "leg_wall_s": time.perf_counter() - t_leg}
     # an exact search proves the same optimum whatever its kind: compare the
     # makespans of the kinds that proved it
@@ -437,6 +441,9 @@ def main() -> int:
                     help="time limit of each search of the 20x20 instance (s)")
     ap.add_argument("--bnb-seeds", type=int, default=0,
                     help="with --workload bnb: only the first K held-out seeds")
+    ap.add_argument("--bound-choice", type=int, default=0, choices=[0, 1],
+                    help="with --workload bnb: 1 = the one-machine bound at the depths the "
+                         "autotuner picks per shape (the two-machine bound elsewhere)")
     ap.add_argument("--host-threads", type=int, default=0,
                     help="with --workload bnb: hybrid search, this many CPU threads "
                          "exploring subtrees beside the device")
@@ -487,7 +494,8 @@ def main() -> int:
     if args.workload == "bnb":
         seeds = HELD_OUT_SEEDS[:args.bnb_seeds] if args.bnb_seeds else HELD_OUT_SEEDS
         print(json.dumps(bnb_leg(seeds, args.bnb_limit, args.bnb_kind, args.prefilter,
-                                 host_threads=args.host_threads)),
+                                 host_threads=args.host_threads,
+                                 bound_choice=args.bound_choice)),
               flush=True)
         return 0
     n, m, seed = 20, 20, 2000

@@ -305,6 +305,18 @@ typedef struct {
                              jobs taken from the deepest bucket whenever
                              they are idle, sharing UB with the device at
                              every batch of pools; 0: none                 */
+  int32_t bound_choice;   /* the bound per depth (Sec. VI: other lower
+                             bounds): 0: the two-machine bound at every
+                             depth; 1: the depths chosen by
+                             fsp_autotune_bounds (cached per shape) take
+                             the one-machine bound, the others the
+                             two-machine bound; 2: the depths whose bit is
+                             set in lb1_depths take the one-machine bound.
+                             Exact in every case (both are lower bounds);
+                             host threads of the hybrid always take the
+                             two-machine bound.                            */
+  uint32_t lb1_depths[8]; /* bound_choice 2: bit d of word d / 32 set for
+                             every depth d bounded by the one-machine bound */
 } fsp_pool_policy;
 
 typedef struct {
@@ -388,6 +400,34 @@ int fsp_branch_and_bound(const fsp_instance *inst,
 int fsp_adaptive_schedule(int32_t threads_per_block, int32_t cus, int64_t max_threads,
                           int64_t max_pool, const double *efficiency, int32_t batches,
                           int64_t *targets_out);
+
+/* The per-depth choice of bound (bound_choice 1; Sec. VI names other lower
+ * bounds as future work).  A short search from NEH (budget_s seconds, <= 0:
+ * 1 s; autotuned pool, the two-machine bound everywhere) counts per depth d
+ * the bounded nodes with jobs left, those the one-machine bound eliminates
+ * against the UB of the moment, and those the two-machine bound eliminates;
+ * fsp_bound_choice_rule turns the counts into the mask (8 words, bit d of
+ * word d / 32).  Cached per (device, n, m): later calls return the first
+ * result. */
+int fsp_autotune_bounds(const fsp_instance *inst, double budget_s, uint32_t *mask_out);
+
+/* The rule of fsp_autotune_bounds (host only): from the deepest depth up,
+ * depth d (1 .. n-1) takes the one-machine bound when it had nodes, the
+ * next depth keeps the two-machine bound, and (elim2[d] - elim1[d]) *
+ * (n - d) <= total[d] / 2 -- the nodes only the two-machine bound would have
+ * eliminated, branched into n - d children that the next depth's
+ * two-machine bound eliminates, cost at most half of the two-machine
+ * walks saved.  total, elim1, elim2: 256 counts each, indexed by depth. */
+int fsp_bound_choice_rule(int32_t n, const uint32_t *total, const uint32_t *elim1,
+                          const uint32_t *elim2, uint32_t *mask_out);
+
+/* fsp_branch_and_bound that also returns the per-depth counts of the bound
+ * choice (stats_out: [3][256] words: bounded nodes with jobs left, those
+ * the one-machine bound eliminates, those the two-machine bound eliminates,
+ * against the UB of the moment).  While counting, the pre-filter skips no
+ * walk; policy->bound_choice must be 0 (FSP_EINVAL otherwise). */
+int fsp_depth_stats(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_in,
+                    uint32_t *stats_out, fsp_result *result);
 
 /*
  * fsp_autotune_pool -- the pool size (children per pool) that maximises

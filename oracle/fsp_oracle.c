@@ -469,8 +469,22 @@ static int keeps(int rule, int64_t lb, int64_t ub) {
   return rule == 1 ? (lb <= ub) : (lb < ub);
 }
 
-int64_t orc_bnb(const int32_t *p, int n, int m, int64_t ub_in, int rule,
-                int64_t max_bounded, uint8_t *perm_out, orc_stats *st) {
+/* The bound of a node under a per-depth choice (Sec. VI: other lower
+ * bounds): a node of depth d, 0 < d < n, whose bit d is set in lb1_mask (8
+ * words, bit d of word d / 32) takes the one-machine bound; every other node
+ * (the root, complete schedules, unset depths, or no mask) the two-machine
+ * bound. */
+static int64_t bound_at_depth(const int32_t *p, int n, int m, const uint8_t *node,
+                              const uint32_t *lb1_mask) {
+  const int d = node[0];
+  if (lb1_mask && d > 0 && d < n && ((lb1_mask[d >> 5] >> (d & 31)) & 1u))
+    return orc_lower_bound_one_machine(p, n, m, node);
+  return orc_lower_bound(p, n, m, node);
+}
+
+int64_t orc_bnb_choice(const int32_t *p, int n, int m, int64_t ub_in, int rule,
+                       int64_t max_bounded, const uint32_t *lb1_mask, uint8_t *perm_out,
+                       orc_stats *st) {
   /* max_bounded > 0 stops the search once that many bounds were evaluated
    * (complete = 0); the returned UB is then only an upper bound. */
   memset(st, 0, sizeof(*st));
@@ -528,7 +542,7 @@ int64_t orc_bnb(const int32_t *p, int n, int m, int64_t ub_in, int rule,
       memcpy(child, v, (size_t)rec);
       child[0] = (uint8_t)(d + 1);
       child[1 + d] = (uint8_t)j;
-      int64_t clb = orc_lower_bound(p, n, m, child);
+      int64_t clb = bound_at_depth(p, n, m, child, lb1_mask);
       st->nodes_bounded++;
       if (d + 1 == n) {
         st->leaves++;
@@ -557,4 +571,10 @@ int64_t orc_bnb(const int32_t *p, int n, int m, int64_t ub_in, int rule,
   free(stk);
   free(slb);
   return ub;
+}
+
+/* The search with the two-machine bound at every depth. */
+int64_t orc_bnb(const int32_t *p, int n, int m, int64_t ub_in, int rule,
+                int64_t max_bounded, uint8_t *perm_out, orc_stats *st) {
+  return orc_bnb_choice(p, n, m, ub_in, rule, max_bounded, NULL, perm_out, st);
 }

@@ -95,6 +95,9 @@ def _load(path: str | None = None):
     lib.orc_bnb.argtypes = [P, ctypes.c_int, ctypes.c_int, i64, ctypes.c_int, i64, P,
                             ctypes.POINTER(Stats)]
     lib.orc_bnb.restype = i64
+    lib.orc_bnb_choice.argtypes = [P, ctypes.c_int, ctypes.c_int, i64, ctypes.c_int, i64, P, P,
+                                   ctypes.POINTER(Stats)]
+    lib.orc_bnb_choice.restype = i64
     del i32
     _lib = lib
     return lib
@@ -222,4 +225,19 @@ def bnb(p, ub_in: int = 0, rule: int = 0, max_bounded: int = 0):
     st = Stats()
     c = _load().orc_bnb(_ptr(p), n, m, int(ub_in), int(rule), int(max_bounded),
                         _ptr(perm), ctypes.byref(st))
+    return int(c), perm, st
+
+
+def bnb_choice(p, lb1_depths, ub_in: int = 0, rule: int = 0, max_bounded: int = 0):
+    """The same search with the one-machine bound at the depths in
+    `lb1_depths` (0 < d < n) and the two-machine bound elsewhere (the
+    per-depth choice of bound; Sec. VI).  Returns (makespan, perm, Stats)."""
+    p, n, m = _p(p)
+    mask = np.zeros(8, dtype=np.uint32)
+    for d in lb1_depths:
+        mask[int(d) >> 5] |= np.uint32(1 << (int(d) & 31))
+    perm = np.zeros(n, dtype=np.uint8)
+    st = Stats()
+    c = _load().orc_bnb_choice(_ptr(p), n, m, int(ub_in), int(rule), int(max_bounded),
+                               _ptr(mask), _ptr(perm), ctypes.byref(st))
     return int(c), perm, st

@@ -541,7 +541,8 @@ void BnbState::release() {
                   (void *)desc, (void *)best_perm, (void *)target_dev, (void *)bscore,
                   (void *)tnodes, (void *)tlb, (void *)tscore, (void *)hist, X,
                   (void *)rowdst,
-                  (void *)log_nodes, (void *)log_lb, (void *)min_est})
+                  (void *)log_nodes, (void *)log_lb, (void *)min_est, (void *)lb1_mask,
+                  (void *)depth_stats})
     if (p) (void)hipFree(p);
   if (host_min_est) (void)hipHostFree(host_min_est);
   if (host_desc) (void)hipHostFree(host_desc);
@@ -598,10 +599,12 @@ int BnbState::enqueue_iteration_impl(hipStream_t s) {
                      hist, model ? 1 : 0);
   FSP_HIP_TRY(hipGetLastError());
   Prefilter pf;
-  if (prefilter) {
+  if (prefilter || depth_stats) {
     pf.ub = &desc->ub;  // constant from this iteration's plan to the next
     pf.rule = rule;
   }
+  pf.lb1_depths = lb1_mask;
+  pf.depth_stats = depth_stats;
   rc = launch_bound(inst, pool, stride, cap, pool_lb, s, &desc->children, slots, pf);
   if (rc != FSP_OK) return rc;
   hipLaunchKernelGGL(prune_kernel, dim3(grid), dim3(kThreads), 0, s, desc,
@@ -798,9 +801,16 @@ struct TuneEntry {
 };
 std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune;
+// depths bounded by the one-machine bound, per (device, n, m)
+struct BoundTuneEntry {
+  int dev, n, m;
+  uint32_t mask[8];
+};
+std::vector<BoundTuneEntry> g_bound_tune;
 
 int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_in,
-            fsp_result *out, const SampleSpec *samples, RateWindow *window = nullptr);
+            fsp_result *out, const SampleSpec *samples, RateWindow *window = nullptr,
+            std::vector<uint32_t> *depth_stats = nullptr);
 
 int tuned_pool(const fsp_instance *inst, int64_t *pool) {
   int64_t p = 0;
@@ -848,8 +858,19 @@ int hybrid_exchange(BnbState &S, HostSearch &hs, const BnbDesc &h, int threads, 
 }
 
 int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_in,
-            fsp_result *out, const SampleSpec *samples, RateWindow *window) {
+            fsp_result *out, const SampleSpec *samples, RateWindow *window,
+            std::vector<uint32_t> *depth_stats) {
   if (!inst || !policy || !out) return FSP_EINVAL;
+  if (policy->bound_choice < 0 || policy->bound_choice > 2) return FSP_EINVAL;
+  // the per-depth choice of bound (Sec. VI: other lower bounds): the depths
+  // whose nodes take the one-machine bound, from the autotuner or the caller
+  uint32_t lb1_mask[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (policy->bound_choice == 1) {
+    const int rc = fsp_autotune_bounds(inst, 0.0, lb1_mask);
+    if (rc != FSP_OK) return rc;
+  } else if (policy->bound_choice == 2) {
+    std::copy(policy->lb1_depths, policy->lb1_depths + 8, lb1_mask);
+  }
   if (policy->prune_rule != FSP_PRUNE_GE && policy->prune_rule != FSP_PRUNE_GT)
     return FSP_EINVAL;
   if (policy->host_threads < 0 || policy->host_threads > 256) return FSP_EINVAL;
@@ -904,6 +925,16 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
   BnbState S;
   int rc = S.init(inst, max_pool, policy->prune_rule);
   S.prefilter = policy->prefilter == 1 ? 1 : 0;
+  if (rc == FSP_OK && policy->bound_choice != 0) {
+    if (hipMalloc(&S.lb1_mask, sizeof(lb1_mask)) != hipSuccess ||
+        hipMemcpy(S.lb1_mask, lb1_mask, sizeof(lb1_mask), hipMemcpyHostToDevice) != hipSuccess)
+      rc = FSP_ENOMEM;
+  }
+  if (rc == FSP_OK && depth_stats) {
+    if (hipMalloc(&S.depth_stats, 768 * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(S.depth_stats, 0, 768 * sizeof(uint32_t)) != hipSuccess)
+      rc = FSP_ENOMEM;
+  }
   // the batched kinds fill each pool from several depths, deepest first; the
   // paper's adaptive kind and fixed pools take one depth per pool
   S.multi = kind == FSP_POOL_AUTOTUNED || kind == FSP_POOL_LEARNED ? 1 : 0;
@@ -1102,6 +1133,14 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
     }
     if (status == 1) out->open_lb = std::min(out->open_lb, std::min(hs.open_lb(), out->makespan));
   }
+  if (depth_stats) {
+    depth_stats->assign(768, 0u);
+    if (hipMemcpy(depth_stats->data(), S.depth_stats, 768 * sizeof(uint32_t),
+                  hipMemcpyDeviceToHost) != hipSuccess) {
+      S.release();
+      return FSP_EDEVICE;
+    }
+  }
   S.release();
   return FSP_OK;
 }
@@ -1148,6 +1187,74 @@ int fsp_policy_samples(const fsp_instance *inst, const fsp_pool_policy *policy, 
   SampleSpec s{max_samples, sample_prob, seed, x_out, target_out, n_out};
   *n_out = 0;
   return run_bnb(inst, policy, ub_in, result, &s);
+}
+
+int fsp_bound_choice_rule(int32_t n, const uint32_t *total, const uint32_t *elim1,
+                          const uint32_t *elim2, uint32_t *mask_out) {
+  if (n < 1 || n > kMaxJobs || !total || !elim1 || !elim2 || !mask_out) return FSP_EINVAL;
+  std::fill(mask_out, mask_out + 8, 0u);
+  // deepest first: depth d takes the one-machine bound when the nodes that
+  // only the pair bound eliminates there, each branched into n - d children
+  // bounded at the next depth, cost at most half the pair walks it saves, and
+  // the next depth keeps the pair bound (so those children are eliminated
+  // there: the pair bound never decreases along a branch)
+  bool next_lb1 = false;
+  for (int d = n - 1; d >= 1; --d) {
+    const double t = total[d];
+    const double extra = elim2[d] > elim1[d] ? (double)(elim2[d] - elim1[d]) : 0.0;
+    const bool lb1 = t > 0 && !next_lb1 && extra * (double)(n - d) <= 0.5 * t;
+    if (lb1) mask_out[d >> 5] |= 1u << (d & 31);
+    next_lb1 = lb1;
+  }
+  return FSP_OK;
+}
+
+int fsp_autotune_bounds(const fsp_instance *inst, double budget_s, uint32_t *mask_out) {
+  if (!inst || !mask_out) return FSP_EINVAL;
+  int dev = 0;
+  FSP_HIP_TRY(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const BoundTuneEntry &e : g_bound_tune)
+      if (e.dev == dev && e.n == inst->n && e.m == inst->m) {
+        std::copy(e.mask, e.mask + 8, mask_out);
+        return FSP_OK;
+      }
+  }
+  // a short search from NEH with the pair bound at every depth, counting per
+  // depth how many bounded nodes each bound eliminates against the UB of
+  // the moment
+  fsp_pool_policy pol{};
+  pol.kind = FSP_POOL_AUTOTUNED;
+  pol.nb_iterations = 10;
+  pol.time_limit_s = budget_s > 0 ? budget_s : 1.0;
+  pol.prune_rule = FSP_PRUNE_GE;
+  fsp_result r{};
+  std::vector<uint32_t> st;
+  int rc = run_bnb(inst, &pol, 0, &r, nullptr, nullptr, &st);
+  if (rc != FSP_OK) return rc;
+  uint32_t mask[8];
+  rc = fsp_bound_choice_rule(inst->n, st.data(), st.data() + 256, st.data() + 512, mask);
+  if (rc != FSP_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    BoundTuneEntry e{dev, inst->n, inst->m, {}};
+    std::copy(mask, mask + 8, e.mask);
+    g_bound_tune.push_back(e);
+  }
+  std::copy(mask, mask + 8, mask_out);
+  return FSP_OK;
+}
+
+int fsp_depth_stats(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_in,
+                    uint32_t *stats_out, fsp_result *result) {
+  if (!inst || !policy || !stats_out || !result) return FSP_EINVAL;
+  if (policy->bound_choice != 0) return FSP_EINVAL;  // counts need the pair bound everywhere
+  std::vector<uint32_t> st;
+  const int rc = run_bnb(inst, policy, ub_in, result, nullptr, nullptr, &st);
+  if (rc != FSP_OK) return rc;
+  std::copy(st.begin(), st.end(), stats_out);
+  return FSP_OK;
 }
 
 int fsp_autotune_pool(const fsp_instance *inst, double budget_s, int64_t *pool_out,

@@ -111,6 +111,8 @@ struct BnbState {
   const fsp_instance *inst = nullptr;
   int n = 0, stride = 0, rule = 0, cus = 0;
   int prefilter = 0;  // one-machine pre-filter in the bounding launches
+  uint32_t *lb1_mask = nullptr;     // depths bounded by the one-machine bound (8 words)
+  uint32_t *depth_stats = nullptr;  // measurement of the per-depth choice ([3][256])
   int multi = 0;      // pools take parents from several depths (deepest first)
   int64_t cap = 0;  // records per bucket and in the pool buffer
   uint8_t *bnodes = nullptr;   // [n][cap][stride]

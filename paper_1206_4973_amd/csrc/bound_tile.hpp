@@ -720,6 +720,34 @@ __device__ __forceinline__ bool eliminated(int lb, int ub, int rule) {
   return rule == FSP_PRUNE_GT ? lb > ub : lb >= ub;
 }
 
+// Whether the per-depth choice gives a node of depth d the one-machine bound.
+__device__ __forceinline__ bool lb1_at_depth(const uint32_t *mask, int d) {
+  return mask && ((mask[d >> 5] >> (d & 31)) & 1u);
+}
+
+// Measurement of the per-depth choice: one count per node with jobs left
+// (cnt), per depth d, of the node and of its eliminations by the one-machine
+// (e1) and the pair bound (e2).  The lanes at the depth of the wave's first
+// lane are counted with one atomic per counter, the others one by one.
+// Every lane of the wave calls it.
+__device__ __forceinline__ void count_depth_stats(uint32_t *stats, bool cnt, int d, bool e1,
+                                                  bool e2) {
+  const int d0 = __builtin_amdgcn_readfirstlane(d);
+  const bool same = d == d0;
+  const uint64_t b0 = __ballot(cnt && same), b1 = __ballot(cnt && same && e1),
+                 b2 = __ballot(cnt && same && e2);
+  if (__lane_id() == 0 && b0) {
+    atomicAdd(&stats[d0], (uint32_t)__popcll(b0));
+    if (b1) atomicAdd(&stats[256 + d0], (uint32_t)__popcll(b1));
+    if (b2) atomicAdd(&stats[512 + d0], (uint32_t)__popcll(b2));
+  }
+  if (cnt && !same) {
+    atomicAdd(&stats[d], 1u);
+    if (e1) atomicAdd(&stats[256 + d], 1u);
+    if (e2) atomicAdd(&stats[512 + d], 1u);
+  }
+}
+
 // Bound the 256 nodes [base, base + 256) of a pool (one per lane), writing
 // lb_out[idx] for idx < count.  For n > 32, tile_slots is this tile's part of
 // the mask scratch: kBlock / 64 slots of I.slot_bytes, never used by another
@@ -758,16 +786,18 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
 
   // one-machine bound max_k r[k] + S[k] + q[k] (T and Q carry r + S and q);
   // the wave skips the pair walks when it decides every live node
-  bool skip = false;
+  bool skip = false, only1 = false;
   int lb1 = 0;
-  if (pf.lb1_only || pf.ub) {
+  if (pf.lb1_only || pf.ub || pf.lb1_depths) {
     int m1 = 0;
 #pragma unroll
     for (int k = 0; k < M; ++k) m1 = max(m1, T256[k] + Q256[k]);
     lb1 = m1 >> 8;
-    bool decided = !live || bad || u_left == 0;
-    if (!pf.lb1_only) decided = decided || eliminated(lb1, *pf.ub, pf.rule);
-    skip = pf.lb1_only || __ballot(!decided) == 0;
+    only1 = pf.lb1_only || (live && !bad && lb1_at_depth(pf.lb1_depths, d));
+    bool decided = !live || bad || u_left == 0 || only1;
+    if (pf.ub && !pf.lb1_only && !pf.depth_stats)
+      decided = decided || eliminated(lb1, *pf.ub, pf.rule);
+    skip = __ballot(!decided) == 0;
   }
 
   // ---- 3. (n > 32) the wave's job masks, then every machine pair.  The
@@ -834,7 +864,13 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   }
 
   // ---- 4. result ----
-  int lb = u_left == 0 ? last : (skip ? lb1 : (LB256 >> 8));
+  int lb = u_left == 0 ? last : ((skip || only1) ? lb1 : (LB256 >> 8));
+  if (pf.depth_stats && pf.ub) {
+    const int ub = *pf.ub;
+    const bool cnt = live && !bad && u_left > 0;
+    count_depth_stats(pf.depth_stats, cnt, d, cnt && eliminated(lb1, ub, pf.rule),
+                      cnt && eliminated(LB256 >> 8, ub, pf.rule));
+  }
   if (bad) lb = FSP_LB_INVALID;
   if (live) lb_out[idx] = lb;
 }
@@ -1212,18 +1248,21 @@ __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView 
   node_state_p16<M>(I, reinterpret_cast<const uint32_t *>(L.s_p), nodes, stride,
                     aligned, ia, ib, la, lbv, UA, UB, badA, badB, last, R, T, Q);
   // one-machine bounds of both nodes (see bound_nodes)
-  bool skip = false;
+  bool skip = false, onlyA = false, onlyB = false;
   uint32_t LB1 = 0;
-  if (pf.lb1_only || pf.ub) {
+  const int dA = I.n - __builtin_popcount(UA), dB = I.n - __builtin_popcount(UB);
+  if (pf.lb1_only || pf.ub || pf.lb1_depths) {
 #pragma unroll
     for (int k = 0; k < M; ++k) LB1 = pk_max(LB1, pk_add(T[k], Q[k]));
-    bool da = !la || badA || UA == 0u, db = !lbv || badB || UB == 0u;
-    if (!pf.lb1_only) {
+    onlyA = pf.lb1_only || (la && !badA && lb1_at_depth(pf.lb1_depths, dA));
+    onlyB = pf.lb1_only || (lbv && !badB && lb1_at_depth(pf.lb1_depths, dB));
+    bool da = !la || badA || UA == 0u || onlyA, db = !lbv || badB || UB == 0u || onlyB;
+    if (pf.ub && !pf.lb1_only && !pf.depth_stats) {
       const int ub = *pf.ub;
       da = da || eliminated((int)(LB1 & 0xffffu), ub, pf.rule);
       db = db || eliminated((int)(LB1 >> 16), ub, pf.rule);
     }
-    skip = pf.lb1_only || __ballot(!(da && db)) == 0;
+    skip = __ballot(!(da && db)) == 0;
   }
 #pragma unroll
   for (int k = 0; k < M; ++k) asm volatile("" : "+v"(R[k]), "+v"(T[k]), "+v"(Q[k]));
@@ -1236,12 +1275,20 @@ __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView 
       AL[j] = ((UA >> j) & 1u) | (((UB >> j) & 1u) << 16);
     LB = pair_sweep_p16<M>(L.s_rec, I.job16, I.npad, AL, R, T, Q);
   }
+  if (pf.depth_stats && pf.ub) {
+    const int ub = *pf.ub;
+    const bool ca = la && !badA && UA != 0u, cb = lbv && !badB && UB != 0u;
+    count_depth_stats(pf.depth_stats, ca, dA, ca && eliminated((int)(LB1 & 0xffffu), ub, pf.rule),
+                      ca && eliminated((int)(LB & 0xffffu), ub, pf.rule));
+    count_depth_stats(pf.depth_stats, cb, dB, cb && eliminated((int)(LB1 >> 16), ub, pf.rule),
+                      cb && eliminated((int)(LB >> 16), ub, pf.rule));
+  }
   if (la) {
-    int lb = UA == 0u ? (int)(last & 0xffffu) : (int)(LB & 0xffffu);
+    int lb = UA == 0u ? (int)(last & 0xffffu) : (int)(((skip || onlyA) ? LB1 : LB) & 0xffffu);
     lb_out[ia] = badA ? FSP_LB_INVALID : lb;
   }
   if (lbv) {
-    int lb = UB == 0u ? (int)(last >> 16) : (int)(LB >> 16);
+    int lb = UB == 0u ? (int)(last >> 16) : (int)(((skip || onlyB) ? LB1 : LB) >> 16);
     lb_out[ib] = badB ? FSP_LB_INVALID : lb;
   }
 }

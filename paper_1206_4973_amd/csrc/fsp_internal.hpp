@@ -114,11 +114,19 @@ inline size_t walk_scratch_bytes(const fsp_instance *in, int64_t count) {
 // live nodes all have a one-machine bound that the rule eliminates against
 // *ub skips the pair walks and reports those bounds (the eliminations are
 // the same: the pair bound is never smaller).  lb1_only: every node gets
-// its one-machine bound.
+// its one-machine bound.  lb1_depths (device, 8 words): a node whose depth's
+// bit is set gets its one-machine bound (the other bound of the choice per
+// depth); a wave whose nodes all have it skips the pair walks.
+// depth_stats (device, [3][256] words, measurement): per depth of the
+// bounded nodes with jobs left, the count of such nodes, of those the
+// one-machine bound eliminates against *ub, and of those the pair bound
+// eliminates; the pre-filter's skipping is off while measuring.
 struct Prefilter {
   const int32_t *ub = nullptr;  // device pointer, read when the kernel starts
   int rule = 0;                 // FSP_PRUNE_GE or FSP_PRUNE_GT
   int lb1_only = 0;
+  const uint32_t *lb1_depths = nullptr;
+  uint32_t *depth_stats = nullptr;
 };
 
 int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,

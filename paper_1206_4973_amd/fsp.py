@@ -63,7 +63,8 @@ class _Policy(ctypes.Structure):
                 ("fixed_pool", ctypes.c_int64), ("max_pool", ctypes.c_int64),
                 ("time_limit_s", ctypes.c_double), ("prune_rule", ctypes.c_int32),
                 ("prefilter", ctypes.c_int32), ("model", ctypes.c_void_p),
-                ("log_path", ctypes.c_char_p), ("host_threads", ctypes.c_int32)]
+                ("log_path", ctypes.c_char_p), ("host_threads", ctypes.c_int32),
+                ("bound_choice", ctypes.c_int32), ("lb1_depths", ctypes.c_uint32 * 8)]
 
 
 class _Result(ctypes.Structure):
@@ -134,6 +135,12 @@ def lib() -> ctypes.CDLL:
     L.fsp_autotune_pool.restype = ctypes.c_int
     L.fsp_adaptive_schedule.argtypes = [i32, i32, i64, i64, P, i32, P]
     L.fsp_adaptive_schedule.restype = ctypes.c_int
+    L.fsp_autotune_bounds.argtypes = [P, ctypes.c_double, P]
+    L.fsp_autotune_bounds.restype = ctypes.c_int
+    L.fsp_bound_choice_rule.argtypes = [i32, P, P, P, P]
+    L.fsp_bound_choice_rule.restype = ctypes.c_int
+    L.fsp_depth_stats.argtypes = [P, ctypes.POINTER(_Policy), i32, P, ctypes.POINTER(_Result)]
+    L.fsp_depth_stats.restype = ctypes.c_int
     L.fsp_policy_samples.argtypes = [P, ctypes.POINTER(_Policy), i32, i64, ctypes.c_double,
                                      ctypes.c_uint64, P, P, ctypes.POINTER(i64),
                                      ctypes.POINTER(_Result)]
@@ -290,7 +297,12 @@ class Result:
 def make_policy(kind: str = "adaptive", *, fixed_pool: int = 0, max_pool: int = 0,
                 nb_iterations: int = 10, time_limit: float | None = None,
                 prune_rule: str = "ge", model=None, log_path: str | None = None,
-                prefilter: bool = False, host_threads: int = 0) -> _Policy:
+                prefilter: bool = False, host_threads: int = 0,
+                bound_choice: int = 0, lb1_depths=None) -> _Policy:
+    """The search policy (fsp_pool_policy).  bound_choice: 0 the two-machine
+    bound at every depth; 1 the depths fsp_autotune_bounds picks take the
+    one-machine bound; 2 the depths in `lb1_depths` (an iterable of depths)
+    take it."""
     pol = _Policy()
     pol.kind = POOL_KINDS[kind]
     pol.nb_iterations = int(nb_iterations)
@@ -302,6 +314,9 @@ def make_policy(kind: str = "adaptive", *, fixed_pool: int = 0, max_pool: int = 
     pol.model = ctypes.c_void_p(model.handle.value) if model is not None else None
     pol.log_path = log_path.encode() if log_path else None
     pol.host_threads = int(host_threads)
+    pol.bound_choice = int(bound_choice)
+    for d in (lb1_depths or ()):
+        pol.lb1_depths[int(d) >> 5] |= 1 << (int(d) & 31)
     return pol
 
 
@@ -316,6 +331,46 @@ def branch_and_bound(inst: Instance, kind: str = "adaptive", ub: int | None = No
                                       int(ub) if ub else 0, ctypes.byref(res)),
            "fsp_branch_and_bound")
     return Result(res, perm[:inst.n].copy())
+
+
+def _mask_depths(words) -> list:
+    return [32 * w + b for w in range(8) for b in range(32) if (int(words[w]) >> b) & 1]
+
+
+def autotune_bounds(inst: Instance, budget_s: float = 0.0) -> list:
+    """Depths that fsp_autotune_bounds gives the one-machine bound (cached
+    per shape)."""
+    mask = (ctypes.c_uint32 * 8)()
+    _check(lib().fsp_autotune_bounds(inst.handle, float(budget_s), mask), "fsp_autotune_bounds")
+    return _mask_depths(mask)
+
+
+def bound_choice_rule(n: int, total, elim1, elim2) -> list:
+    """Depths that fsp_bound_choice_rule gives the one-machine bound for the
+    per-depth counts (host only)."""
+    arrs = [np.zeros(256, dtype=np.uint32) for _ in range(3)]
+    for a, v in zip(arrs, (total, elim1, elim2)):
+        v = np.asarray(v, dtype=np.uint32)
+        a[:len(v)] = v
+    mask = (ctypes.c_uint32 * 8)()
+    _check(lib().fsp_bound_choice_rule(int(n), *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs],
+                                       mask), "fsp_bound_choice_rule")
+    return _mask_depths(mask)
+
+
+def depth_stats(inst: Instance, kind: str = "adaptive", ub: int | None = None, **policy):
+    """(Result, counts [3][256]) of fsp_depth_stats: per depth, bounded nodes
+    with jobs left and those the one-machine and the two-machine bound
+    eliminate."""
+    pol = make_policy(kind, **policy)
+    perm = np.zeros(max(inst.n, 1), dtype=np.uint8)
+    res = _Result()
+    res.perm = perm.ctypes.data_as(ctypes.c_void_p).value
+    st = np.zeros((3, 256), dtype=np.uint32)
+    _check(lib().fsp_depth_stats(inst.handle, ctypes.byref(pol), int(ub) if ub else 0,
+                                 st.ctypes.data_as(ctypes.c_void_p), ctypes.byref(res)),
+           "fsp_depth_stats")
+    return Result(res, perm[:inst.n].copy()), st
 
 
 def autotune_pool(inst: Instance, budget_s: float = 0.0):

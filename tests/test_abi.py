@@ -105,3 +105,46 @@ def test_load_flags_checked_before_device_work(L):
         rc = L.fsp_load_instance_ex(p.ctypes.data_as(ctypes.c_void_p), 4, 3, flags,
                                     ctypes.byref(h))
         assert rc == -1 and not h.value
+
+
+def test_bound_choice_rule(L):
+    """The host rule of the per-depth bound choice on hand-made counts:
+    deepest first, a depth takes the one-machine bound when it had nodes, the
+    next depth keeps the pair bound, and (elim2 - elim1) * (n - d) <=
+    total / 2."""
+    L.fsp_bound_choice_rule.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 4
+    L.fsp_bound_choice_rule.restype = ctypes.c_int
+
+    def rule(n, total, e1, e2):
+        arrs = [np.zeros(256, np.uint32) for _ in range(3)]
+        for a, v in zip(arrs, (total, e1, e2)):
+            for d, x in v.items():
+                a[d] = x
+        mask = np.zeros(8, np.uint32)
+        rc = L.fsp_bound_choice_rule(n, *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs],
+                                     mask.ctypes.data_as(ctypes.c_void_p))
+        assert rc == 0
+        return [32 * w + b for w in range(8) for b in range(32) if (int(mask[w]) >> b) & 1]
+
+    n = 10
+    flat = {d: 1000 for d in range(1, n)}
+    # nothing only the pair bound eliminates: every other depth from n - 1 up
+    assert rule(n, flat, {}, {}) == [1, 3, 5, 7, 9]
+    # depth 9 (one child per survivor): 500 extra of 1000 is exactly half
+    assert rule(n, flat, {}, {9: 500}) == [1, 3, 5, 7, 9]
+    assert rule(n, flat, {}, {9: 501}) == [2, 4, 6, 8]
+    # depth 6 (4 children per survivor): 126 extra is over the limit; depth 5
+    # (5 children): 100 extra (107 - 7) is the limit
+    assert rule(n, flat, {5: 7}, {9: 501, 6: 126, 5: 107}) == [1, 3, 5, 8]
+    assert rule(n, flat, {5: 7}, {9: 501, 6: 126, 5: 108}) == [2, 4, 8]
+    # a depth below one that takes the one-machine bound keeps the pair bound
+    assert rule(n, flat, {}, {9: 501, 6: 125}) == [2, 4, 6, 8]
+    # depths without nodes keep the pair bound (and free the one above)
+    assert rule(n, {3: 10, 4: 10}, {}, {}) == [4]
+    assert rule(n, {}, {}, {}) == []
+    # elim1 above elim2 (not expected) counts as no extra elimination
+    assert rule(4, {1: 10, 2: 10, 3: 10}, {3: 9}, {3: 2}) == [1, 3]
+    mask = np.zeros(8, np.uint32)
+    z = np.zeros(256, np.uint32).ctypes.data_as(ctypes.c_void_p)
+    assert L.fsp_bound_choice_rule(0, z, z, z, mask.ctypes.data_as(ctypes.c_void_p)) == -1
+    assert L.fsp_bound_choice_rule(10, None, z, z, mask.ctypes.data_as(ctypes.c_void_p)) == -1

@@ -292,3 +292,64 @@ def test_hybrid_reaches_the_optimum(fsp, orc, kind):
         assert 0 <= res.host_nodes <= res.nodes_bounded
         host_total += res.host_nodes
     assert host_total > 0
+
+
+@pytest.mark.parametrize("rule", ["ge", "gt"])
+@pytest.mark.parametrize("packed", [True, False], ids=["packed", "one_node"])
+@pytest.mark.parametrize("n,m,seed", [(9, 5, 1000), (11, 7, 71), (12, 6, 61)])
+def test_bound_chosen_per_depth_counts_equal_oracle(fsp, orc, n, m, seed, rule, packed):
+    """The per-depth choice of bound (Sec. VI: other lower bounds): with UB =
+    the optimum, the search that gives the one-machine bound to the depths
+    of a mask bounds, branches and eliminates exactly the nodes of the
+    oracle's search with the same choice, in every kind, with two nodes per
+    lane (packed) and one (the code of every one-node form)."""
+    p = I.instance(n, m, seed)
+    opt, _, _ = orc.bnb(p)
+    inst = fsp.Instance(p, packed=packed)
+    assert inst.bound_path == ("packed" if packed else "register")
+    model = fsp.Model(2 + 2 * min(m, 15), 2, seed=seed)
+    r = 0 if rule == "ge" else 1
+    masks = ([1, 2, 3], [n - 1], list(range(1, n, 2)), list(range(1, n)))
+    for depths in masks:
+        say(f"{n}x{m} {rule}: oracle with the one-machine bound at {depths[:4]}..")
+        oc, _, ost = orc.bnb_choice(p, depths, opt, r)
+        assert oc == opt and ost.complete == 1
+        for kind, kw in (("fixed", {"fixed_pool": 37}), ("adaptive", {}),
+                         ("autotuned", {"fixed_pool": 64}),
+                         ("learned", {"fixed_pool": 3000, "model": model}),
+                         ("fixed", {"fixed_pool": 37, "prefilter": True})):
+            res = fsp.branch_and_bound(inst, kind, ub=opt, prune_rule=rule, bound_choice=2,
+                                       lb1_depths=depths, **kw)
+            say(f"{n}x{m} {rule} lb1 at {depths[:4]}.. {kind}: {res.nodes_bounded} vs "
+                f"{ost.nodes_bounded}")
+            assert res.makespan == opt and res.found == 0 and res.status == 0
+            assert res.nodes_bounded == ost.nodes_bounded
+            assert res.nodes_branched == ost.nodes_branched
+            assert res.leaves == ost.leaves
+            assert res.nodes_pruned == ost.nodes_pruned
+
+
+def test_autotuned_bound_choice_reaches_the_optimum(fsp, orc):
+    """fsp_autotune_bounds: the depths it picks are within 1..n-1, no two
+    adjacent, the same on a second call (cached); searches with the choice
+    from NEH return the oracle's optimum with a valid schedule; the counts
+    behind the choice are consistent (the pair bound eliminates every node
+    the one-machine bound eliminates)."""
+    for n, m, seed in ((12, 6, 61), (14, 7, 63), (20, 10, 4501)):
+        p = I.instance(n, m, seed)
+        inst = fsp.Instance(p)
+        depths = fsp.autotune_bounds(inst, 0.5)
+        say(f"{n}x{m}: one-machine bound at depths {depths}")
+        assert all(1 <= d <= n - 1 for d in depths)
+        assert all(b - a >= 2 for a, b in zip(depths, depths[1:]))
+        assert fsp.autotune_bounds(inst) == depths
+        res, st = fsp.depth_stats(inst, "autotuned", time_limit=0.5)
+        assert (st[1] <= st[2]).all() and (st[2] <= st[0]).all()
+        assert int(st[0].sum()) <= res.nodes_bounded
+        assert st[0][n:].sum() == 0 and st[0][0] == 0
+        if n <= 14:
+            oc, _, _ = orc.bnb(p)
+            for kind in ("adaptive", "autotuned"):
+                res = fsp.branch_and_bound(inst, kind, bound_choice=1)
+                assert res.status == 0 and res.makespan == oc
+                check_schedule(orc, p, res)

@@ -327,7 +327,7 @@ def test_neh_is_a_valid_upper_bound(orc):
         assert orc.neh(p)[0] == orc.brute_force(p)[0]
 
 
-def _critical_tree_counts(orc, p, opt, rule):
+def _critical_tree_counts(orc, p, opt, rule, lb1_depths=()):
     """Counters of any complete search started with UB = opt, enumerated
     breadth-first.  No schedule beats opt, so UB never changes: a node is
     branched iff it is incomplete and kept (LB < opt for rule 0, LB <= opt
@@ -337,6 +337,9 @@ def _critical_tree_counts(orc, p, opt, rule):
     bounded, and eliminated when it is not kept."""
     n = p.shape[0]
     keep = (lambda lb: lb < opt) if rule == 0 else (lambda lb: lb <= opt)
+    # the per-depth choice: the one-machine bound at the depths listed
+    bound = lambda pre: (orc.lower_bound_one_machine(p, pre) if len(pre) in lb1_depths
+                         else orc.lower_bound(p, pre))
     c = {"bounded": 1, "branched": 0, "pruned": 0, "leaves": 0}
     if keep(orc.lower_bound(p, [])) and n > 0:
         frontier = [[]]
@@ -355,7 +358,7 @@ def _critical_tree_counts(orc, p, opt, rule):
                 if len(child) == n:
                     c["leaves"] += 1
                     c["pruned"] += 1
-                elif keep(orc.lower_bound(p, child)):
+                elif keep(bound(child)):
                     nxt.append(child)
                 else:
                     c["pruned"] += 1
@@ -378,6 +381,31 @@ def test_critical_tree_is_order_independent(orc, rule):
         c, _, st = orc.bnb(p, opt, rule)
         assert c == opt and st.found == 0 and st.complete == 1
         assert _stats_counts(st) == _critical_tree_counts(orc, p, opt, rule)
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_critical_tree_with_the_bound_chosen_per_depth(orc, rule):
+    """The search with the one-machine bound at some depths (Sec. VI: other
+    lower bounds) has the critical-tree counters of that choice, enumerated
+    independently, and at least those of the two-machine bound everywhere
+    (the one-machine bound is never larger, so every node kept by the pair
+    bound is kept by it); searched from NEH it still returns the optimum."""
+    rng = np.random.default_rng(40 + rule)
+    for _ in range(10):
+        n, m = int(rng.integers(3, 8)), int(rng.integers(2, 6))
+        p = rng.integers(1, 99, size=(n, m)).astype(np.int32)
+        opt, _ = orc.brute_force(p)
+        plain = _critical_tree_counts(orc, p, opt, rule)
+        for depths in ([1], [n - 1], list(range(1, n)), [d for d in range(1, n) if d % 2]):
+            c, _, st = orc.bnb_choice(p, depths, opt, rule)
+            assert c == opt and st.found == 0 and st.complete == 1
+            got = _stats_counts(st)
+            assert got == _critical_tree_counts(orc, p, opt, rule, set(depths))
+            assert got["bounded"] >= plain["bounded"]
+            c, perm, st = orc.bnb_choice(p, depths, 0, rule)
+            assert c == opt and st.complete == 1 and orc.makespan(p, perm) == opt
+        # no depth chosen: the plain search
+        assert _stats_counts(orc.bnb_choice(p, [], opt, rule)[2]) == plain
 
 
 def test_identical_jobs_search_counters_closed_form(orc):
