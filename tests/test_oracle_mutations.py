@@ -55,6 +55,12 @@ MUTATIONS = [
      "        ++nk;\n      } else {\n        (void)0;"),
     ("one_machine_largest_tail", "if (min_after < 0 || after < min_after) min_after = after;",
      "if (min_after < 0 || after > min_after) min_after = after;"),
+    # the per-depth choice of bound
+    ("choice_bounds_swapped", "    return orc_lower_bound_one_machine(p, n, m, node);\n  return orc_lower_bound(p, n, m, node);",
+     "    return orc_lower_bound(p, n, m, node);\n  return orc_lower_bound_one_machine(p, n, m, node);"),
+    ("choice_depth_off_by_one", "((lb1_mask[d >> 5] >> (d & 31)) & 1u)",
+     "((lb1_mask[(d + 1) >> 5] >> ((d + 1) & 31)) & 1u)"),
+    ("choice_mask_ignored", "  if (lb1_mask && d > 0 && d < n &&", "  if (0 && lb1_mask && d > 0 && d < n &&"),
 ]
 
 PINS = [
@@ -99,6 +105,10 @@ def _run_pins():
             pins.test_critical_tree_is_order_independent(O, rule)
         except AssertionError:
             failed.append("critical_tree_%d" % rule)
+        try:
+            pins.test_critical_tree_with_the_bound_chosen_per_depth(O, rule)
+        except AssertionError:
+            failed.append("critical_tree_choice_%d" % rule)
     return failed
 
 
