@@ -204,21 +204,28 @@ typedef struct {
  *   autotune          1: before planning, time the candidate walk forms of
  *                     each (n, m) shape on the batch's own segments of that
  *                     shape (packed or 32-bit for n <= 32, 64-bit register or
- *                     job masks for 33..64 jobs), then the workgroups per CU
+ *                     job masks for 33..64 jobs, job masks or bytes above),
+ *                     then the workgroups per CU
  *                     on the whole batch, and keep the fastest; the picks
  *                     are cached per device and shape (forms) and per batch
  *                     signature (workgroups per CU), so later batches of the
  *                     same shapes plan without timing.  Timing launches the
  *                     batch: its lb_out buffers are written.  0: every
  *                     segment takes its shape's default form (the fastest in
- *                     single-pool measurements, as fsp_instance_path).
+ *                     single-pool measurements, as fsp_instance_path, but the
+ *                     job masks above 64 jobs: in a batch the bytes walk runs
+ *                     in a kernel of its own after the others, which cost
+ *                     more than it saved on the mixed batches measured).
  *   one_node_per_lane 1: never the packed two-nodes-per-lane form.
+ *   bytes_walk        1: segments of more than 64 jobs take the bytes walk
+ *                     by default (instances loaded with FSP_LOAD_JOB_MASKS
+ *                     keep the job masks).
  * Other values are FSP_EINVAL. */
 typedef struct {
   int32_t blocks_per_cu;
   int32_t autotune;
   int32_t one_node_per_lane;
-  int32_t reserved;
+  int32_t bytes_walk;
 } fsp_batch_config;
 
 typedef struct fsp_batch fsp_batch;
@@ -244,9 +251,10 @@ int fsp_batch_launch(fsp_batch *b, void *stream);
  * call and replayed on every call (on `stream`). */
 int fsp_batch_replay(fsp_batch *b, void *stream);
 
-/* Tiles (256 nodes, or 512 in the packed form), persistent grid size,
- * segments in the batch kernel and segments bounded by single-pool launches
- * (any pointer may be NULL). */
+/* Tiles (256 nodes, or 512 in the packed form), the largest persistent
+ * grid, segments in the batch kernels (one-node forms, packed form, bytes
+ * form) and segments bounded by single-pool launches (any pointer may be
+ * NULL). */
 int fsp_batch_info(const fsp_batch *b, int64_t *tiles, int32_t *grid,
                    int32_t *kernel_segments, int32_t *fallback_segments);
 

@@ -43,8 +43,18 @@ enum SegForm : int {
   kSegMasksC = 2,  // job masks, table streamed in chunks
   kSegReg64 = 3,   // 33..64 jobs, 64-bit register
   kSegPacked = 4,  // n <= 32 and total work <= 32767, two nodes per lane
-  kSegForms = 5
+  kSegBytes = 5,   // n > 64, flag bytes in LDS, whole table in LDS
+  kSegBytesC = 6,  // n > 64, flag bytes in LDS, table streamed in chunks
+  kSegForms = 7
 };
+
+// Kernel (part) of a form: the one-node register and mask forms, the packed
+// form, the bytes form (each pins registers or LDS that would cost the others
+// occupancy).
+constexpr int kParts = 3;
+__host__ __device__ constexpr int part_of(int form) {
+  return form == kSegPacked ? 1 : (form == kSegBytes || form == kSegBytesC) ? 2 : 0;
+}
 
 // Variant = machine-count base (5, 10 or 20 machines) * kSegForms + form.
 __host__ __device__ constexpr int variant(int mbase, int form) { return mbase * kSegForms + form; }
@@ -64,20 +74,23 @@ struct BatchSeg {
 constexpr size_t kWideBudget = 32 * 1024;
 constexpr size_t kNarrowBudget = 64 * 1024;
 
-__global__ void reset_counters(unsigned long long *c0, unsigned long long *c1) {
+__global__ void reset_counters(unsigned long long *c0, unsigned long long *c1,
+                               unsigned long long *c2) {
   if (threadIdx.x == 0 && c0) *c0 = 0ull;
   if (threadIdx.x == 1 && c1) *c1 = 0ull;
+  if (threadIdx.x == 2 && c2) *c2 = 0ull;
 }
 
 template <int M, int FORM, bool CHUNKED>
 __device__ __forceinline__ void run_tile(const BatchSeg &S, char *smem,
                                          int64_t t, bool restage,
                                          char *tile_slots) {
-  constexpr bool WIDE = FORM == kFormMasks;
+  constexpr bool WIDE = FORM == kFormMasks || FORM == kFormBytes;
+  constexpr bool BYTES = FORM == kFormBytes;
   const InstView I = S.I;
-  const LdsView L = carve<WIDE>(smem, I);
+  const LdsView L = carve<WIDE, BYTES>(smem, I);
   if (restage) {
-    stage_instance<WIDE>(I, L);
+    stage_instance<WIDE, BYTES>(I, L);
     __syncthreads();
   }
   bound_nodes<M, FORM, CHUNKED>(I, L, S.nodes, S.stride, S.aligned != 0,
@@ -98,11 +111,16 @@ __device__ __forceinline__ void run_tile_p16(const BatchSeg &S, char *smem, int6
                      (t - S.tile_begin) * 2 * kBlock, S.count, S.lb);
 }
 
-template <int M, bool PACKED>
+template <int M, int KIND>
 __device__ __forceinline__ void run_any(const BatchSeg &S, int form, char *smem, int64_t t,
                                         bool restage, char *ts) {
-  if constexpr (PACKED) {
+  if constexpr (KIND == 1) {
     run_tile_p16<M>(S, smem, t, restage);
+  } else if constexpr (KIND == 2) {
+    if (form == kSegBytes)
+      run_tile<M, kFormBytes, false>(S, smem, t, restage, ts);
+    else
+      run_tile<M, kFormBytes, true>(S, smem, t, restage, ts);
   } else {
     switch (form) {
       case kSegReg32: run_tile<M, kFormReg32, false>(S, smem, t, restage, ts); break;
@@ -116,9 +134,11 @@ __device__ __forceinline__ void run_any(const BatchSeg &S, int form, char *smem,
 
 // The packed segments run in a kernel of their own: the packed walk pins
 // 48 VGPRs (its multipliers and load buffers), which in one kernel with the
-// other forms cost those forms spills and a fifth of their speed.
-template <bool PACKED>
-__global__ __launch_bounds__(kBlock, 4) void batch_kernel(
+// other forms cost those forms spills and a fifth of their speed.  So do the
+// bytes segments (64 pinned VGPRs, two workgroups per CU for their LDS).
+// KIND: 0 the one-node register and mask forms, 1 packed, 2 bytes.
+template <int KIND>
+__global__ __launch_bounds__(kBlock, KIND == 2 ? 2 : 4) void batch_kernel(
     const BatchSeg *__restrict__ segs, int nsegs, int64_t total_tiles,
     unsigned long long *counter, char *slots, int64_t tile_bytes) {
   extern __shared__ __align__(16) char smem[];
@@ -145,9 +165,9 @@ __global__ __launch_bounds__(kBlock, 4) void batch_kernel(
     char *ts = slots + t * tile_bytes;  // this tile's job-mask slots
     const int mbase = S.variant / kSegForms, form = S.variant - mbase * kSegForms;
     switch (mbase) {
-      case 0: run_any<5, PACKED>(S, form, smem, t, restage, ts); break;
-      case 1: run_any<10, PACKED>(S, form, smem, t, restage, ts); break;
-      case 2: run_any<20, PACKED>(S, form, smem, t, restage, ts); break;
+      case 0: run_any<5, KIND>(S, form, smem, t, restage, ts); break;
+      case 1: run_any<10, KIND>(S, form, smem, t, restage, ts); break;
+      case 2: run_any<20, KIND>(S, form, smem, t, restage, ts); break;
       default: break;
     }
   }
@@ -157,20 +177,26 @@ int machine_base(int m) { return m == 5 ? 0 : m == 10 ? 1 : m == 20 ? 2 : -1; }
 
 // The walk forms an instance's shape allows, the default (fastest in
 // single-pool measurements) first.
-std::vector<int> forms_for(const fsp_instance *inst, const InstView &v, bool allow_packed) {
+std::vector<int> forms_for(const fsp_instance *inst, const InstView &v, bool allow_packed,
+                           bool prefer_bytes) {
   const int masks = v.nchunks > 1 ? kSegMasksC : kSegMasks;
   if (!inst->wide) {
     if (inst->p16 && allow_packed) return {kSegPacked, kSegReg32};
     return {kSegReg32};
   }
   if (!uses_job_masks(inst->n)) return {kSegReg64, masks};
-  return {masks};
+  const int bytes =
+      inst_view(inst, table_budget_bytes(inst->n)).nchunks > 1 ? kSegBytesC : kSegBytes;
+  // the job masks by default (an instance loaded for them always), the bytes
+  // walk when the batch asks for it
+  if (prefer_bytes && !inst->masks_walk) return {bytes, masks};
+  return {masks, bytes};
 }
 
 // Relative cost of one tile: table steps per node times nodes per tile times
 // the walk's vector instructions per step (per node).
 double tile_cost(const fsp_instance *in, int form) {
-  static const double per_step[kSegForms] = {4.0, 3.0, 3.0, 5.0, 1.5};
+  static const double per_step[kSegForms] = {4.0, 3.0, 3.0, 5.0, 1.5, 4.25, 4.25};
   const double nodes = form == kSegPacked ? 2.0 * kBlock : (double)kBlock;
   return (double)in->P * in->npad * nodes * per_step[form];
 }
@@ -178,7 +204,8 @@ double tile_cost(const fsp_instance *in, int form) {
 }  // namespace
 
 // One persistent launch over a segment table: part 0 holds the one-node-per-
-// lane forms, part 1 the packed form.
+// lane register and mask forms, part 1 the packed form, part 2 the bytes
+// form.
 struct BatchPart {
   int nsegs = 0;
   int64_t total_tiles = 0;
@@ -190,7 +217,7 @@ struct BatchPart {
 
 struct fsp_batch {
   int device = 0;
-  BatchPart part[2];
+  BatchPart part[kParts];
   char *d_slots = nullptr;  // job-mask scratch of part 0 and the fallbacks
   int64_t tile_bytes = 0;   // scratch bytes per tile of part 0
   std::vector<fsp_segment> fallback;  // bounded by single-pool launches
@@ -204,16 +231,21 @@ struct fsp_batch {
 namespace {
 
 int enqueue(fsp_batch *b, hipStream_t s) {
-  const BatchPart &p0 = b->part[0], &p1 = b->part[1];
-  if (p0.nsegs > 0 || p1.nsegs > 0) {
-    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, p0.d_counter, p1.d_counter);
+  const BatchPart &p0 = b->part[0], &p1 = b->part[1], &p2 = b->part[2];
+  if (p0.nsegs > 0 || p1.nsegs > 0 || p2.nsegs > 0) {
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, p0.d_counter, p1.d_counter,
+                       p2.d_counter);
     if (p0.nsegs > 0)
-      hipLaunchKernelGGL(batch_kernel<false>, dim3(p0.grid), dim3(kBlock), p0.lds, s,
+      hipLaunchKernelGGL(batch_kernel<0>, dim3(p0.grid), dim3(kBlock), p0.lds, s,
                          p0.d_segs, p0.nsegs, p0.total_tiles, p0.d_counter, b->d_slots,
                          b->tile_bytes);
     if (p1.nsegs > 0)
-      hipLaunchKernelGGL(batch_kernel<true>, dim3(p1.grid), dim3(kBlock), p1.lds, s,
+      hipLaunchKernelGGL(batch_kernel<1>, dim3(p1.grid), dim3(kBlock), p1.lds, s,
                          p1.d_segs, p1.nsegs, p1.total_tiles, p1.d_counter,
+                         (char *)nullptr, (int64_t)0);
+    if (p2.nsegs > 0)
+      hipLaunchKernelGGL(batch_kernel<2>, dim3(p2.grid), dim3(kBlock), p2.lds, s,
+                         p2.d_segs, p2.nsegs, p2.total_tiles, p2.d_counter,
                          (char *)nullptr, (int64_t)0);
     FSP_HIP_TRY(hipGetLastError());
   }
@@ -250,6 +282,8 @@ int path_of_form(int form) {
     case kSegReg32: return FSP_PATH_REGISTER;
     case kSegPacked: return FSP_PATH_PACKED;
     case kSegReg64: return FSP_PATH_REGISTER64;
+    case kSegBytes:
+    case kSegBytesC: return FSP_PATH_BYTES;
     default: return FSP_PATH_MASKS;
   }
 }
@@ -257,7 +291,7 @@ int path_of_form(int form) {
 // Plans a batch with the given form per shape (absent shapes: the default
 // form) and workgroups per CU (<= 0: as many as fit).
 int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
-          bool allow_packed, fsp_batch **out) {
+          bool allow_packed, bool prefer_bytes, fsp_batch **out) {
   *out = nullptr;
   fsp_batch *b = new (std::nothrow) fsp_batch();
   if (!b) return FSP_ENOMEM;
@@ -282,7 +316,7 @@ int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
     }
     Item it{};
     it.s.I = inst_view(in, in->wide ? kWideBudget : kNarrowBudget);
-    const std::vector<int> allowed = forms_for(in, it.s.I, allow_packed);
+    const std::vector<int> allowed = forms_for(in, it.s.I, allow_packed, prefer_bytes);
     int form = allowed[0];
     const auto f = forms.find({in->n, in->m});
     if (f != forms.end() &&
@@ -290,8 +324,13 @@ int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
       form = f->second;
     b->path[i] = path_of_form(form);
     // the job-mask walk needs its per-wave slots also below 65 jobs (where
-    // the instance's default form needs none)
+    // the instance's default form needs none); the bytes walk none, and its
+    // own table budget
     if (form == kSegMasks || form == kSegMasksC) it.s.I.slot_bytes = mask_slot_bytes(in->n);
+    if (part_of(form) == 2) {
+      it.s.I = inst_view(in, table_budget_bytes(in->n));
+      it.s.I.slot_bytes = 0;
+    }
     it.s.variant = variant(mb, form);
     it.s.tile_nodes = form == kSegPacked ? 2 * kBlock : kBlock;
     it.s.nodes = g.data;
@@ -307,9 +346,9 @@ int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
   }
   std::stable_sort(items.begin(), items.end(),
                    [](const Item &a, const Item &c) { return a.cost > c.cost; });
-  std::vector<BatchSeg> table[2];
-  int64_t tiles[2] = {0, 0};
-  size_t lds[2] = {16, 16};
+  std::vector<BatchSeg> table[kParts];
+  int64_t tiles[kParts] = {0, 0, 0};
+  size_t lds[kParts] = {16, 16, 16};
   int slot_max = 0;
   for (const Item &it : items) slot_max = std::max(slot_max, it.s.I.slot_bytes);
   size_t scratch = 0;
@@ -317,13 +356,14 @@ int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
     scratch = std::max(scratch, bound_scratch_bytes(f.inst->n, f.count));
   for (Item &it : items) {
     const int form = it.s.variant % kSegForms;
-    const int k = form == kSegPacked ? 1 : 0;
+    const int k = part_of(form);
     it.s.tile_begin = tiles[k];
     tiles[k] += (it.s.count + it.s.tile_nodes - 1) / it.s.tile_nodes;
     const InstView &I = it.s.I;
     lds[k] = std::max(lds[k], k == 1 ? lds_bytes_p16(I.n, I.mp, I.npad, I.P)
-                                     : lds_bytes(I.n, I.mp, I.npad, I.ppc,
-                                                 form == kSegMasks || form == kSegMasksC));
+                              : k == 2 ? lds_bytes(I.n, I.mp, I.npad, I.ppc, true, true)
+                                       : lds_bytes(I.n, I.mp, I.npad, I.ppc,
+                                                   form == kSegMasks || form == kSegMasksC));
     table[k].push_back(it.s);
   }
   b->tile_bytes = (int64_t)(kBlock / 64) * slot_max;
@@ -349,7 +389,7 @@ int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
     destroy(b);
     return FSP_EDEVICE;
   }
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < kParts; ++k) {
     BatchPart &p = b->part[k];
     p.nsegs = (int)table[k].size();
     p.total_tiles = tiles[k];
@@ -365,8 +405,9 @@ int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
       destroy(b);
       return FSP_EDEVICE;
     }
-    const void *fn = k == 0 ? reinterpret_cast<const void *>(batch_kernel<false>)
-                            : reinterpret_cast<const void *>(batch_kernel<true>);
+    const void *fn = k == 0   ? reinterpret_cast<const void *>(batch_kernel<0>)
+                     : k == 1 ? reinterpret_cast<const void *>(batch_kernel<1>)
+                              : reinterpret_cast<const void *>(batch_kernel<2>);
     int per_cu = 0;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds) !=
             hipSuccess ||
@@ -416,13 +457,16 @@ int time_batch(fsp_batch *b, double *secs) {
   return rc;
 }
 
-// Autotuner caches: the form per (device, n, m, packed allowed), and the
-// workgroups per CU per (device, batch signature).
+// Autotuner caches: the form per (device, n, m, packed allowed); per
+// (device, batch signature) whether the shapes on the bytes walk keep it, and
+// the workgroups per CU.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, int> g_form_cache;
 std::map<std::pair<int, std::vector<int64_t>>, int> g_bpc_cache;
+std::map<std::pair<int, std::vector<int64_t>>, bool> g_mix_cache;
 
-int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, FormMap *forms,
+int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, bool prefer_bytes,
+             FormMap *forms,
              int *bpc) {
   int dev = 0;
   FSP_HIP_TRY(hipGetDevice(&dev));
@@ -438,7 +482,7 @@ int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, FormMap 
     bool mixed = false;
     for (const fsp_segment &g : sh.second) mixed = mixed || g.inst->p16 != in->p16;
     const InstView v = inst_view(in, in->wide ? kWideBudget : kNarrowBudget);
-    const std::vector<int> allowed = forms_for(in, v, allow_packed);
+    const std::vector<int> allowed = forms_for(in, v, allow_packed, prefer_bytes);
     if (allowed.size() < 2 || mixed) continue;
     const auto key = std::make_tuple(dev, sh.first.first, sh.first.second,
                                      (int)(allow_packed && in->p16));
@@ -456,7 +500,8 @@ int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, FormMap 
       FormMap fm;
       fm[sh.first] = form;
       fsp_batch *b = nullptr;
-      int rc = build(sh.second.data(), (int32_t)sh.second.size(), fm, 0, allow_packed, &b);
+      int rc = build(sh.second.data(), (int32_t)sh.second.size(), fm, 0, allow_packed,
+                     prefer_bytes, &b);
       double t = 0.0;
       if (rc == FSP_OK) rc = time_batch(b, &t);
       if (b) destroy(b);
@@ -470,24 +515,72 @@ int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, FormMap 
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_form_cache[key] = best;
   }
-  // workgroups per CU on the whole batch: signature = sorted (n, m, form,
-  // tiles rounded to a power of two) of its segments
-  std::vector<int64_t> sig;
+  // signature of the batch under a form map: sorted (n, m, form, nodes
+  // rounded up to a power of two) of its segments
+  auto signature = [&](const FormMap &fm) {
+    std::vector<int64_t> sig;
+    for (int i = 0; i < nsegs; ++i) {
+      if (segs[i].count == 0) continue;
+      int64_t c = 1;
+      while (c < segs[i].count) c <<= 1;
+      const auto f = fm.find({segs[i].inst->n, segs[i].inst->m});
+      sig.push_back(((int64_t)segs[i].inst->n << 48) | ((int64_t)segs[i].inst->m << 40) |
+                    ((int64_t)(f == fm.end() ? 7 : f->second) << 36) | c);
+    }
+    std::sort(sig.begin(), sig.end());
+    sig.push_back((int64_t)allow_packed << 1 | (int64_t)prefer_bytes);
+    return sig;
+  };
+  // Shapes that chose the bytes walk alone put a kernel of its own into the
+  // launch, which runs after the others: keep them there only when the whole
+  // batch is faster so than with the job masks in their place.
+  {
+    FormMap alt = *forms;
+    bool any = false;
+    for (const auto &sh : shapes) {
+      const fsp_instance *in = sh.second[0].inst;
+      const InstView v = inst_view(in, in->wide ? kWideBudget : kNarrowBudget);
+      const std::vector<int> allowed = forms_for(in, v, allow_packed, prefer_bytes);
+      const auto f = forms->find(sh.first);
+      const int form = f != forms->end() ? f->second : allowed[0];
+      if (part_of(form) != 2 || in->masks_walk) continue;
+      alt[sh.first] = v.nchunks > 1 ? kSegMasksC : kSegMasks;
+      any = true;
+    }
+    if (any) {
+      const auto mkey = std::make_pair(dev, signature(*forms));
+      bool keep = true, cached = false;
+      {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        const auto c = g_mix_cache.find(mkey);
+        if (c != g_mix_cache.end()) {
+          keep = c->second;
+          cached = true;
+        }
+      }
+      if (!cached) {
+        double t[2] = {0.0, 0.0};
+        for (int k = 0; k < 2; ++k) {
+          fsp_batch *b = nullptr;
+          int rc = build(segs, nsegs, k == 0 ? *forms : alt, 0, allow_packed, prefer_bytes, &b);
+          if (rc == FSP_OK) rc = time_batch(b, &t[k]);
+          if (b) destroy(b);
+          if (rc != FSP_OK) return rc;
+        }
+        keep = t[0] < t[1];
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_mix_cache[mkey] = keep;
+      }
+      if (!keep) *forms = alt;
+    }
+  }
+  // workgroups per CU on the whole batch
   fsp_batch *probe = nullptr;
-  int rc = build(segs, nsegs, *forms, 0, allow_packed, &probe);
+  int rc = build(segs, nsegs, *forms, 0, allow_packed, prefer_bytes, &probe);
   if (rc != FSP_OK) return rc;
   const int max_bpc = probe->blocks_per_cu;
   destroy(probe);
-  for (int i = 0; i < nsegs; ++i) {
-    if (segs[i].count == 0) continue;
-    int64_t c = 1;
-    while (c < segs[i].count) c <<= 1;
-    const auto f = forms->find({segs[i].inst->n, segs[i].inst->m});
-    sig.push_back(((int64_t)segs[i].inst->n << 48) | ((int64_t)segs[i].inst->m << 40) |
-                  ((int64_t)(f == forms->end() ? 7 : f->second) << 36) | c);
-  }
-  std::sort(sig.begin(), sig.end());
-  const auto bkey = std::make_pair(dev, sig);
+  const auto bkey = std::make_pair(dev, signature(*forms));
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     const auto c = g_bpc_cache.find(bkey);
@@ -500,7 +593,7 @@ int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, FormMap 
   double best_t = 0.0;
   for (int k = max_bpc; k >= 1; --k) {
     fsp_batch *b = nullptr;
-    rc = build(segs, nsegs, *forms, k, allow_packed, &b);
+    rc = build(segs, nsegs, *forms, k, allow_packed, prefer_bytes, &b);
     double t = 0.0;
     if (rc == FSP_OK) rc = time_batch(b, &t);
     if (b) destroy(b);
@@ -534,18 +627,20 @@ int fsp_batch_create(const fsp_segment *segs, int32_t nsegs,
     if (g.stride < g.inst->n + 1) return FSP_EINVAL;
   }
   if (cfg && (cfg->blocks_per_cu < 0 || (cfg->autotune != 0 && cfg->autotune != 1) ||
-              (cfg->one_node_per_lane != 0 && cfg->one_node_per_lane != 1)))
+              (cfg->one_node_per_lane != 0 && cfg->one_node_per_lane != 1) ||
+              (cfg->bytes_walk != 0 && cfg->bytes_walk != 1)))
     return FSP_EINVAL;
   const bool allow_packed = !(cfg && cfg->one_node_per_lane == 1);
+  const bool prefer_bytes = cfg && cfg->bytes_walk == 1;
   FormMap forms;
   int bpc = cfg ? cfg->blocks_per_cu : 0;
   if (cfg && cfg->autotune == 1) {
     int tuned = 0;
-    const int rc = autotune(segs, nsegs, allow_packed, &forms, &tuned);
+    const int rc = autotune(segs, nsegs, allow_packed, prefer_bytes, &forms, &tuned);
     if (rc != FSP_OK) return rc;
     if (bpc <= 0) bpc = tuned;
   }
-  return build(segs, nsegs, forms, bpc, allow_packed, out);
+  return build(segs, nsegs, forms, bpc, allow_packed, prefer_bytes, out);
 }
 
 int fsp_batch_launch(fsp_batch *b, void *stream) {
@@ -576,9 +671,16 @@ int fsp_batch_replay(fsp_batch *b, void *stream) {
 int fsp_batch_info(const fsp_batch *b, int64_t *tiles, int32_t *grid,
                    int32_t *kernel_segments, int32_t *fallback_segments) {
   if (!b) return FSP_EINVAL;
-  if (tiles) *tiles = b->part[0].total_tiles + b->part[1].total_tiles;
-  if (grid) *grid = std::max(b->part[0].grid, b->part[1].grid);
-  if (kernel_segments) *kernel_segments = b->part[0].nsegs + b->part[1].nsegs;
+  int64_t t = 0;
+  int32_t g = 0, k = 0;
+  for (const BatchPart &p : b->part) {
+    t += p.total_tiles;
+    g = std::max(g, (int32_t)p.grid);
+    k += p.nsegs;
+  }
+  if (tiles) *tiles = t;
+  if (grid) *grid = g;
+  if (kernel_segments) *kernel_segments = k;
   if (fallback_segments) *fallback_segments = (int32_t)b->fallback.size();
   return FSP_OK;
 }

@@ -171,15 +171,7 @@ BoundFn kernel_for(int m, int form, bool chunked) {
 // on a compute unit next to the job words.
 constexpr size_t kTableBudgetNarrow = 64 * 1024;
 constexpr size_t kTableBudgetWide = 32 * 1024;
-// The bytes walk: the table chunk (8 bytes of record and 4 of flag offset
-// per position) gets what is left of 80 KB (two workgroups per compute
-// unit) next to the job words and the flag rows.
-size_t table_budget_bytes(int n) {
-  const size_t fixed = (size_t)((n + 31) / 32) * kBlock * 4 + alpha_bytes(n) + 32;
-  const size_t per_wg = 80 * 1024;
-  const size_t rest = fixed + 16 * 1024 <= per_wg ? per_wg - fixed : 16 * 1024;
-  return rest * sizeof(Rec) / (sizeof(Rec) + sizeof(uint32_t));
-}
+
 
 }  // namespace
 

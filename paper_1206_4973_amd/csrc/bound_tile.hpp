@@ -71,6 +71,17 @@ __host__ __device__ inline size_t aoff_bytes(int ppc, int npad) {
   return ((size_t)ppc * npad + 8) * sizeof(uint32_t);
 }
 
+// The bytes walk's budget for records (inst_view's table budget): the chunk
+// (8 bytes of record and 4 of flag offset per position) gets what is left of
+// 80 KB (two workgroups per compute unit) next to the job words and the flag
+// rows.
+inline size_t table_budget_bytes(int n) {
+  const size_t fixed = (size_t)((n + 31) / 32) * kBlock * 4 + alpha_bytes(n) + 32;
+  const size_t per_wg = 80 * 1024;
+  const size_t rest = fixed + 16 * 1024 <= per_wg ? per_wg - fixed : 16 * 1024;
+  return rest * sizeof(Rec) / (sizeof(Rec) + sizeof(uint32_t));
+}
+
 __host__ __device__ inline size_t lds_bytes(int n, int mp, int npad, int ppc,
                                             bool wide, bool bytes = false) {
   size_t b = (size_t)ppc * npad * sizeof(Rec);

@@ -68,30 +68,40 @@ def test_mixed_batch_matches_oracle_and_single_launches(fsp, orc):
 
 
 def test_forms_in_one_launch(fsp, orc):
-    """Packed, 32-bit, 64-bit-register and job-mask segments in one launch
-    (the same 20-job shape both packed and, with large times, 32-bit), with
-    ragged tails of both tile sizes: every node equals the oracle, and the
-    batch reports the form each segment took."""
+    """Packed, 32-bit, 64-bit-register, job-mask and (asked for) bytes
+    segments in one launch (the same 20-job shape both packed and, with large
+    times, 32-bit; a 200-job instance loaded for the job-mask walk keeps it),
+    with ragged tails of both tile sizes: every node equals the oracle, and
+    the batch reports the form each segment took."""
     rng = np.random.default_rng(11)
     big = rng.integers(1500, 3000, size=(20, 10)).astype(np.int32)  # total > 32767
     cases = [(I.instance(20, 10, 3501), 1537), (big, 999), (I.instance(20, 20, 3502), 513),
              (I.instance(50, 10, 3503), 700), (I.instance(100, 5, 3504), 900),
-             (I.instance(20, 5, 3505), 511)]
+             (I.instance(20, 5, 3505), 511), (I.instance(200, 10, 3506), 650)]
     items, host = [], []
     for i, (p, cnt) in enumerate(cases):
         n = p.shape[0]
         pool = I.random_pool(n, cnt, 0, n, 3600 + i)
-        items.append((fsp.Instance(p), torch.from_numpy(pool).cuda(), None))
+        inst = fsp.Instance(p, job_masks=(i == 6))
+        items.append((inst, torch.from_numpy(pool).cuda(), None))
         host.append((p, pool))
     b = fsp.Batch(items)
     paths, bpc = b.paths()
     say("paths", paths, "blocks per CU", bpc)
-    assert paths == ["packed", "register", "packed", "register64", "masks", "packed"]
+    assert paths == ["packed", "register", "packed", "register64", "masks", "packed", "masks"]
     outs = b.launch()
     torch.cuda.synchronize()
     for out, (p, pool) in zip(outs, host):
         assert np.array_equal(out.cpu().numpy(), orc.bound_pool(p, pool, nthreads=8))
     b.close()
+    bb = fsp.Batch(items, bytes_walk=True)
+    assert bb.paths()[0] == ["packed", "register", "packed", "register64", "bytes", "packed",
+                             "masks"]
+    outs = bb.launch()
+    torch.cuda.synchronize()
+    for out, (p, pool) in zip(outs, host):
+        assert np.array_equal(out.cpu().numpy(), orc.bound_pool(p, pool, nthreads=8))
+    bb.close()
     one = fsp.Batch(items, packed=False)
     assert one.paths()[0][0] == "register" and one.paths()[0][2] == "register"
     outs1 = one.launch()
