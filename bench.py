@@ -572,7 +572,7 @@ def main() -> int:
                            "2.4 GHz" if packed else
                            "32-bit vector integer ops: 256 CUs x 64 lanes x 2.4 GHz"),
             "traffic": measured_traffic(),
-            "kernel": {"packed": f"bound_kernel_p16<{m}> (two nodes per lane, 16-bit)",
+            "kernel": {"packed": f"bound_kernel_p16<{m}, false> (two nodes per lane, 16-bit)",
                        "register": f"bound_kernel<{m}> (one node per lane)",
                        "masks": f"bound_kernel<{m}> (job masks)",
                        "bytes": f"bound_kernel<{m}> (flag bytes in LDS)"}[inst.bound_path],

@@ -107,8 +107,8 @@ __device__ __forceinline__ void run_tile_p16(const BatchSeg &S, char *smem, int6
     stage_p16_rows(I, L);
     __syncthreads();
   }
-  bound_nodes_p16<M>(I, L, S.nodes, S.stride, S.aligned != 0,
-                     (t - S.tile_begin) * 2 * kBlock, S.count, S.lb);
+  bound_nodes_p16<M, false>(I, L, S.nodes, S.stride, S.aligned != 0,
+                            (t - S.tile_begin) * 2 * kBlock, S.count, S.lb);
 }
 
 template <int M, int KIND>

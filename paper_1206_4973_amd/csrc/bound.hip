@@ -104,8 +104,9 @@ __global__ __launch_bounds__(kBlock, FORM == kFormBytes ? 2 : 4) void bound_kern
 
 // Two nodes per lane in packed 16-bit arithmetic (n <= 32, total work <=
 // 32767): tiles of 2 * kBlock nodes.  Both nodes are set up together in
-// packed form, so the kernel fits four workgroups per CU (128 VGPRs).
-template <int M>
+// packed form, so the kernel fits four workgroups per CU (128 VGPRs).  PF:
+// the launch carries a pre-filter, a per-depth bound choice or depth counts.
+template <int M, bool PF>
 __global__ __launch_bounds__(kBlock, 4) void bound_kernel_p16(const BoundParams a) {
   extern __shared__ __align__(16) char smem[];
   int64_t count = a.count, ntiles = a.ntiles;
@@ -118,16 +119,17 @@ __global__ __launch_bounds__(kBlock, 4) void bound_kernel_p16(const BoundParams 
   stage_p16_rows(a.I, L);
   __syncthreads();
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-    bound_nodes_p16<M>(a.I, L, a.nodes, a.stride, a.aligned != 0,
-                       tile * 2 * kBlock, count, a.lb, a.pf);
+    bound_nodes_p16<M, PF>(a.I, L, a.nodes, a.stride, a.aligned != 0,
+                           tile * 2 * kBlock, count, a.lb, a.pf);
 }
 
 using BoundFn = void (*)(BoundParams);
 
 template <int... Ks>
-BoundFn p16_kernel(int m, std::integer_sequence<int, Ks...>) {
-  constexpr BoundFn table[] = {bound_kernel_p16<Ks + 2>...};
-  return table[m - 2];
+BoundFn p16_kernel(int m, bool pf, std::integer_sequence<int, Ks...>) {
+  constexpr BoundFn plain[] = {bound_kernel_p16<Ks + 2, false>...};
+  constexpr BoundFn filtered[] = {bound_kernel_p16<Ks + 2, true>...};
+  return pf ? filtered[m - 2] : plain[m - 2];
 }
 
 template <int M>
@@ -283,7 +285,8 @@ int launch_bound(const fsp_instance *inst, const uint8_t *nodes, int stride,
   BoundFn fn;
   if (p16) {
     fn = inst->m >= 2 && inst->m <= kMaxMachines
-             ? p16_kernel(inst->m, std::make_integer_sequence<int, kMaxMachines - 1>())
+             ? p16_kernel(inst->m, pf.ub || pf.lb1_only || pf.lb1_depths || pf.depth_stats,
+                          std::make_integer_sequence<int, kMaxMachines - 1>())
              : nullptr;
   } else {
     fn = kernel_for(inst->m, form, a.I.nchunks > 1);

@@ -1243,8 +1243,10 @@ __device__ __forceinline__ void node_state_p16(
 // halves) and base + 256 + tid (high halves), writing lb_out[idx] for
 // idx < count.  n <= 32 and the table is whole in LDS (I.rec is the packed
 // table, L.s_p holds the packed rows of p).  Every lane of the workgroup must
-// call it.
-template <int M>
+// call it.  PF = false compiles the pre-filter, the per-depth choice and the
+// depth counts out (pf is then ignored): their state, live across the walk,
+// costs this form spills at 20 machines.
+template <int M, bool PF>
 __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView &L,
                                                 const uint8_t *nodes, int stride,
                                                 bool aligned, int64_t base,
@@ -1262,7 +1264,7 @@ __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView 
   bool skip = false, onlyA = false, onlyB = false;
   uint32_t LB1 = 0;
   const int dA = I.n - __builtin_popcount(UA), dB = I.n - __builtin_popcount(UB);
-  if (pf.lb1_only || pf.ub || pf.lb1_depths) {
+  if (PF && (pf.lb1_only || pf.ub || pf.lb1_depths)) {
 #pragma unroll
     for (int k = 0; k < M; ++k) LB1 = pk_max(LB1, pk_add(T[k], Q[k]));
     onlyA = pf.lb1_only || (la && !badA && lb1_at_depth(pf.lb1_depths, dA));
@@ -1286,7 +1288,7 @@ __device__ __forceinline__ void bound_nodes_p16(const InstView I, const LdsView 
       AL[j] = ((UA >> j) & 1u) | (((UB >> j) & 1u) << 16);
     LB = pair_sweep_p16<M>(L.s_rec, I.job16, I.npad, AL, R, T, Q);
   }
-  if (pf.depth_stats && pf.ub) {
+  if (PF && pf.depth_stats && pf.ub) {
     const int ub = *pf.ub;
     const bool ca = la && !badA && UA != 0u, cb = lbv && !badB && UB != 0u;
     count_depth_stats(pf.depth_stats, ca, dA, ca && eliminated((int)(LB1 & 0xffffu), ub, pf.rule),
