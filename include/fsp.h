@@ -81,7 +81,7 @@ int fsp_load_instance(const int32_t *p_host, int32_t n, int32_t m,
  * fsp_instance_path) on the one-node-per-lane 32-bit register form; the
  * bounds are identical, only the arithmetic differs (for comparing the two
  * forms on one pool).  FSP_LOAD_JOB_MASKS puts an instance of more than 64
- * jobs on the job-mask walk instead of the LDS bytes walk (same bounds; the
+ * jobs on the job-mask walk instead of the bytes walk (same bounds; the
  * job-mask walk needs per-wave scratch, see fsp_bound_pool_noalloc). */
 #define FSP_LOAD_ONE_NODE_PER_LANE 1
 #define FSP_LOAD_JOB_MASKS 2
@@ -108,7 +108,7 @@ int fsp_instance_info(const fsp_instance *inst, int32_t *n, int32_t *m,
  *                        in packed 16-bit arithmetic (every value of the bound
  *                        then fits in 16 bits);
  *   FSP_PATH_BYTES       n > 64: one node per lane, each lane's unscheduled
- *                        flags as bytes in LDS;
+ *                        flags as bytes in LDS, the table by scalar loads;
  *   FSP_PATH_MASKS       n > 64 when loaded with FSP_LOAD_JOB_MASKS: one node
  *                        per lane, per-wave job masks read by scalar loads;
  *   FSP_PATH_REGISTER64  32 < n <= 64: one node per lane, the unscheduled set

@@ -135,10 +135,10 @@ __device__ __forceinline__ void run_any(const BatchSeg &S, int form, char *smem,
 // The packed segments run in a kernel of their own: the packed walk pins
 // 48 VGPRs (its multipliers and load buffers), which in one kernel with the
 // other forms cost those forms spills and a fifth of their speed.  So do the
-// bytes segments (64 pinned VGPRs, two workgroups per CU for their LDS).
+// bytes segments (48 pinned SGPRs).
 // KIND: 0 the one-node register and mask forms, 1 packed, 2 bytes.
 template <int KIND>
-__global__ __launch_bounds__(kBlock, KIND == 2 ? 2 : 4) void batch_kernel(
+__global__ __launch_bounds__(kBlock, 4) void batch_kernel(
     const BatchSeg *__restrict__ segs, int nsegs, int64_t total_tiles,
     unsigned long long *counter, char *slots, int64_t tile_bytes) {
   extern __shared__ __align__(16) char smem[];

@@ -21,15 +21,16 @@
 // whatever the order).  Every lane walks the same table position in
 // lock-step; the record {x = 256 (b - a), y = 256 (lag + b) + job} is a
 // wave-uniform LDS broadcast, and a lane whose node has the position's job
-// already scheduled must keep its z.  Four forms of that choice:
+// already scheduled must keep its z.  Five forms of that choice:
 //   register (n <= 32): the node's unscheduled set U is one register, and
 //       alpha = bit job of U;  z = max(z + alpha*x, alpha*y)
 //     (v_bfe_u32, v_mad_i32_i24, v_mul_u32_u24, v_max_i32); alpha = 0 gives
 //     max(z, 0) = z.
 //   packed (n <= 32 and total work <= 32767): the same step for two nodes
-//     per lane in 16-bit halves, both sets interleaved in one 64-bit word
-//     (v_lshrrev_b64, v_and_b32, v_pk_mad_u16, v_pk_mul_lo_u16,
-//     v_pk_max_i16: five instructions for two nodes); see bound_tile.hpp.
+//     per lane in 16-bit halves, the per-job multipliers of both nodes in
+//     registers picked by the VGPR index mode (v_pk_mad_u16,
+//     v_pk_mul_lo_u16, v_pk_max_i16: three instructions for two nodes); see
+//     bound_tile.hpp.
 //   register64 (33..64 jobs): U in a 64-bit register pair, alpha taken with
 //     v_lshrrev_b64 by the job in y's low bits and v_and_b32.
 //   masks (n > 64): each wave first writes, once per tile, the 64-bit mask of
@@ -39,19 +40,28 @@
 //       t = max(z + x, y);  z = mask[job] ? t : z
 //     (v_add_u32, v_max_i32, v_cndmask_b32 on the SGPR pair).  Up to 64 jobs
 //     the register forms are faster: the scalar loads miss the scalar cache
-//     more than the bit extract they save costs.
-// z is kept scaled by 256 with the job id riding in the low byte of y (so no
-// extra instruction is needed to split the record): for integers the high
-// part of max(256u + e, 256v + j) with 0 <= e, j < 256 is max(u, v), so
-// z = Z >> 8 exactly.
+//     more than the bit extract they save costs.  Taken by load flag.
+//   bytes (n > 64, the default there): each lane keeps its unscheduled flags
+//     as bytes in LDS ([job][lane] rows of its wave); the records, one word
+//     x | y << 16 in plain units (b - a and lag + b fit in 16 bits under the
+//     instance limits), and the job ids come from scalar loads of global
+//     tables, so LDS returns only the flag bytes:
+//       z = max(z + alpha*x, alpha*y)
+//     (v_lshl_add_u32 for the flag address, v_mad_i32_i16 and v_mad_u32_u16
+//     on the record's halves, v_max_i32).
+// In the register and mask forms z is kept scaled by 256 with the job id
+// riding in the low byte of y (so no extra instruction is needed to split
+// the record): for integers the high part of max(256u + e, 256v + j) with
+// 0 <= e, j < 256 is max(u, v), so z = Z >> 8 exactly.
 //
 // Data layout: in LDS (per workgroup) the pair records (whole table, or chunk
-// by chunk when it does not fit), the padded p matrix for the prefix
-// recurrence (packed machine pairs in the packed form) and, for n > 32, the
-// unscheduled-job words of every lane; in global memory the mask offset of
-// every table position (read by scalar loads) and, for n > 64, the scratch
-// of job-mask slots, one per wave of every tile, each written once per
-// launch.
+// by chunk when it does not fit; none in the bytes form), the padded p
+// matrix for the prefix recurrence (packed machine pairs in the packed form)
+// and, for n > 32, the unscheduled-job words of every lane (the flag bytes in
+// the bytes form); in global memory the tables read by scalar loads (mask
+// offsets; the bytes form's record words and job bytes) and, for the job-mask
+// walk, the scratch of job-mask slots, one per wave of every tile, each
+// written once per launch.
 #include <algorithm>
 #include <mutex>
 #include <thread>
@@ -77,10 +87,8 @@ struct BoundParams {
   Prefilter pf;
 };
 
-// The bytes walk's LDS (flag rows) leaves room for two workgroups per compute
-// unit, so its kernels may use twice the registers of the other forms.
 template <int M, int FORM, bool CHUNKED>
-__global__ __launch_bounds__(kBlock, FORM == kFormBytes ? 2 : 4) void bound_kernel(
+__global__ __launch_bounds__(kBlock, 4) void bound_kernel(
     const BoundParams a) {
   constexpr bool WIDE = FORM == kFormMasks || FORM == kFormBytes;
   extern __shared__ __align__(16) char smem[];
@@ -189,6 +197,9 @@ InstView inst_view(const fsp_instance *inst, size_t table_budget) {
   v.joff = inst->d_joff;
   v.xy16 = inst->d_xy16;
   v.job16 = inst->d_job16;
+  v.bxy = inst->d_bxy;
+  v.bjob = inst->d_bjob;
+  v.npad8 = inst->npad8;
   v.slot_bytes = uses_job_masks(inst->n) ? mask_slot_bytes(inst->n) : 0;
   v.n = inst->n;
   v.mp = inst->mp;

@@ -18,7 +18,10 @@ struct InstView {
   const uint32_t *__restrict__ joff; // [P][npad] 8 * job id per position
   const uint32_t *__restrict__ xy16;  // packed form: [P][npad] x | y << 16
   const uint32_t *__restrict__ job16; // packed form: [P][npad] job id
+  const uint32_t *__restrict__ bxy;   // bytes form: [P][npad8] x | y << 16
+  const uint8_t *__restrict__ bjob;   // bytes form: [P][npad8] job id
   int n, mp, npad, P;
+  int npad8;       // bytes form: n rounded up to 8
   int ppc;         // pairs per LDS chunk
   int nchunks;     // chunks of the pair table
   int slot_bytes;  // bytes of one wave's mask slot (mask_slot_bytes(n))
@@ -26,14 +29,13 @@ struct InstView {
 
 // LDS of one workgroup for one instance: the table chunk, then (n <= 32)
 // the p matrix for the prefix recurrence, or (n > 32) the unscheduled-job
-// mask of every lane as ceil(n/32) words laid out [word][lane], and in the
-// bytes form the same flags as bytes, [wave][job 0 .. n][lane].
+// mask of every lane as ceil(n/32) words laid out [word][lane]; in the bytes
+// form only the same flags as bytes, [wave][job 0 .. n][lane].
 struct LdsView {
   char *s_rec;
   int32_t *s_p;       // narrow only
   uint32_t *s_words;  // wide only
   uint8_t *s_alpha;   // bytes form only
-  uint32_t *s_aoff;   // bytes form only: flag offsets of the chunk's positions
 };
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -63,31 +65,22 @@ __host__ __device__ constexpr int pair_index(int k, int l) {
 // up to 16 bytes, so that a row is read with 16-byte loads.
 __host__ __device__ constexpr int p16_row_words(int mp) { return (mp / 2 + 3) & ~3; }
 
-// Bytes of the bytes form's flag rows: one byte per lane for jobs 0 .. n,
-// and of its staged flag offsets: one word per position of a chunk and two
-// spare groups of four (the walk requests up to two groups ahead).
+// Bytes of the bytes form's flag rows: one byte per lane for jobs 0 .. n.
 __host__ __device__ inline size_t alpha_bytes(int n) { return (size_t)kBlock * (n + 1); }
-__host__ __device__ inline size_t aoff_bytes(int ppc, int npad) {
-  return ((size_t)ppc * npad + 8) * sizeof(uint32_t);
-}
 
-// The bytes walk's budget for records (inst_view's table budget): the chunk
-// (8 bytes of record and 4 of flag offset per position) gets what is left of
-// 80 KB (two workgroups per compute unit) next to the job words and the flag
-// rows.
-inline size_t table_budget_bytes(int n) {
-  const size_t fixed = (size_t)((n + 31) / 32) * kBlock * 4 + alpha_bytes(n) + 32;
-  const size_t per_wg = 80 * 1024;
-  const size_t rest = fixed + 16 * 1024 <= per_wg ? per_wg - fixed : 16 * 1024;
-  return rest * sizeof(Rec) / (sizeof(Rec) + sizeof(uint32_t));
-}
+// The bytes walk's table budget (inst_view's): its records and flag offsets
+// are read from global memory, so the whole table is one chunk and none of
+// it is staged in LDS.
+inline size_t table_budget_bytes(int) { return (size_t)1 << 40; }
 
 __host__ __device__ inline size_t lds_bytes(int n, int mp, int npad, int ppc,
                                             bool wide, bool bytes = false) {
-  size_t b = (size_t)ppc * npad * sizeof(Rec);
-  if (wide)
-    b += (size_t)((n + 31) / 32) * kBlock * 4 +
-         (bytes ? alpha_bytes(n) + aoff_bytes(ppc, npad) : 0);
+  // the bytes walk stages no records
+  size_t b = bytes ? 0 : (size_t)ppc * npad * sizeof(Rec);
+  if (bytes)
+    b += alpha_bytes(n);  // the flag bytes stand in for the job words
+  else if (wide)
+    b += (size_t)((n + 31) / 32) * kBlock * 4;
   else {  // 32-bit rows of p, or the packed rows plus a row of zeros
     const int rows32 = n * mp, rows16 = (n + 1) * p16_row_words(mp);
     b += (size_t)(rows32 > rows16 ? rows32 : rows16) * 4;
@@ -98,14 +91,11 @@ __host__ __device__ inline size_t lds_bytes(int n, int mp, int npad, int ppc,
 template <bool WIDE, bool BYTES = false>
 __device__ __forceinline__ LdsView carve(char *smem, const InstView I) {
   LdsView L;
-  L.s_rec = smem;
-  char *after = smem + (size_t)I.ppc * I.npad * sizeof(Rec);
-  L.s_aoff = BYTES ? reinterpret_cast<uint32_t *>(after) : nullptr;
-  if (BYTES) after += aoff_bytes(I.ppc, I.npad);
+  L.s_rec = BYTES ? nullptr : smem;
+  char *after = BYTES ? smem : smem + (size_t)I.ppc * I.npad * sizeof(Rec);
   L.s_p = WIDE ? nullptr : reinterpret_cast<int32_t *>(after);
-  L.s_words = WIDE ? reinterpret_cast<uint32_t *>(after) : nullptr;
-  L.s_alpha = BYTES ? reinterpret_cast<uint8_t *>(after + (size_t)((I.n + 31) / 32) * kBlock * 4)
-                    : nullptr;
+  L.s_words = WIDE && !BYTES ? reinterpret_cast<uint32_t *>(after) : nullptr;
+  L.s_alpha = BYTES ? reinterpret_cast<uint8_t *>(after) : nullptr;
   return L;
 }
 
@@ -119,18 +109,6 @@ __device__ __forceinline__ void stage_chunk(const InstView I, char *s_rec,
   for (int i = threadIdx.x; i < total; i += kBlock) dst[i] = src[i];
 }
 
-// The bytes form also stages the chunk's flag offsets: 8 * (the mask offset
-// 8 * job) = job * 64, the byte offset of the job's row of flags; the two
-// spare groups name row n (all zero).
-__device__ __forceinline__ void stage_aoff(const InstView I, uint32_t *s_aoff, int chunk) {
-  const int lo = chunk * I.ppc;
-  const int hi = min(I.P, lo + I.ppc);
-  const int total = (hi - lo) * I.npad;
-  const uint32_t *src = I.joff + (size_t)lo * I.npad;
-  for (int i = threadIdx.x; i < total + 8; i += kBlock)
-    s_aoff[i] = i < total ? src[i] * 8u : (uint32_t)I.n * 64u;
-}
-
 // Stage what stays in LDS for the whole instance: p, and the whole pair table
 // when it fits.  The caller synchronises the workgroup afterwards.
 template <bool WIDE, bool BYTES = false>
@@ -138,10 +116,7 @@ __device__ __forceinline__ void stage_instance(const InstView I,
                                                const LdsView &L) {
   if (!WIDE)
     for (int i = threadIdx.x; i < I.n * I.mp; i += kBlock) L.s_p[i] = I.p[i];
-  if (I.nchunks == 1) {
-    stage_chunk(I, L.s_rec, 0);
-    if (BYTES) stage_aoff(I, L.s_aoff, 0);
-  }
+  if (!BYTES && I.nchunks == 1) stage_chunk(I, L.s_rec, 0);
 }
 
 // Write the wave's job masks: entry j of the slot is the 64-bit set of lanes
@@ -331,194 +306,207 @@ __device__ __forceinline__ uint32_t lds_offset(const char *p) {
   return (uint32_t)(uintptr_t)((__attribute__((address_space(3))) const char *)p);
 }
 
-// ---- n > 32, bytes form: each lane keeps its node's unscheduled flags as
-//      bytes in LDS, laid out [job][lane] in its wave's rows (row n is all
-//      zero and is the one the padding positions name).  A position reads
-//      the lane's byte of its job at job * 64 + lane (the row offsets are
-//      staged in LDS next to the records): 64 consecutive bytes per wave, no
-//      bank conflict.  Then the register form's step: 4 vector instructions
-//      per position (address, v_mad_i32_i24, v_mul_u32_u24, v_max_i32) and
-//      one LDS byte load.  Every load of the walk is an LDS load, so they
-//      complete in order and the walk can run ahead: the records and flags
-//      of the next group of four positions and the offsets of the group
-//      after are requested before the current group is computed. ----
-__device__ __forceinline__ int step_f(uint32_t al, int x, int y, int Z) {
-  const int up = __mul24((int)al, x) + Z;
-  const int lo = (int)__umul24(al, (uint32_t)y);
-  return max(up, lo);
-}
-
-// One pair: npad records at rp_raw and npad flag offsets at op_raw (LDS);
-// the requests past the pair's end stay inside the staged chunk (the next
-// pair's entries, the spare offset groups, the offsets after the records).
-// The index of the next group passes through an empty asm statement every
-// iteration: otherwise the compiler proves that the next group's load is
-// the same as the current group's load one iteration later, and moves it
-// there, next to its use, which undoes the running ahead.
-__device__ __forceinline__ int walk1_b(const char *rp_raw, const char *op_raw,
-                                       const uint8_t *al, int npad, int Z) {
-  const int4 *rp = reinterpret_cast<const int4 *>(rp_raw);
-  const u32x4 *op = reinterpret_cast<const u32x4 *>(op_raw);
-  const u32x4 q = op[0];
-  u32x4 p1 = op[1];
-  int4 r0 = rp[0], r1 = rp[1];
-  uint32_t f0 = al[q.x], f1 = al[q.y], f2 = al[q.z], f3 = al[q.w];
-  for (int i = 0; i < npad / 4; ++i) {
-    int g = i + 1;
-    asm volatile("" : "+s"(g));
-    const int4 *rn = rp + 2 * g;
-    const u32x4 *on = op + g + 1;
-    const int4 n0 = rn[0], n1 = rn[1];
-    const uint32_t g0 = al[p1.x], g1 = al[p1.y], g2 = al[p1.z], g3 = al[p1.w];
-    const u32x4 p2 = on[0];
-    Z = step_f(f0, r0.x, r0.y, Z);
-    Z = step_f(f1, r0.z, r0.w, Z);
-    Z = step_f(f2, r1.x, r1.y, Z);
-    Z = step_f(f3, r1.z, r1.w, Z);
-    r0 = n0;
-    r1 = n1;
-    f0 = g0;
-    f1 = g1;
-    f2 = g2;
-    f3 = g3;
-    p1 = p2;
-  }
-  return Z;
-}
-
-// Two pairs walked together: two independent dependency chains per lane,
-// in one asm loop over groups of four positions.  Two register sets take
-// turns (X = v80..v111, Y = v112..v143; in each, records of pair A at +0 and
-// of pair B at +8, flags of A at +16 and of B at +20, and the flag offsets of
-// the other set's group, A at +24 and B at +28).  A half waits for its set's
-// loads, forms the other set's flag addresses from the offsets it holds,
-// requests the other set's flags, records and the offsets after them, then
-// computes its own group: the requests overlap 24 steps of arithmetic.  All
-// loads are LDS loads (they complete in order), and all are waited for
-// before the statement ends.  The requests past a pair's end (one group of
-// records, two of offsets) stay inside the staged chunk.
-#define FSP_B_STEP2(FA, XA, YA, FB, XB, YB)                \
-  "v_mad_i32_i24 %[tA], " FA ", " XA ", %[zA]\n\t"         \
-  "v_mul_u32_u24 %[uA], " FA ", " YA "\n\t"                \
-  "v_mad_i32_i24 %[tB], " FB ", " XB ", %[zB]\n\t"         \
-  "v_mul_u32_u24 %[uB], " FB ", " YB "\n\t"                \
-  "v_max_i32 %[zA], %[tA], %[uA]\n\t"                      \
+// ---- the bytes walk's loop: records and job ids by scalar loads ----
+//
+// The records (x | y << 16, one word per position) and job ids (one byte per
+// position) are read from the instance tables in global memory with scalar
+// loads: every wave of the launch walks the same tables, so they are served
+// by the scalar cache and the L2, and the arithmetic takes the record halves
+// as scalar operands (op_sel picks the half):
+//   t = z + al * x   (v_mad_i32_i16: x is signed)
+//   u = al * y       (v_mad_u32_u16)
+//   z = max(t, u)    (v_max_i32)
+// with the lane's flag al = 0 or 1 read from its LDS byte row of the job,
+// 64 * job bytes past its row 0 (v_lshl_add_u32 on the job id, which a
+// scalar bit-field extract takes from the job bytes).  LDS returns only the
+// lanes' flag bytes; a 16-byte record broadcast to a wave returns 1 KB
+// through the LDS, which bounded the rate when the records were staged there.
+// Groups of eight positions; two register sets take turns: records in
+// s[64:79] (set X) and s[80:95] (set Y), pair A at +0 and pair B at +8; flags
+// in v80..v95 (X) and v96..v111 (Y), A at +0 and B at +8; the job ids of a
+// set's next group in s[48:51] (for X) and s[52:55] (for Y), A at +0, B at
+// +2; s[56:63] hold the extracted ids.  A half waits for everything
+// requested (scalar loads complete out of order, so the wait is for all),
+// forms the other set's flag addresses from the job ids it holds, requests
+// those flags, the other set's records and the job ids two groups ahead,
+// then computes its own group.  The requests past a pair's end (one group of
+// records, two of job ids) stay inside the tables, which carry two spare
+// groups past the last pair; every request is waited for before the
+// statement ends.
+#define FSP_B8_STEP2(FA, RA, FB, RB)                                   \
+  "v_mad_i32_i16 %[tA], " FA ", " RA ", %[zA]\n\t"                     \
+  "v_mad_u32_u16 %[uA], " FA ", " RA ", 0 op_sel:[0,1,0,0]\n\t"        \
+  "v_mad_i32_i16 %[tB], " FB ", " RB ", %[zB]\n\t"                     \
+  "v_mad_u32_u16 %[uB], " FB ", " RB ", 0 op_sel:[0,1,0,0]\n\t"        \
+  "v_max_i32 %[zA], %[tA], %[uA]\n\t"                                  \
   "v_max_i32 %[zB], %[tB], %[uB]\n\t"
+#define FSP_B8_STEP1(FA, RA)                                           \
+  "v_mad_i32_i16 %[tA], " FA ", " RA ", %[zA]\n\t"                     \
+  "v_mad_u32_u16 %[uA], " FA ", " RA ", 0 op_sel:[0,1,0,0]\n\t"        \
+  "v_max_i32 %[zA], %[tA], %[uA]\n\t"
+// the eight job ids of two words into s56..s63
+#define FSP_B8_IDS(W0, W1)                                             \
+  "s_bfe_u32 s56, " W0 ", 0x80000\n\t"                                 \
+  "s_bfe_u32 s57, " W0 ", 0x80008\n\t"                                 \
+  "s_bfe_u32 s58, " W0 ", 0x80010\n\t"                                 \
+  "s_lshr_b32 s59, " W0 ", 24\n\t"                                     \
+  "s_bfe_u32 s60, " W1 ", 0x80000\n\t"                                 \
+  "s_bfe_u32 s61, " W1 ", 0x80008\n\t"                                 \
+  "s_bfe_u32 s62, " W1 ", 0x80010\n\t"                                 \
+  "s_lshr_b32 s63, " W1 ", 24\n\t"
+// flag address (lane's row-0 byte + 64 * job) and the byte load, in place
+#define FSP_B8_FLAG(V, S)                                              \
+  "v_lshl_add_u32 " V ", " S ", 6, %[lane]\n\t"                        \
+  "ds_read_u8 " V ", " V "\n\t"
+#define FSP_B8_FLAGS(V0, V1, V2, V3, V4, V5, V6, V7)                   \
+  FSP_B8_FLAG(V0, "s56") FSP_B8_FLAG(V1, "s57")                        \
+  FSP_B8_FLAG(V2, "s58") FSP_B8_FLAG(V3, "s59")                        \
+  FSP_B8_FLAG(V4, "s60") FSP_B8_FLAG(V5, "s61")                        \
+  FSP_B8_FLAG(V6, "s62") FSP_B8_FLAG(V7, "s63")
 
-__device__ __forceinline__ void walk2_b(const char *ra_raw, const char *rb_raw,
-                                        const char *oa_raw, const char *ob_raw,
-                                        const uint8_t *al, int npad, int &ZA, int &ZB) {
-  uint32_t ra = lds_offset(ra_raw), rb = lds_offset(rb_raw);
-  uint32_t oa = lds_offset(oa_raw), ob = lds_offset(ob_raw);
-  const uint32_t lane = lds_offset(reinterpret_cast<const char *>(al));
+__device__ __forceinline__ void walk2_b8(uint64_t ra, uint64_t rb, uint64_t ja, uint64_t jb,
+                                         uint32_t lane, int npad8, int &ZA, int &ZB) {
   int tA, uA, tB, uB;
-  uint32_t cnt = (uint32_t)(npad / 4);  // groups
+  uint32_t cnt = (uint32_t)(npad8 / 8);  // groups
+  uint32_t ro = 0, jo = 0;
   asm volatile(
-      "ds_read_b128 v[104:107], %[oa] offset:0\n\t"
-      "ds_read_b128 v[108:111], %[ob] offset:0\n\t"
+      // group 0 into set X, the job ids of group 1 for set Y
+      "s_load_dwordx2 s[48:49], %[ja], %[jo]\n\t"
+      "s_load_dwordx2 s[50:51], %[jb], %[jo]\n\t"
+      "s_load_dwordx8 s[64:71], %[ra], %[ro]\n\t"
+      "s_load_dwordx8 s[72:79], %[rb], %[ro]\n\t"
+      "s_add_u32 %[jo], %[jo], 8\n\t"
+      "s_load_dwordx2 s[52:53], %[ja], %[jo]\n\t"
+      "s_load_dwordx2 s[54:55], %[jb], %[jo]\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
-      "v_add_u32 v96, v104, %[lane]\n\t"
-      "v_add_u32 v97, v105, %[lane]\n\t"
-      "v_add_u32 v98, v106, %[lane]\n\t"
-      "v_add_u32 v99, v107, %[lane]\n\t"
-      "v_add_u32 v100, v108, %[lane]\n\t"
-      "v_add_u32 v101, v109, %[lane]\n\t"
-      "v_add_u32 v102, v110, %[lane]\n\t"
-      "v_add_u32 v103, v111, %[lane]\n\t"
-      "ds_read_u8 v96, v96\n\t"
-      "ds_read_u8 v97, v97\n\t"
-      "ds_read_u8 v98, v98\n\t"
-      "ds_read_u8 v99, v99\n\t"
-      "ds_read_u8 v100, v100\n\t"
-      "ds_read_u8 v101, v101\n\t"
-      "ds_read_u8 v102, v102\n\t"
-      "ds_read_u8 v103, v103\n\t"
-      "ds_read_b128 v[80:83], %[ra] offset:0\n\t"
-      "ds_read_b128 v[84:87], %[ra] offset:16\n\t"
-      "ds_read_b128 v[88:91], %[rb] offset:0\n\t"
-      "ds_read_b128 v[92:95], %[rb] offset:16\n\t"
-      "ds_read_b128 v[104:107], %[oa] offset:16\n\t"
-      "ds_read_b128 v[108:111], %[ob] offset:16\n"
+      FSP_B8_IDS("s48", "s49")
+      FSP_B8_FLAGS("v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87")
+      FSP_B8_IDS("s50", "s51")
+      FSP_B8_FLAGS("v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95")
       "1:\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
-      "v_add_u32 v128, v104, %[lane]\n\t"
-      "v_add_u32 v129, v105, %[lane]\n\t"
-      "v_add_u32 v130, v106, %[lane]\n\t"
-      "v_add_u32 v131, v107, %[lane]\n\t"
-      "v_add_u32 v132, v108, %[lane]\n\t"
-      "v_add_u32 v133, v109, %[lane]\n\t"
-      "v_add_u32 v134, v110, %[lane]\n\t"
-      "v_add_u32 v135, v111, %[lane]\n\t"
-      "ds_read_u8 v128, v128\n\t"
-      "ds_read_u8 v129, v129\n\t"
-      "ds_read_u8 v130, v130\n\t"
-      "ds_read_u8 v131, v131\n\t"
-      "ds_read_u8 v132, v132\n\t"
-      "ds_read_u8 v133, v133\n\t"
-      "ds_read_u8 v134, v134\n\t"
-      "ds_read_u8 v135, v135\n\t"
-      "ds_read_b128 v[112:115], %[ra] offset:32\n\t"
-      "ds_read_b128 v[116:119], %[ra] offset:48\n\t"
-      "ds_read_b128 v[120:123], %[rb] offset:32\n\t"
-      "ds_read_b128 v[124:127], %[rb] offset:48\n\t"
-      "ds_read_b128 v[136:139], %[oa] offset:32\n\t"
-      "ds_read_b128 v[140:143], %[ob] offset:32\n\t"
-      FSP_B_STEP2("v96", "v80", "v81", "v100", "v88", "v89")
-      FSP_B_STEP2("v97", "v82", "v83", "v101", "v90", "v91")
-      FSP_B_STEP2("v98", "v84", "v85", "v102", "v92", "v93")
-      FSP_B_STEP2("v99", "v86", "v87", "v103", "v94", "v95")
+      FSP_B8_IDS("s52", "s53")
+      FSP_B8_FLAGS("v96", "v97", "v98", "v99", "v100", "v101", "v102", "v103")
+      FSP_B8_IDS("s54", "s55")
+      FSP_B8_FLAGS("v104", "v105", "v106", "v107", "v108", "v109", "v110", "v111")
+      "s_add_u32 %[ro], %[ro], 32\n\t"
+      "s_add_u32 %[jo], %[jo], 8\n\t"
+      "s_load_dwordx8 s[80:87], %[ra], %[ro]\n\t"
+      "s_load_dwordx8 s[88:95], %[rb], %[ro]\n\t"
+      "s_load_dwordx2 s[48:49], %[ja], %[jo]\n\t"
+      "s_load_dwordx2 s[50:51], %[jb], %[jo]\n\t"
+      FSP_B8_STEP2("v80", "s64", "v88", "s72")
+      FSP_B8_STEP2("v81", "s65", "v89", "s73")
+      FSP_B8_STEP2("v82", "s66", "v90", "s74")
+      FSP_B8_STEP2("v83", "s67", "v91", "s75")
+      FSP_B8_STEP2("v84", "s68", "v92", "s76")
+      FSP_B8_STEP2("v85", "s69", "v93", "s77")
+      FSP_B8_STEP2("v86", "s70", "v94", "s78")
+      FSP_B8_STEP2("v87", "s71", "v95", "s79")
       "s_sub_u32 %[cnt], %[cnt], 1\n\t"
       "s_cmp_eq_u32 %[cnt], 0\n\t"
       "s_cbranch_scc1 2f\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
-      "v_add_u32 v96, v136, %[lane]\n\t"
-      "v_add_u32 v97, v137, %[lane]\n\t"
-      "v_add_u32 v98, v138, %[lane]\n\t"
-      "v_add_u32 v99, v139, %[lane]\n\t"
-      "v_add_u32 v100, v140, %[lane]\n\t"
-      "v_add_u32 v101, v141, %[lane]\n\t"
-      "v_add_u32 v102, v142, %[lane]\n\t"
-      "v_add_u32 v103, v143, %[lane]\n\t"
-      "ds_read_u8 v96, v96\n\t"
-      "ds_read_u8 v97, v97\n\t"
-      "ds_read_u8 v98, v98\n\t"
-      "ds_read_u8 v99, v99\n\t"
-      "ds_read_u8 v100, v100\n\t"
-      "ds_read_u8 v101, v101\n\t"
-      "ds_read_u8 v102, v102\n\t"
-      "ds_read_u8 v103, v103\n\t"
-      "ds_read_b128 v[80:83], %[ra] offset:64\n\t"
-      "ds_read_b128 v[84:87], %[ra] offset:80\n\t"
-      "ds_read_b128 v[88:91], %[rb] offset:64\n\t"
-      "ds_read_b128 v[92:95], %[rb] offset:80\n\t"
-      "ds_read_b128 v[104:107], %[oa] offset:48\n\t"
-      "ds_read_b128 v[108:111], %[ob] offset:48\n\t"
-      FSP_B_STEP2("v128", "v112", "v113", "v132", "v120", "v121")
-      FSP_B_STEP2("v129", "v114", "v115", "v133", "v122", "v123")
-      FSP_B_STEP2("v130", "v116", "v117", "v134", "v124", "v125")
-      FSP_B_STEP2("v131", "v118", "v119", "v135", "v126", "v127")
-      "v_add_u32 %[ra], 64, %[ra]\n\t"
-      "v_add_u32 %[rb], 64, %[rb]\n\t"
-      "v_add_u32 %[oa], 32, %[oa]\n\t"
-      "v_add_u32 %[ob], 32, %[ob]\n\t"
+      FSP_B8_IDS("s48", "s49")
+      FSP_B8_FLAGS("v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87")
+      FSP_B8_IDS("s50", "s51")
+      FSP_B8_FLAGS("v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95")
+      "s_add_u32 %[ro], %[ro], 32\n\t"
+      "s_add_u32 %[jo], %[jo], 8\n\t"
+      "s_load_dwordx8 s[64:71], %[ra], %[ro]\n\t"
+      "s_load_dwordx8 s[72:79], %[rb], %[ro]\n\t"
+      "s_load_dwordx2 s[52:53], %[ja], %[jo]\n\t"
+      "s_load_dwordx2 s[54:55], %[jb], %[jo]\n\t"
+      FSP_B8_STEP2("v96", "s80", "v104", "s88")
+      FSP_B8_STEP2("v97", "s81", "v105", "s89")
+      FSP_B8_STEP2("v98", "s82", "v106", "s90")
+      FSP_B8_STEP2("v99", "s83", "v107", "s91")
+      FSP_B8_STEP2("v100", "s84", "v108", "s92")
+      FSP_B8_STEP2("v101", "s85", "v109", "s93")
+      FSP_B8_STEP2("v102", "s86", "v110", "s94")
+      FSP_B8_STEP2("v103", "s87", "v111", "s95")
       "s_sub_u32 %[cnt], %[cnt], 1\n\t"
       "s_cmp_eq_u32 %[cnt], 0\n\t"
       "s_cbranch_scc0 1b\n"
       "2:\n\t"
       "s_waitcnt lgkmcnt(0)"
       : [zA] "+v"(ZA), [zB] "+v"(ZB), [tA] "=&v"(tA), [uA] "=&v"(uA), [tB] "=&v"(tB),
-        [uB] "=&v"(uB), [ra] "+v"(ra), [rb] "+v"(rb), [oa] "+v"(oa), [ob] "+v"(ob),
+        [uB] "=&v"(uB), [ro] "+s"(ro), [jo] "+s"(jo), [cnt] "+s"(cnt)
+      : [ra] "s"(ra), [rb] "s"(rb), [ja] "s"(ja), [jb] "s"(jb), [lane] "v"(lane)
+      : "v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87", "v88", "v89", "v90",
+        "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101",
+        "v102", "v103", "v104", "v105", "v106", "v107", "v108", "v109", "v110", "v111",
+        "s48", "s49", "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58",
+        "s59", "s60", "s61", "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69",
+        "s70", "s71", "s72", "s73", "s74", "s75", "s76", "s77", "s78", "s79", "s80",
+        "s81", "s82", "s83", "s84", "s85", "s86", "s87", "s88", "s89", "s90", "s91",
+        "s92", "s93", "s94", "s95", "scc", "memory");
+}
+
+// One pair, the same loop with pair A's registers only.
+__device__ __forceinline__ int walk1_b8(uint64_t ra, uint64_t ja, uint32_t lane, int npad8,
+                                        int Z) {
+  int tA, uA;
+  uint32_t cnt = (uint32_t)(npad8 / 8);
+  uint32_t ro = 0, jo = 0;
+  asm volatile(
+      "s_load_dwordx2 s[48:49], %[ja], %[jo]\n\t"
+      "s_load_dwordx8 s[64:71], %[ra], %[ro]\n\t"
+      "s_add_u32 %[jo], %[jo], 8\n\t"
+      "s_load_dwordx2 s[52:53], %[ja], %[jo]\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      FSP_B8_IDS("s48", "s49")
+      FSP_B8_FLAGS("v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87")
+      "1:\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      FSP_B8_IDS("s52", "s53")
+      FSP_B8_FLAGS("v96", "v97", "v98", "v99", "v100", "v101", "v102", "v103")
+      "s_add_u32 %[ro], %[ro], 32\n\t"
+      "s_add_u32 %[jo], %[jo], 8\n\t"
+      "s_load_dwordx8 s[80:87], %[ra], %[ro]\n\t"
+      "s_load_dwordx2 s[48:49], %[ja], %[jo]\n\t"
+      FSP_B8_STEP1("v80", "s64") FSP_B8_STEP1("v81", "s65")
+      FSP_B8_STEP1("v82", "s66") FSP_B8_STEP1("v83", "s67")
+      FSP_B8_STEP1("v84", "s68") FSP_B8_STEP1("v85", "s69")
+      FSP_B8_STEP1("v86", "s70") FSP_B8_STEP1("v87", "s71")
+      "s_sub_u32 %[cnt], %[cnt], 1\n\t"
+      "s_cmp_eq_u32 %[cnt], 0\n\t"
+      "s_cbranch_scc1 2f\n\t"
+      "s_waitcnt lgkmcnt(0)\n\t"
+      FSP_B8_IDS("s48", "s49")
+      FSP_B8_FLAGS("v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87")
+      "s_add_u32 %[ro], %[ro], 32\n\t"
+      "s_add_u32 %[jo], %[jo], 8\n\t"
+      "s_load_dwordx8 s[64:71], %[ra], %[ro]\n\t"
+      "s_load_dwordx2 s[52:53], %[ja], %[jo]\n\t"
+      FSP_B8_STEP1("v96", "s80") FSP_B8_STEP1("v97", "s81")
+      FSP_B8_STEP1("v98", "s82") FSP_B8_STEP1("v99", "s83")
+      FSP_B8_STEP1("v100", "s84") FSP_B8_STEP1("v101", "s85")
+      FSP_B8_STEP1("v102", "s86") FSP_B8_STEP1("v103", "s87")
+      "s_sub_u32 %[cnt], %[cnt], 1\n\t"
+      "s_cmp_eq_u32 %[cnt], 0\n\t"
+      "s_cbranch_scc0 1b\n"
+      "2:\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : [zA] "+v"(Z), [tA] "=&v"(tA), [uA] "=&v"(uA), [ro] "+s"(ro), [jo] "+s"(jo),
         [cnt] "+s"(cnt)
-      : [lane] "v"(lane)
-      : "v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87", "v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101", "v102", "v103", "v104", "v105", "v106", "v107", "v108", "v109", "v110", "v111", "v112", "v113", "v114", "v115", "v116", "v117", "v118", "v119", "v120", "v121", "v122", "v123", "v124", "v125", "v126", "v127", "v128", "v129", "v130", "v131", "v132", "v133", "v134", "v135", "v136", "v137", "v138", "v139", "v140", "v141", "v142", "v143", "scc", "memory");
+      : [ra] "s"(ra), [ja] "s"(ja), [lane] "v"(lane)
+      : "v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87", "v96", "v97", "v98",
+        "v99", "v100", "v101", "v102", "v103", "s48", "s49", "s52", "s53", "s56", "s57",
+        "s58", "s59", "s60", "s61", "s62", "s63", "s64", "s65", "s66", "s67", "s68",
+        "s69", "s70", "s71", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87",
+        "scc", "memory");
+  return Z;
 }
 
 template <int FORM>
 __device__ __forceinline__ int walk1_any(const char *rp, kchar *jp, kchar *ms,
-                                         const uint8_t *al, const char *so, int npad,
+                                         const uint8_t *al, int npad,
                                          uint64_t U, int Z) {
   if constexpr (FORM == kFormMasks) return walk1(rp, jp, ms, npad, Z);
-  else if constexpr (FORM == kFormBytes) return walk1_b(rp, so, al, npad, Z);
+  else if constexpr (FORM == kFormBytes)
+    return walk1_b8(reinterpret_cast<uint64_t>(rp), reinterpret_cast<uint64_t>(jp),
+                    lds_offset(reinterpret_cast<const char *>(al)), npad, Z);
   else if constexpr (FORM == kFormReg64) return walk1_u64(rp, npad, U, Z);
   else return walk1_u(rp, npad, (uint32_t)U, Z);
 }
@@ -526,17 +514,21 @@ __device__ __forceinline__ int walk1_any(const char *rp, kchar *jp, kchar *ms,
 // Every pair whose index lies in [lo, hi): pairs (k,l) and (k,l+1) are walked
 // together.  s_rec holds the records of pairs lo.. (LDS), jt the mask offsets
 // of pair lo.  Returns the max over those pairs of 256*(pair bound) + junk.
+// The bytes form walks the whole table from global memory (s_rec the record
+// words, jt the job bytes, npad = npad8) and returns the plain maximum.
 // The record and job pointers advance pair by pair (pair index order = table
 // order) so that no per-pair address stays live.
 template <int M, int FORM>
 __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
                                           int hi, int npad, uint64_t U,
                                           kchar *ms, const uint8_t *al,
-                                          const char *so, const int (&R256)[M],
+                                          const int (&R256)[M],
                                           const int (&T256)[M],
                                           const int (&Q256)[M], int LB256) {
-  int pb = npad * (int)sizeof(Rec);
-  int jb = npad * (int)sizeof(uint32_t);
+  // per pair: npad records and mask offsets, or (bytes form, npad = npad8)
+  // npad record words and job bytes
+  int pb = npad * (FORM == kFormBytes ? 4 : (int)sizeof(Rec));
+  int jb = npad * (FORM == kFormBytes ? 1 : (int)sizeof(uint32_t));
   // Opaque per call: otherwise every per-pair offset is loop-invariant in the
   // tile loop and gets hoisted, one scalar register per pair.
   asm volatile("" : "+s"(pb), "+s"(jb));
@@ -558,7 +550,11 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
             walk2(s_rec + off, s_rec + offb, jt + joff, jt + joffb, ms, npad,
                   ZA, ZB);
           else if constexpr (FORM == kFormBytes)
-            walk2_b(s_rec + off, s_rec + offb, so + joff, so + joffb, al, npad, ZA, ZB);
+            walk2_b8(reinterpret_cast<uint64_t>(s_rec + off),
+                     reinterpret_cast<uint64_t>(s_rec + offb),
+                     reinterpret_cast<uint64_t>(jt + joff),
+                     reinterpret_cast<uint64_t>(jt + joffb),
+                     lds_offset(reinterpret_cast<const char *>(al)), npad, ZA, ZB);
           else if constexpr (FORM == kFormReg64)
             walk2_u64(s_rec + off, s_rec + offb, npad, U, ZA, ZB);
           else
@@ -570,13 +566,13 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
           asm volatile("" : "+v"(LB256));
         } else {
           if (ina) {
-            int Z = walk1_any<FORM>(s_rec + off, jt + joff, ms, al, so + joff, npad, U,
+            int Z = walk1_any<FORM>(s_rec + off, jt + joff, ms, al, npad, U,
                                     R256[l] - R256[k]);
             LB256 = max(LB256, T256[k] + Q256[l] + Z);
             asm volatile("" : "+v"(LB256));
           }
           if (inb) {
-            int Z = walk1_any<FORM>(s_rec + offb, jt + joffb, ms, al, so + joffb, npad, U,
+            int Z = walk1_any<FORM>(s_rec + offb, jt + joffb, ms, al, npad, U,
                                     R256[l + 1] - R256[k]);
             LB256 = max(LB256, T256[k] + Q256[l + 1] + Z);
             asm volatile("" : "+v"(LB256));
@@ -586,7 +582,7 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
         joff += 2 * jb;
       } else {
         if (pa >= lo && pa < hi) {
-          int Z = walk1_any<FORM>(s_rec + off, jt + joff, ms, al, so + joff, npad, U,
+          int Z = walk1_any<FORM>(s_rec + off, jt + joff, ms, al, npad, U,
                                   R256[l] - R256[k]);
           LB256 = max(LB256, T256[k] + Q256[l] + Z);
           asm volatile("" : "+v"(LB256));
@@ -602,15 +598,18 @@ __device__ __forceinline__ int pair_sweep(const char *s_rec, kchar *jt, int lo,
 // Steps 1 and 2 for the node at idx (one per lane): decode the prefix (U,
 // the front F, the prefix column sums), then heads r[k], tails q[k] and
 // r[k] + S[k] (S = remaining work), each shifted left by SH into R, T, Q.
-// last = F[m-1], the makespan of the prefix.
-template <int M, bool WIDE, int SH, typename SetT = uint32_t>
+// last = F[m-1], the makespan of the prefix.  WIDE: the unscheduled set is
+// kept in LDS, as the lane's words ([word][lane], words_lane), or with FLAGS
+// as the lane's flag bytes (flags_lane[64 j] = job j unscheduled, for
+// j < n; the byte of row n is zero).
+template <int M, bool WIDE, int SH, typename SetT = uint32_t, bool FLAGS = false>
 __device__ __forceinline__ void node_state(const InstView I, const int32_t *s_p,
                                            uint32_t *words_lane,
                                            const uint8_t *nodes, int stride,
                                            bool aligned, int64_t idx, bool live,
                                            SetT &U, int &d, bool &bad,
                                            int &last, int (&R)[M], int (&T)[M],
-                                           int (&Q)[M]) {
+                                           int (&Q)[M], uint8_t *flags_lane = nullptr) {
   const int n = I.n, mp = I.mp;
   constexpr int kSetBits = 8 * (int)sizeof(SetT);
   const SetT full = n >= kSetBits ? ~SetT(0) : ((SetT(1) << n) - SetT(1));
@@ -619,7 +618,10 @@ __device__ __forceinline__ void node_state(const InstView I, const int32_t *s_p,
 #pragma unroll
   for (int k = 0; k < M; ++k) F[k] = Pk[k] = 0;
   U = full;
-  if constexpr (WIDE)
+  if constexpr (FLAGS) {
+    for (int j = 0; j < n; ++j) flags_lane[j * 64] = 1;
+    flags_lane[n * 64] = 0;
+  } else if constexpr (WIDE)
     for (int w = 0; w * 32 < n; ++w)
       words_lane[w * kBlock] = n - w * 32 >= 32 ? 0xffffffffu
                                                  : ((1u << (n - w * 32)) - 1u);
@@ -659,7 +661,10 @@ __device__ __forceinline__ void node_state(const InstView I, const int32_t *s_p,
             bad = true;
             continue;
           }
-          if constexpr (WIDE) {
+          if constexpr (FLAGS) {
+            if (flags_lane[j * 64] == 0) bad = true;
+            flags_lane[j * 64] = 0;
+          } else if constexpr (WIDE) {
             uint32_t *wp = words_lane + (j >> 5) * kBlock;
             const uint32_t v = *wp, bit = 1u << (j & 31);
             if (!(v & bit)) bad = true;
@@ -694,7 +699,9 @@ __device__ __forceinline__ void node_state(const InstView I, const int32_t *s_p,
     const int mp2 = mp / 2;
     for (int j = 0; j < n; ++j) {
       uint32_t g;
-      if constexpr (WIDE)
+      if constexpr (FLAGS)
+        g = (uint32_t)flags_lane[j * 64] - 1u;
+      else if constexpr (WIDE)
         g = (uint32_t)__builtin_amdgcn_sbfe((int)~words_lane[(j >> 5) * kBlock], j & 31, 1);
       else if constexpr (sizeof(SetT) == 8)
         g = 0u - (uint32_t)((~U >> j) & 1u);
@@ -776,7 +783,12 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   const int n = I.n, npad = I.npad;
   char *s_rec = L.s_rec;
   const int32_t *s_p = L.s_p;
-  uint32_t *words_lane = WIDE ? L.s_words + tid : nullptr;
+  uint32_t *words_lane = WIDE && FORM != kFormBytes ? L.s_words + tid : nullptr;
+  // the bytes form: the lane's flag bytes, rows [job 0 .. n] of its wave
+  uint8_t *flags_lane =
+      FORM == kFormBytes
+          ? L.s_alpha + (size_t)(tid >> 6) * (size_t)(n + 1) * 64 + (tid & 63)
+          : nullptr;
   const int64_t idx = base + tid;
   const bool live = idx < count;
 
@@ -784,9 +796,13 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   SetT U;
   int d, last;
   bool bad;
+  // values carry SH bits of fraction: 8 for the walks whose records carry
+  // the job in y's low byte, none for the bytes walk
+  constexpr int SH = FORM == kFormBytes ? 0 : 8;
   int T256[M], R256[M], Q256[M];
-  node_state<M, WIDE, 8, SetT>(I, s_p, words_lane, nodes, stride, aligned, idx,
-                               live, U, d, bad, last, R256, T256, Q256);
+  node_state<M, WIDE, SH, SetT, FORM == kFormBytes>(I, s_p, words_lane, nodes, stride,
+                                                   aligned, idx, live, U, d, bad, last,
+                                                   R256, T256, Q256, flags_lane);
   int u_left;
   if constexpr (WIDE)
     u_left = n - d;
@@ -803,7 +819,7 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
     int m1 = 0;
 #pragma unroll
     for (int k = 0; k < M; ++k) m1 = max(m1, T256[k] + Q256[k]);
-    lb1 = m1 >> 8;
+    lb1 = m1 >> SH;
     only1 = pf.lb1_only || (live && !bad && lb1_at_depth(pf.lb1_depths, d));
     bool decided = !live || bad || u_left == 0 || only1;
     if (pf.ub && !pf.lb1_only && !pf.depth_stats)
@@ -820,19 +836,8 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   //         can hold an older copy of it. ----
   kchar *ms = nullptr, *jt = nullptr;
   const uint8_t *al = nullptr;
-  if constexpr (FORM == kFormBytes) {
-    // the lane's flags as bytes: rows 0 .. n-1 from the words, row n zero;
-    // only this lane reads its bytes, so no barrier is needed
-    uint8_t *mine = L.s_alpha + (size_t)(tid >> 6) * (size_t)(n + 1) * 64 + (tid & 63);
-    for (int w = 0; w * 32 < n; ++w) {
-      const uint32_t word = words_lane[w * kBlock];
-      const int jend = min(n, w * 32 + 32);
-      for (int j = w * 32; j < jend; ++j) mine[j * 64] = (uint8_t)((word >> (j & 31)) & 1u);
-    }
-    mine[n * 64] = 0;
-    al = mine;
-  }
-  const char *so = reinterpret_cast<const char *>(L.s_aoff);
+  // only this lane reads its flag bytes, so no barrier is needed
+  if constexpr (FORM == kFormBytes) al = flags_lane;
   if constexpr (FORM == kFormMasks) if (!skip) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     uint64_t *slot = reinterpret_cast<uint64_t *>(
@@ -847,18 +852,27 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
   }
 
   int LB256 = 0;
-  if constexpr (!CHUNKED) {
+  if constexpr (FORM == kFormBytes) {
+    // the whole table, from global memory (one pass, no barriers)
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      asm volatile("" : "+v"(R256[k]), "+v"(T256[k]), "+v"(Q256[k]));
+    jt = reinterpret_cast<kchar *>(reinterpret_cast<uint64_t>(I.bjob));
+    if (!skip)
+      LB256 = pair_sweep<M, FORM>(reinterpret_cast<const char *>(I.bxy), jt, 0,
+                                  M * (M - 1) / 2, I.npad8, U, ms, al, R256, T256,
+                                  Q256, LB256);
+  } else if constexpr (!CHUNKED) {
 #pragma unroll
     for (int k = 0; k < M; ++k)
       asm volatile("" : "+v"(R256[k]), "+v"(T256[k]), "+v"(Q256[k]));
     if (!skip)
-      LB256 = pair_sweep<M, FORM>(s_rec, jt, 0, M * (M - 1) / 2, npad, U, ms, al, so,
+      LB256 = pair_sweep<M, FORM>(s_rec, jt, 0, M * (M - 1) / 2, npad, U, ms, al,
                                   R256, T256, Q256, LB256);
   } else {
     for (int chunk = 0; chunk < I.nchunks; ++chunk) {
       __syncthreads();
       stage_chunk(I, s_rec, chunk);
-      if constexpr (FORM == kFormBytes) stage_aoff(I, L.s_aoff, chunk);
       __syncthreads();
       // keep the per-node values from being re-derived per pair outside
       // the chunk loop (which would cost a register per pair)
@@ -870,17 +884,17 @@ __device__ __forceinline__ void bound_nodes(const InstView I, const LdsView &L,
       // the barriers above are kept when the wave skips its walks
       if (!skip)
         LB256 = pair_sweep<M, FORM>(s_rec, jt + (size_t)lo * npad * 4, lo, hi,
-                                    npad, U, ms, al, so, R256, T256, Q256, LB256);
+                                    npad, U, ms, al, R256, T256, Q256, LB256);
     }
   }
 
   // ---- 4. result ----
-  int lb = u_left == 0 ? last : ((skip || only1) ? lb1 : (LB256 >> 8));
+  int lb = u_left == 0 ? last : ((skip || only1) ? lb1 : (LB256 >> SH));
   if (pf.depth_stats && pf.ub) {
     const int ub = *pf.ub;
     const bool cnt = live && !bad && u_left > 0;
     count_depth_stats(pf.depth_stats, cnt, d, cnt && eliminated(lb1, ub, pf.rule),
-                      cnt && eliminated(LB256 >> 8, ub, pf.rule));
+                      cnt && eliminated(LB256 >> SH, ub, pf.rule));
   }
   if (bad) lb = FSP_LB_INVALID;
   if (live) lb_out[idx] = lb;

@@ -43,9 +43,10 @@ inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
 
 // Bytes of the mask-offset table: [P][npad] plus one group of four entries
 // that the walk may request (and not use) past the last pair.
-inline size_t joff_bytes(int P, int npad) {
-  return ((size_t)P * npad + 4) * sizeof(uint32_t);
-}
+inline size_t joff_bytes(int P, int npad) { return ((size_t)P * npad + 4) * sizeof(uint32_t); }
+// Entries of the bytes walk's tables: [P][npad8] plus two groups of eight
+// past the last pair that the walk may request (and not use).
+inline size_t bytes_entries(int P, int npad8) { return (size_t)P * npad8 + 16; }
 inline int npairs(int m) { return m * (m - 1) / 2; }
 // Words of the packed job table: [P][npad] plus one group of eight that the
 // walk may request (and not use) past the last pair.
@@ -71,8 +72,16 @@ struct fsp_instance {
   uint32_t *d_job16 = nullptr;
   uint32_t *d_joff = nullptr;  // [P][npad] 8 * job id per table position
   // n > 64: 1 when loaded with FSP_LOAD_JOB_MASKS (the job-mask walk, with
-  // its per-wave scratch), 0 for the LDS bytes walk
+  // its per-wave scratch), 0 for the bytes walk
   int masks_walk = 0;
+  // The bytes walk's tables (n > 64), [P][npad8] with npad8 = n rounded up
+  // to 8, read by scalar loads (bytes_entries(P, npad8) entries each):
+  //   bxy   x | y << 16 with x = b - a (two's complement), y = lag + b; both
+  //         fit in 16 bits because p <= 32767 and every job total <= 65535
+  //   bjob  the position's job id (padding: n)
+  int npad8 = 0;
+  uint32_t *d_bxy = nullptr;
+  uint8_t *d_bjob = nullptr;
   std::vector<int32_t> p_host;  // [n][m], for host-side set-up work (NEH)
 };
 

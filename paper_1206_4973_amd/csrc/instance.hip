@@ -58,7 +58,8 @@ __global__ void stage_totals(const int32_t *__restrict__ p, int n, int mp,
 __global__ __launch_bounds__(256) void stage_pairs(
     const int32_t *__restrict__ p, int n, int m, int mp, int npad,
     Rec *__restrict__ rec_out, uint32_t *__restrict__ joff_out,
-    uint32_t *__restrict__ xy16_out, uint32_t *__restrict__ job16_out) {
+    uint32_t *__restrict__ xy16_out, uint32_t *__restrict__ job16_out, int npad8,
+    uint32_t *__restrict__ bxy_out, uint8_t *__restrict__ bjob_out) {
   __shared__ int sA[256], sB[256];
   const int pi = blockIdx.x;
   // (k,l) of pair pi in lexicographic order
@@ -96,6 +97,12 @@ __global__ __launch_bounds__(256) void stage_pairs(
       rank += before ? 1 : 0;
     }
     pos = rank;
+  }
+  if (bxy_out && j < npad8) {
+    // the bytes walk's tables; padding: x = y = 0 and job n (a zero flag)
+    const size_t slot8 = (size_t)pi * npad8 + pos;
+    bxy_out[slot8] = j < n ? ((uint32_t)(b - a) & 0xffffu) | ((uint32_t)(lag + b) << 16) : 0u;
+    bjob_out[slot8] = (uint8_t)(j < n ? j : n);
   }
   if (j >= npad) return;
   // Padding records are all-zero and point at job n's mask, which is empty:
@@ -138,6 +145,8 @@ void free_device(fsp_instance *in) {
   if (in->d_tot) (void)hipFree(in->d_tot);
   if (in->d_rec) (void)hipFree(in->d_rec);
   if (in->d_joff) (void)hipFree(in->d_joff);
+  if (in->d_bxy) (void)hipFree(in->d_bxy);
+  if (in->d_bjob) (void)hipFree(in->d_bjob);
   if (in->d_xy16) (void)hipFree(in->d_xy16);
   if (in->d_job16) (void)hipFree(in->d_job16);
   if (in->d_Hp) (void)hipFree(in->d_Hp);
@@ -146,6 +155,8 @@ void free_device(fsp_instance *in) {
   in->d_p = in->d_H = in->d_Q = in->d_tot = nullptr;
   in->d_rec = nullptr;
   in->d_joff = nullptr;
+  in->d_bxy = nullptr;
+  in->d_bjob = nullptr;
   in->d_xy16 = in->d_job16 = nullptr;
 }
 
@@ -158,6 +169,9 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
       hipMalloc(&in->d_tot, mp * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&in->d_rec, (size_t)in->P * in->npad * sizeof(Rec)) != hipSuccess ||
       hipMalloc(&in->d_joff, joff_bytes(in->P, in->npad)) != hipSuccess ||
+      (in->npad8 > 0 &&
+       (hipMalloc(&in->d_bxy, bytes_entries(in->P, in->npad8) * 4) != hipSuccess ||
+        hipMalloc(&in->d_bjob, bytes_entries(in->P, in->npad8)) != hipSuccess)) ||
       (in->p16 && (hipMalloc(&in->d_xy16, (size_t)in->P * in->npad * 4) != hipSuccess ||
                    hipMalloc(&in->d_job16, p16_job_words(in->P, in->npad) * 4) !=
                        hipSuccess)) ||
@@ -172,9 +186,13 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
   if (hipMemcpy(d_in, p_host, (size_t)n * m * sizeof(int32_t),
                 hipMemcpyHostToDevice) != hipSuccess)
     rc = FSP_EDEVICE;
-  // the offset table's tail group past the last pair is read, never used
+  // the tables' spare entries past the last pair are read, never used (the
+  // bytes walk's job 0 names a valid flag row)
   if (rc == FSP_OK &&
-      hipMemset(in->d_joff, 0, joff_bytes(in->P, in->npad)) != hipSuccess)
+      (hipMemset(in->d_joff, 0, joff_bytes(in->P, in->npad)) != hipSuccess ||
+       (in->npad8 > 0 &&
+        (hipMemset(in->d_bxy, 0, bytes_entries(in->P, in->npad8) * 4) != hipSuccess ||
+         hipMemset(in->d_bjob, 0, bytes_entries(in->P, in->npad8)) != hipSuccess))))
     rc = FSP_EDEVICE;
   // likewise the packed job table's spare group (job 0: a valid index)
   if (rc == FSP_OK && in->p16 &&
@@ -187,7 +205,7 @@ int build_tables(fsp_instance *in, const int32_t *p_host) {
                        in->d_tot);
     hipLaunchKernelGGL(stage_pairs, dim3(in->P), dim3(256), 0, s, in->d_p, n,
                        m, mp, in->npad, in->d_rec, in->d_joff,
-                       in->d_xy16, in->d_job16);
+                       in->d_xy16, in->d_job16, in->npad8, in->d_bxy, in->d_bjob);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
       rc = FSP_EDEVICE;
   }
@@ -245,6 +263,7 @@ int fsp_load_instance_ex(const int32_t *p_host, int32_t n, int32_t m,
   in->mp = round_up(m, 4);
   in->P = npairs(m);
   in->npad = round_up(n, 4);
+  in->npad8 = uses_job_masks(n) ? round_up(n, 8) : 0;
   in->wide = n > 32 ? 1 : 0;
   in->p16 = (n <= 32 && total <= 32767 && !(flags & FSP_LOAD_ONE_NODE_PER_LANE)) ? 1 : 0;
   in->masks_walk = (flags & FSP_LOAD_JOB_MASKS) ? 1 : 0;
