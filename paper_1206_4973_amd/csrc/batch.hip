@@ -43,9 +43,8 @@ enum SegForm : int {
   kSegMasksC = 2,  // job masks, table streamed in chunks
   kSegReg64 = 3,   // 33..64 jobs, 64-bit register
   kSegPacked = 4,  // n <= 32 and total work <= 32767, two nodes per lane
-  kSegBytes = 5,   // n > 64, flag bytes in LDS, whole table in LDS
-  kSegBytesC = 6,  // n > 64, flag bytes in LDS, table streamed in chunks
-  kSegForms = 7
+  kSegBytes = 5,   // n > 64, flag bytes in LDS, table by scalar loads
+  kSegForms = 6
 };
 
 // Kernel (part) of a form: the one-node register and mask forms, the packed
@@ -53,7 +52,7 @@ enum SegForm : int {
 // occupancy).
 constexpr int kParts = 3;
 __host__ __device__ constexpr int part_of(int form) {
-  return form == kSegPacked ? 1 : (form == kSegBytes || form == kSegBytesC) ? 2 : 0;
+  return form == kSegPacked ? 1 : form == kSegBytes ? 2 : 0;
 }
 
 // Variant = machine-count base (5, 10 or 20 machines) * kSegForms + form.
@@ -117,10 +116,7 @@ __device__ __forceinline__ void run_any(const BatchSeg &S, int form, char *smem,
   if constexpr (KIND == 1) {
     run_tile_p16<M>(S, smem, t, restage);
   } else if constexpr (KIND == 2) {
-    if (form == kSegBytes)
-      run_tile<M, kFormBytes, false>(S, smem, t, restage, ts);
-    else
-      run_tile<M, kFormBytes, true>(S, smem, t, restage, ts);
+    run_tile<M, kFormBytes, false>(S, smem, t, restage, ts);
   } else {
     switch (form) {
       case kSegReg32: run_tile<M, kFormReg32, false>(S, smem, t, restage, ts); break;
@@ -185,18 +181,16 @@ std::vector<int> forms_for(const fsp_instance *inst, const InstView &v, bool all
     return {kSegReg32};
   }
   if (!uses_job_masks(inst->n)) return {kSegReg64, masks};
-  const int bytes =
-      inst_view(inst, table_budget_bytes(inst->n)).nchunks > 1 ? kSegBytesC : kSegBytes;
   // the job masks by default (an instance loaded for them always), the bytes
   // walk when the batch asks for it
-  if (prefer_bytes && !inst->masks_walk) return {bytes, masks};
-  return {masks, bytes};
+  if (prefer_bytes && !inst->masks_walk) return {kSegBytes, masks};
+  return {masks, kSegBytes};
 }
 
 // Relative cost of one tile: table steps per node times nodes per tile times
 // the walk's vector instructions per step (per node).
 double tile_cost(const fsp_instance *in, int form) {
-  static const double per_step[kSegForms] = {4.0, 3.0, 3.0, 5.0, 1.5, 4.25, 4.25};
+  static const double per_step[kSegForms] = {4.0, 3.0, 3.0, 5.0, 1.5, 4.0};
   const double nodes = form == kSegPacked ? 2.0 * kBlock : (double)kBlock;
   return (double)in->P * in->npad * nodes * per_step[form];
 }
@@ -282,8 +276,7 @@ int path_of_form(int form) {
     case kSegReg32: return FSP_PATH_REGISTER;
     case kSegPacked: return FSP_PATH_PACKED;
     case kSegReg64: return FSP_PATH_REGISTER64;
-    case kSegBytes:
-    case kSegBytesC: return FSP_PATH_BYTES;
+    case kSegBytes: return FSP_PATH_BYTES;
     default: return FSP_PATH_MASKS;
   }
 }

@@ -146,8 +146,8 @@ BoundFn pick(int form, bool chunked) {
   // table of one chunk)
   if (form == kFormReg64) return bound_kernel<M, kFormReg64, true>;
   if (form == kFormReg32) return bound_kernel<M, kFormReg32, false>;
-  if (form == kFormBytes)
-    return chunked ? bound_kernel<M, kFormBytes, true> : bound_kernel<M, kFormBytes, false>;
+  // the bytes walk stages no table, so it is never chunked
+  if (form == kFormBytes) return bound_kernel<M, kFormBytes, false>;
   return chunked ? bound_kernel<M, kFormMasks, true> : bound_kernel<M, kFormMasks, false>;
 }
 
