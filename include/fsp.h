@@ -212,20 +212,17 @@ typedef struct {
  *                     same shapes plan without timing.  Timing launches the
  *                     batch: its lb_out buffers are written.  0: every
  *                     segment takes its shape's default form (the fastest in
- *                     single-pool measurements, as fsp_instance_path, but the
- *                     job masks above 64 jobs: in a batch the bytes walk runs
- *                     in a kernel of its own after the others, which cost
- *                     more than it saved on the mixed batches measured).
+ *                     single-pool measurements, as fsp_instance_path).
  *   one_node_per_lane 1: never the packed two-nodes-per-lane form.
- *   bytes_walk        1: segments of more than 64 jobs take the bytes walk
- *                     by default (instances loaded with FSP_LOAD_JOB_MASKS
- *                     keep the job masks).
+ *   job_masks         1: segments of more than 64 jobs take the job masks
+ *                     by default instead of the bytes walk (instances loaded
+ *                     with FSP_LOAD_JOB_MASKS always take them).
  * Other values are FSP_EINVAL. */
 typedef struct {
   int32_t blocks_per_cu;
   int32_t autotune;
   int32_t one_node_per_lane;
-  int32_t bytes_walk;
+  int32_t job_masks;
 } fsp_batch_config;
 
 typedef struct fsp_batch fsp_batch;
@@ -252,9 +249,8 @@ int fsp_batch_launch(fsp_batch *b, void *stream);
 int fsp_batch_replay(fsp_batch *b, void *stream);
 
 /* Tiles (256 nodes, or 512 in the packed form), the largest persistent
- * grid, segments in the batch kernels (one-node forms, packed form, bytes
- * form) and segments bounded by single-pool launches (any pointer may be
- * NULL). */
+ * grid, segments in the batch kernels (one-node forms, packed form) and
+ * segments bounded by single-pool launches (any pointer may be NULL). */
 int fsp_batch_info(const fsp_batch *b, int64_t *tiles, int32_t *grid,
                    int32_t *kernel_segments, int32_t *fallback_segments);
 

@@ -14,8 +14,9 @@
 //
 // Launch shape: by default every segment takes the fastest form that its
 // shape allows in single-pool measurements (packed for n <= 32 with small
-// times, the 64-bit register form for 33..64 jobs, job masks above) and the
-// grid holds as many workgroups per CU as fit.  With autotuning, the planner
+// times, the 64-bit register form for 33..64 jobs, the bytes walk above) and
+// the grid holds as many workgroups per CU as fit.  Two kernels: the packed
+// segments, and every one-node form.  With autotuning, the planner
 // times the candidate forms of each shape on the batch's own segments of that
 // shape, then the number of workgroups per CU on the whole batch, and keeps
 // the fastest (cached per device and shape, resp. per batch signature).
@@ -47,13 +48,11 @@ enum SegForm : int {
   kSegForms = 6
 };
 
-// Kernel (part) of a form: the one-node register and mask forms, the packed
-// form, the bytes form (each pins registers or LDS that would cost the others
-// occupancy).
-constexpr int kParts = 3;
-__host__ __device__ constexpr int part_of(int form) {
-  return form == kSegPacked ? 1 : form == kSegBytes ? 2 : 0;
-}
+// Kernel (part) of a form: the one-node forms (register, 64-bit register,
+// job masks, bytes), the packed form (its pinned registers would cost the
+// others occupancy).
+constexpr int kParts = 2;
+__host__ __device__ constexpr int part_of(int form) { return form == kSegPacked ? 1 : 0; }
 
 // Variant = machine-count base (5, 10 or 20 machines) * kSegForms + form.
 __host__ __device__ constexpr int variant(int mbase, int form) { return mbase * kSegForms + form; }
@@ -73,11 +72,9 @@ struct BatchSeg {
 constexpr size_t kWideBudget = 32 * 1024;
 constexpr size_t kNarrowBudget = 64 * 1024;
 
-__global__ void reset_counters(unsigned long long *c0, unsigned long long *c1,
-                               unsigned long long *c2) {
+__global__ void reset_counters(unsigned long long *c0, unsigned long long *c1) {
   if (threadIdx.x == 0 && c0) *c0 = 0ull;
   if (threadIdx.x == 1 && c1) *c1 = 0ull;
-  if (threadIdx.x == 2 && c2) *c2 = 0ull;
 }
 
 template <int M, int FORM, bool CHUNKED>
@@ -115,14 +112,13 @@ __device__ __forceinline__ void run_any(const BatchSeg &S, int form, char *smem,
                                         bool restage, char *ts) {
   if constexpr (KIND == 1) {
     run_tile_p16<M>(S, smem, t, restage);
-  } else if constexpr (KIND == 2) {
-    run_tile<M, kFormBytes, false>(S, smem, t, restage, ts);
   } else {
     switch (form) {
       case kSegReg32: run_tile<M, kFormReg32, false>(S, smem, t, restage, ts); break;
       case kSegMasks: run_tile<M, kFormMasks, false>(S, smem, t, restage, ts); break;
       case kSegMasksC: run_tile<M, kFormMasks, true>(S, smem, t, restage, ts); break;
       case kSegReg64: run_tile<M, kFormReg64, true>(S, smem, t, restage, ts); break;
+      case kSegBytes: run_tile<M, kFormBytes, false>(S, smem, t, restage, ts); break;
       default: break;
     }
   }
@@ -130,9 +126,8 @@ __device__ __forceinline__ void run_any(const BatchSeg &S, int form, char *smem,
 
 // The packed segments run in a kernel of their own: the packed walk pins
 // 48 VGPRs (its multipliers and load buffers), which in one kernel with the
-// other forms cost those forms spills and a fifth of their speed.  So do the
-// bytes segments (48 pinned SGPRs).
-// KIND: 0 the one-node register and mask forms, 1 packed, 2 bytes.
+// other forms cost those forms spills and a fifth of their speed.
+// KIND: 0 the one-node forms, 1 packed.
 template <int KIND>
 __global__ __launch_bounds__(kBlock, 4) void batch_kernel(
     const BatchSeg *__restrict__ segs, int nsegs, int64_t total_tiles,
@@ -174,17 +169,17 @@ int machine_base(int m) { return m == 5 ? 0 : m == 10 ? 1 : m == 20 ? 2 : -1; }
 // The walk forms an instance's shape allows, the default (fastest in
 // single-pool measurements) first.
 std::vector<int> forms_for(const fsp_instance *inst, const InstView &v, bool allow_packed,
-                           bool prefer_bytes) {
+                           bool prefer_masks) {
   const int masks = v.nchunks > 1 ? kSegMasksC : kSegMasks;
   if (!inst->wide) {
     if (inst->p16 && allow_packed) return {kSegPacked, kSegReg32};
     return {kSegReg32};
   }
   if (!uses_job_masks(inst->n)) return {kSegReg64, masks};
-  // the job masks by default (an instance loaded for them always), the bytes
-  // walk when the batch asks for it
-  if (prefer_bytes && !inst->masks_walk) return {kSegBytes, masks};
-  return {masks, kSegBytes};
+  // the bytes walk by default; the job masks when the batch asks for them or
+  // the instance was loaded for them
+  if (prefer_masks || inst->masks_walk) return {masks, kSegBytes};
+  return {kSegBytes, masks};
 }
 
 // Relative cost of one tile: table steps per node times nodes per tile times
@@ -198,8 +193,7 @@ double tile_cost(const fsp_instance *in, int form) {
 }  // namespace
 
 // One persistent launch over a segment table: part 0 holds the one-node-per-
-// lane register and mask forms, part 1 the packed form, part 2 the bytes
-// form.
+// lane forms, part 1 the packed form.
 struct BatchPart {
   int nsegs = 0;
   int64_t total_tiles = 0;
@@ -225,10 +219,9 @@ struct fsp_batch {
 namespace {
 
 int enqueue(fsp_batch *b, hipStream_t s) {
-  const BatchPart &p0 = b->part[0], &p1 = b->part[1], &p2 = b->part[2];
-  if (p0.nsegs > 0 || p1.nsegs > 0 || p2.nsegs > 0) {
-    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, p0.d_counter, p1.d_counter,
-                       p2.d_counter);
+  const BatchPart &p0 = b->part[0], &p1 = b->part[1];
+  if (p0.nsegs > 0 || p1.nsegs > 0) {
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, p0.d_counter, p1.d_counter);
     if (p0.nsegs > 0)
       hipLaunchKernelGGL(batch_kernel<0>, dim3(p0.grid), dim3(kBlock), p0.lds, s,
                          p0.d_segs, p0.nsegs, p0.total_tiles, p0.d_counter, b->d_slots,
@@ -236,10 +229,6 @@ int enqueue(fsp_batch *b, hipStream_t s) {
     if (p1.nsegs > 0)
       hipLaunchKernelGGL(batch_kernel<1>, dim3(p1.grid), dim3(kBlock), p1.lds, s,
                          p1.d_segs, p1.nsegs, p1.total_tiles, p1.d_counter,
-                         (char *)nullptr, (int64_t)0);
-    if (p2.nsegs > 0)
-      hipLaunchKernelGGL(batch_kernel<2>, dim3(p2.grid), dim3(kBlock), p2.lds, s,
-                         p2.d_segs, p2.nsegs, p2.total_tiles, p2.d_counter,
                          (char *)nullptr, (int64_t)0);
     FSP_HIP_TRY(hipGetLastError());
   }
@@ -284,7 +273,7 @@ int path_of_form(int form) {
 // Plans a batch with the given form per shape (absent shapes: the default
 // form) and workgroups per CU (<= 0: as many as fit).
 int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
-          bool allow_packed, bool prefer_bytes, fsp_batch **out) {
+          bool allow_packed, bool prefer_masks, fsp_batch **out) {
   *out = nullptr;
   fsp_batch *b = new (std::nothrow) fsp_batch();
   if (!b) return FSP_ENOMEM;
@@ -309,7 +298,7 @@ int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
     }
     Item it{};
     it.s.I = inst_view(in, in->wide ? kWideBudget : kNarrowBudget);
-    const std::vector<int> allowed = forms_for(in, it.s.I, allow_packed, prefer_bytes);
+    const std::vector<int> allowed = forms_for(in, it.s.I, allow_packed, prefer_masks);
     int form = allowed[0];
     const auto f = forms.find({in->n, in->m});
     if (f != forms.end() &&
@@ -340,8 +329,8 @@ int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
   std::stable_sort(items.begin(), items.end(),
                    [](const Item &a, const Item &c) { return a.cost > c.cost; });
   std::vector<BatchSeg> table[kParts];
-  int64_t tiles[kParts] = {0, 0, 0};
-  size_t lds[kParts] = {16, 16, 16};
+  int64_t tiles[kParts] = {0, 0};
+  size_t lds[kParts] = {16, 16};
   int slot_max = 0;
   for (const Item &it : items) slot_max = std::max(slot_max, it.s.I.slot_bytes);
   size_t scratch = 0;
@@ -354,7 +343,7 @@ int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
     tiles[k] += (it.s.count + it.s.tile_nodes - 1) / it.s.tile_nodes;
     const InstView &I = it.s.I;
     lds[k] = std::max(lds[k], k == 1 ? lds_bytes_p16(I.n, I.mp, I.npad, I.P)
-                              : k == 2 ? lds_bytes(I.n, I.mp, I.npad, I.ppc, true, true)
+                              : form == kSegBytes ? lds_bytes(I.n, I.mp, I.npad, I.ppc, true, true)
                                        : lds_bytes(I.n, I.mp, I.npad, I.ppc,
                                                    form == kSegMasks || form == kSegMasksC));
     table[k].push_back(it.s);
@@ -398,9 +387,8 @@ int build(const fsp_segment *segs, int32_t nsegs, const FormMap &forms, int bpc,
       destroy(b);
       return FSP_EDEVICE;
     }
-    const void *fn = k == 0   ? reinterpret_cast<const void *>(batch_kernel<0>)
-                     : k == 1 ? reinterpret_cast<const void *>(batch_kernel<1>)
-                              : reinterpret_cast<const void *>(batch_kernel<2>);
+    const void *fn = k == 0 ? reinterpret_cast<const void *>(batch_kernel<0>)
+                            : reinterpret_cast<const void *>(batch_kernel<1>);
     int per_cu = 0;
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds) !=
             hipSuccess ||
@@ -450,15 +438,13 @@ int time_batch(fsp_batch *b, double *secs) {
   return rc;
 }
 
-// Autotuner caches: the form per (device, n, m, packed allowed); per
-// (device, batch signature) whether the shapes on the bytes walk keep it, and
-// the workgroups per CU.
+// Autotuner caches: the form per (device, n, m, packed allowed), and the
+// workgroups per CU per (device, batch signature).
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, int> g_form_cache;
 std::map<std::pair<int, std::vector<int64_t>>, int> g_bpc_cache;
-std::map<std::pair<int, std::vector<int64_t>>, bool> g_mix_cache;
 
-int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, bool prefer_bytes,
+int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, bool prefer_masks,
              FormMap *forms,
              int *bpc) {
   int dev = 0;
@@ -475,7 +461,7 @@ int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, bool pre
     bool mixed = false;
     for (const fsp_segment &g : sh.second) mixed = mixed || g.inst->p16 != in->p16;
     const InstView v = inst_view(in, in->wide ? kWideBudget : kNarrowBudget);
-    const std::vector<int> allowed = forms_for(in, v, allow_packed, prefer_bytes);
+    const std::vector<int> allowed = forms_for(in, v, allow_packed, prefer_masks);
     if (allowed.size() < 2 || mixed) continue;
     const auto key = std::make_tuple(dev, sh.first.first, sh.first.second,
                                      (int)(allow_packed && in->p16));
@@ -494,7 +480,7 @@ int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, bool pre
       fm[sh.first] = form;
       fsp_batch *b = nullptr;
       int rc = build(sh.second.data(), (int32_t)sh.second.size(), fm, 0, allow_packed,
-                     prefer_bytes, &b);
+                     prefer_masks, &b);
       double t = 0.0;
       if (rc == FSP_OK) rc = time_batch(b, &t);
       if (b) destroy(b);
@@ -521,55 +507,12 @@ int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, bool pre
                     ((int64_t)(f == fm.end() ? 7 : f->second) << 36) | c);
     }
     std::sort(sig.begin(), sig.end());
-    sig.push_back((int64_t)allow_packed << 1 | (int64_t)prefer_bytes);
+    sig.push_back((int64_t)allow_packed << 1 | (int64_t)prefer_masks);
     return sig;
   };
-  // Shapes that chose the bytes walk alone put a kernel of its own into the
-  // launch, which runs after the others: keep them there only when the whole
-  // batch is faster so than with the job masks in their place.
-  {
-    FormMap alt = *forms;
-    bool any = false;
-    for (const auto &sh : shapes) {
-      const fsp_instance *in = sh.second[0].inst;
-      const InstView v = inst_view(in, in->wide ? kWideBudget : kNarrowBudget);
-      const std::vector<int> allowed = forms_for(in, v, allow_packed, prefer_bytes);
-      const auto f = forms->find(sh.first);
-      const int form = f != forms->end() ? f->second : allowed[0];
-      if (part_of(form) != 2 || in->masks_walk) continue;
-      alt[sh.first] = v.nchunks > 1 ? kSegMasksC : kSegMasks;
-      any = true;
-    }
-    if (any) {
-      const auto mkey = std::make_pair(dev, signature(*forms));
-      bool keep = true, cached = false;
-      {
-        std::lock_guard<std::mutex> lock(g_tune_mu);
-        const auto c = g_mix_cache.find(mkey);
-        if (c != g_mix_cache.end()) {
-          keep = c->second;
-          cached = true;
-        }
-      }
-      if (!cached) {
-        double t[2] = {0.0, 0.0};
-        for (int k = 0; k < 2; ++k) {
-          fsp_batch *b = nullptr;
-          int rc = build(segs, nsegs, k == 0 ? *forms : alt, 0, allow_packed, prefer_bytes, &b);
-          if (rc == FSP_OK) rc = time_batch(b, &t[k]);
-          if (b) destroy(b);
-          if (rc != FSP_OK) return rc;
-        }
-        keep = t[0] < t[1];
-        std::lock_guard<std::mutex> lock(g_tune_mu);
-        g_mix_cache[mkey] = keep;
-      }
-      if (!keep) *forms = alt;
-    }
-  }
   // workgroups per CU on the whole batch
   fsp_batch *probe = nullptr;
-  int rc = build(segs, nsegs, *forms, 0, allow_packed, prefer_bytes, &probe);
+  int rc = build(segs, nsegs, *forms, 0, allow_packed, prefer_masks, &probe);
   if (rc != FSP_OK) return rc;
   const int max_bpc = probe->blocks_per_cu;
   destroy(probe);
@@ -586,7 +529,7 @@ int autotune(const fsp_segment *segs, int32_t nsegs, bool allow_packed, bool pre
   double best_t = 0.0;
   for (int k = max_bpc; k >= 1; --k) {
     fsp_batch *b = nullptr;
-    rc = build(segs, nsegs, *forms, k, allow_packed, prefer_bytes, &b);
+    rc = build(segs, nsegs, *forms, k, allow_packed, prefer_masks, &b);
     double t = 0.0;
     if (rc == FSP_OK) rc = time_batch(b, &t);
     if (b) destroy(b);
@@ -621,19 +564,19 @@ int fsp_batch_create(const fsp_segment *segs, int32_t nsegs,
   }
   if (cfg && (cfg->blocks_per_cu < 0 || (cfg->autotune != 0 && cfg->autotune != 1) ||
               (cfg->one_node_per_lane != 0 && cfg->one_node_per_lane != 1) ||
-              (cfg->bytes_walk != 0 && cfg->bytes_walk != 1)))
+              (cfg->job_masks != 0 && cfg->job_masks != 1)))
     return FSP_EINVAL;
   const bool allow_packed = !(cfg && cfg->one_node_per_lane == 1);
-  const bool prefer_bytes = cfg && cfg->bytes_walk == 1;
+  const bool prefer_masks = cfg && cfg->job_masks == 1;
   FormMap forms;
   int bpc = cfg ? cfg->blocks_per_cu : 0;
   if (cfg && cfg->autotune == 1) {
     int tuned = 0;
-    const int rc = autotune(segs, nsegs, allow_packed, prefer_bytes, &forms, &tuned);
+    const int rc = autotune(segs, nsegs, allow_packed, prefer_masks, &forms, &tuned);
     if (rc != FSP_OK) return rc;
     if (bpc <= 0) bpc = tuned;
   }
-  return build(segs, nsegs, forms, bpc, allow_packed, prefer_bytes, out);
+  return build(segs, nsegs, forms, bpc, allow_packed, prefer_masks, out);
 }
 
 int fsp_batch_launch(fsp_batch *b, void *stream) {

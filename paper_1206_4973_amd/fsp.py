@@ -51,7 +51,7 @@ class _Segment(ctypes.Structure):
 
 class _BatchConfig(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("one_node_per_lane", ctypes.c_int32), ("bytes_walk", ctypes.c_int32)]
+                ("one_node_per_lane", ctypes.c_int32), ("job_masks", ctypes.c_int32)]
 
 
 POOL_KINDS = {"fixed": 0, "adaptive": 1, "autotuned": 2, "learned": 3}
@@ -451,7 +451,7 @@ class Batch:
     keep their storage) as long as the batch is used."""
 
     def __init__(self, items, blocks_per_cu: int = 0, autotune: bool = False,
-                 packed: bool = True, bytes_walk: bool = False):
+                 packed: bool = True, job_masks: bool = False):
         self._keep = [(i, n) for i, n, _ in items]
         self.nsegs = len(items)
         segs, self.outs = _segments(items)
@@ -459,7 +459,7 @@ class Batch:
         cfg.blocks_per_cu = int(blocks_per_cu)
         cfg.autotune = 1 if autotune else 0
         cfg.one_node_per_lane = 0 if packed else 1
-        cfg.bytes_walk = 1 if bytes_walk else 0
+        cfg.job_masks = 1 if job_masks else 0
         h = ctypes.c_void_p()
         _check(lib().fsp_batch_create(segs, len(items), ctypes.byref(cfg), ctypes.byref(h)),
                "fsp_batch_create")

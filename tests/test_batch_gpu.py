@@ -68,11 +68,12 @@ def test_mixed_batch_matches_oracle_and_single_launches(fsp, orc):
 
 
 def test_forms_in_one_launch(fsp, orc):
-    """Packed, 32-bit, 64-bit-register, job-mask and (asked for) bytes
-    segments in one launch (the same 20-job shape both packed and, with large
-    times, 32-bit; a 200-job instance loaded for the job-mask walk keeps it),
-    with ragged tails of both tile sizes: every node equals the oracle, and
-    the batch reports the form each segment took."""
+    """Packed, 32-bit, 64-bit-register, bytes and job-mask segments in one
+    launch (the same 20-job shape both packed and, with large times, 32-bit;
+    a 200-job instance loaded for the job-mask walk keeps it; with job_masks
+    the 100-job segment takes them too), with ragged tails of both tile
+    sizes: every node equals the oracle, and the batch reports the form each
+    segment took."""
     rng = np.random.default_rng(11)
     big = rng.integers(1500, 3000, size=(20, 10)).astype(np.int32)  # total > 32767
     cases = [(I.instance(20, 10, 3501), 1537), (big, 999), (I.instance(20, 20, 3502), 513),
@@ -88,14 +89,14 @@ def test_forms_in_one_launch(fsp, orc):
     b = fsp.Batch(items)
     paths, bpc = b.paths()
     say("paths", paths, "blocks per CU", bpc)
-    assert paths == ["packed", "register", "packed", "register64", "masks", "packed", "masks"]
+    assert paths == ["packed", "register", "packed", "register64", "bytes", "packed", "masks"]
     outs = b.launch()
     torch.cuda.synchronize()
     for out, (p, pool) in zip(outs, host):
         assert np.array_equal(out.cpu().numpy(), orc.bound_pool(p, pool, nthreads=8))
     b.close()
-    bb = fsp.Batch(items, bytes_walk=True)
-    assert bb.paths()[0] == ["packed", "register", "packed", "register64", "bytes", "packed",
+    bb = fsp.Batch(items, job_masks=True)
+    assert bb.paths()[0] == ["packed", "register", "packed", "register64", "masks", "packed",
                              "masks"]
     outs = bb.launch()
     torch.cuda.synchronize()
