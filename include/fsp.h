@@ -374,7 +374,10 @@ typedef struct {
  * estimate reaches UB (the network expects no pending node to beat UB: what
  * is left is a proof, in which order does not matter), pools take the
  * largest size the buffers hold (policy->max_pool, or the device's resident
- * threads) and the network is no longer run (proof_pools = 1).  The exact
+ * threads) and the network is no longer run (proof_pools = 1); on an
+ * instance of more jobs than the network was trained on
+ * (fsp_model_set_trained_jobs) the search does not switch and keeps diving,
+ * its dive pools doubling up to that largest size.  The exact
  * bound still decides every elimination, so the optimum does not depend on
  * the model.
  * FSP_POOL_AUTOTUNED and FSP_POOL_LEARNED fill a pool from several depths,
@@ -485,6 +488,13 @@ int fsp_model_create(int32_t in_features, int32_t hidden, int32_t outputs,
                      uint64_t seed, fsp_model **out); /* hidden must be 128 */
 int fsp_model_free(fsp_model *m);
 int64_t fsp_model_param_count(void);
+/* The job count of the instances the network was trained on (0, the value
+ * at creation: unknown).  The learned search (FSP_POOL_LEARNED) switches to
+ * proof pools on the network's estimates only for instances of at most that
+ * many jobs; on larger ones the estimates are extrapolations and the search
+ * keeps diving (see fsp_branch_and_bound).  n < 0 or a NULL model:
+ * FSP_EINVAL. */
+int fsp_model_set_trained_jobs(fsp_model *m, int32_t n);
 int fsp_model_set_params(fsp_model *m, const float *host, int64_t n);
 int fsp_model_get_params(const fsp_model *m, float *host, int64_t n);
 int fsp_model_get_grads(const fsp_model *m, float *host, int64_t n);

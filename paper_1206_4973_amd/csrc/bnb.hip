@@ -978,9 +978,17 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
   // doubles the dive pool (up to that largest size; an improvement resets
   // it), so a network whose estimates stay below UB still reaches large
   // pools.
+  //
+  // The switch to proof pools trusts the network's estimates only on
+  // instances of at most as many jobs as it was trained on: beyond them its
+  // estimates are extrapolations (on 200-job instances, with a network
+  // trained on 50-job ones, they never fell below UB, so the search proved
+  // from the start and never dived), and the search keeps diving.
   const int64_t dive_pool = std::max<int64_t>(1, fixed / 16);
   int64_t dive = dive_pool;
   bool proof = false;
+  const bool trust_estimates =
+      model && (model_trained_jobs(model) == 0 || inst->n <= model_trained_jobs(model));
   const double t_loop0 = elapsed();
   while (true) {
     target = kind == FSP_POOL_ADAPTIVE ? ap.current
@@ -1031,12 +1039,14 @@ int run_bnb(const fsp_instance *inst, const fsp_pool_policy *policy, int32_t ub_
     }
     if (kind == FSP_POOL_ADAPTIVE && t1 > t0) ap.observe(eff);
     if (model && !proof) {
-      // estimates are completions in units of the NEH makespan
-      float me = 0.f;
-      if ((rc = S.pending_min_estimate(&me)) != FSP_OK) break;
-      if ((double)me * (double)neh >= (double)h.ub) {
-        proof = true;
-        if ((rc = S.capture_plain(nb_iter)) != FSP_OK) break;
+      if (trust_estimates) {
+        // estimates are completions in units of the NEH makespan
+        float me = 0.f;
+        if ((rc = S.pending_min_estimate(&me)) != FSP_OK) break;
+        if ((double)me * (double)neh >= (double)h.ub) {
+          proof = true;
+          if ((rc = S.capture_plain(nb_iter)) != FSP_OK) break;
+        }
       }
       dive = h.improved ? dive_pool : std::min<int64_t>(max_pool, 2 * dive);
     }

@@ -197,6 +197,7 @@ int model_forward_score_dev(const fsp_model *m, const void *x, const int32_t *n_
                             int64_t max_n, const ScoreEpilogue &sc, hipStream_t s);
 int model_outputs(const fsp_model *m);
 int model_in_features(const fsp_model *m);
+int model_trained_jobs(const fsp_model *m);
 
 struct AdaptivePolicy {
   int nb_threads = 256, nb_blocks = 0;

@@ -527,6 +527,7 @@ __global__ void loss_grad_kernel(const float *__restrict__ Y, const float *__res
 struct fsp_model {
   int device = 0;
   int in_features = 0, outputs = 0;
+  int trained_jobs = 0;  // job count of the training instances (0: unknown)
   float *P = nullptr, *G = nullptr, *m1 = nullptr, *m2 = nullptr;
   uint8_t *mask = nullptr;  // 1 for parameters that exist at this size
   bf16 *E = nullptr;
@@ -605,6 +606,7 @@ int model_forward(const fsp_model *m, const void *x, int64_t n, float *y, hipStr
 }
 int model_outputs(const fsp_model *m) { return m->outputs; }
 int model_in_features(const fsp_model *m) { return m->in_features; }
+int model_trained_jobs(const fsp_model *m) { return m->trained_jobs; }
 }  // namespace fspi
 
 extern "C" {
@@ -680,6 +682,12 @@ int fsp_model_free(fsp_model *m) {
 }
 
 int64_t fsp_model_param_count(void) { return kParams; }
+
+int fsp_model_set_trained_jobs(fsp_model *m, int32_t n) {
+  if (!m || n < 0) return FSP_EINVAL;
+  m->trained_jobs = n;
+  return FSP_OK;
+}
 
 int fsp_model_set_params(fsp_model *m, const float *host, int64_t n) {
   if (!m || !host || n != kParams) return FSP_EINVAL;

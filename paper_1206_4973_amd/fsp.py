@@ -151,6 +151,8 @@ def lib() -> ctypes.CDLL:
     L.fsp_model_free.restype = ctypes.c_int
     L.fsp_model_param_count.argtypes = []
     L.fsp_model_param_count.restype = i64
+    L.fsp_model_set_trained_jobs.argtypes = [P, i32]
+    L.fsp_model_set_trained_jobs.restype = ctypes.c_int
     for name in ("fsp_model_set_params", "fsp_model_get_params", "fsp_model_get_grads"):
         getattr(L, name).argtypes = [P, P, i64]
         getattr(L, name).restype = ctypes.c_int
@@ -547,6 +549,11 @@ class Model:
         p = np.ascontiguousarray(p, dtype=np.float32)
         _check(lib().fsp_model_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p),
                                           len(p)), "fsp_model_set_params")
+
+    def set_trained_jobs(self, n: int) -> None:
+        """Job count of the training instances (gates the learned search's
+        switch to proof pools; 0: unknown)."""
+        _check(lib().fsp_model_set_trained_jobs(self._h, int(n)), "fsp_model_set_trained_jobs")
 
     def grads(self) -> np.ndarray:
         out = np.zeros(self.nparams, dtype=np.float32)

@@ -106,6 +106,7 @@ def load(path: str) -> fsp.Model:
     meta = json.loads(str(z["meta"]))
     model = fsp.Model(meta["in_features"], meta["outputs"])
     model.set_params(z["params"])
+    model.set_trained_jobs(int(meta.get("n", 0)))
     return model
 
 

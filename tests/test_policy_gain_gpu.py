@@ -79,3 +79,33 @@ def test_learned_ordering_bounds_fewer_nodes(fsp, orc):
     say(f"{len(both)} instances proved by every kind; geomean nodes {nodes}")
     assert nodes["learned"] <= 0.8 * nodes["autotuned"]
     assert nodes["learned"] <= nodes["adaptive"]
+
+
+def test_proof_switch_only_within_the_trained_job_count(fsp, orc):
+    """The learned search switches to proof pools on the network's estimates
+    only for instances of at most the job count the network was trained on
+    (the model file records it).  Told that the network saw fewer jobs, the
+    search keeps diving (proof_pools = 0) and proves the same optimum."""
+    from paper_1206_4973_amd import train_policy
+    model = train_policy.load(MODEL)
+    with pytest.raises(fsp.FspError):
+        model.set_trained_jobs(-1)
+    switched = 0
+    for s in SEEDS[:3]:
+        p = I.instance(20, 10, s)
+        inst = fsp.Instance(p)
+        fsp.autotune_pool(inst)
+        res = {}
+        for trained in (20, 10):
+            model.set_trained_jobs(trained)
+            r = fsp.branch_and_bound(inst, "learned", time_limit=LIMIT, model=model)
+            say(f"seed {s} trained on {trained} jobs: makespan {r.makespan} status {r.status} "
+                f"nodes {r.nodes_bounded} proof pools {r.proof_pools}")
+            assert r.status == 0
+            assert orc.makespan(p, r.perm) == r.makespan
+            res[trained] = r
+        inst.close()
+        assert res[10].proof_pools == 0
+        assert res[10].makespan == res[20].makespan
+        switched += res[20].proof_pools
+    assert switched >= 1, "no search switched to proof pools within the trained job count"
