@@ -148,3 +148,10 @@ def test_bound_choice_rule(L):
     z = np.zeros(256, np.uint32).ctypes.data_as(ctypes.c_void_p)
     assert L.fsp_bound_choice_rule(0, z, z, z, mask.ctypes.data_as(ctypes.c_void_p)) == -1
     assert L.fsp_bound_choice_rule(10, None, z, z, mask.ctypes.data_as(ctypes.c_void_p)) == -1
+
+
+def test_model_trained_jobs_rejects_a_null_model(L):
+    # argument checks come before any device work
+    L.fsp_model_set_trained_jobs.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.fsp_model_set_trained_jobs.restype = ctypes.c_int
+    assert L.fsp_model_set_trained_jobs(None, 50) == -1
