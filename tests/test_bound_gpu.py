@@ -330,6 +330,41 @@ def test_packed_path_limits(fsp, orc, n, m, total, big):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("n,m", [(80, 4), (130, 7)])
+def test_bytes_walk_records_at_the_instance_limits(fsp, orc, n, m):
+    """The bytes walk packs each table position into one word, b - a in the
+    low and lag + b in the high 16 bits, which the instance limits (times up
+    to 32767, job totals up to 65535) keep in range.  Jobs that reach those
+    limits, with b - a = +-32767 and lag + b = 65535 in some pairs, beside
+    small ones: every bound equals the oracle's, on the bytes walk and on the
+    job-mask walk."""
+    rng = np.random.default_rng(n * 100 + m)
+    p = rng.integers(1, 100, size=(n, m)).astype(np.int64)
+    for j in range(8):
+        row = np.zeros(m, np.int64)
+        if j % 2 == 0:
+            # pair (0, 3): a = 0, lag = 32767 + 1, b = 32767: b - a = 32767
+            # and lag + b = 65535 (the job's total)
+            row[1], row[2], row[3] = 32767, 1, 32767
+        else:
+            # pairs (0, l): a = 32767, b = 0: b - a = -32767
+            row[0] = 32767
+        p[j] = row
+    p = p.astype(np.int32)
+    assert p.max() <= 32767 and int(p.sum(axis=1).max()) <= 65535
+    assert int(p.sum(axis=1).max()) == 65535
+    assert int(p.sum()) < (1 << 22)
+    pool = I.random_pool(n, 3000, 0, n, 910000 + n + m)
+    want = orc.bound_pool(p, pool, nthreads=8)
+    for masks in (False, True):
+        inst = fsp.Instance(p, job_masks=masks)
+        say(f"limits n={n} m={m} path {inst.bound_path}")
+        assert inst.bound_path == ("masks" if masks else "bytes")
+        got = gpu_bounds(fsp, inst, pool)
+        inst.close()
+        assert np.array_equal(got, want)
+
+
 def test_concurrent_streams_with_job_mask_scratch(fsp, orc):
     """Instances above 64 jobs on the job-mask walk bound with per-wave mask
     scratch that the library keeps per stream: two streams bounding different
