@@ -450,7 +450,9 @@ class Batch:
 
     ``items``: list of (Instance, uint8 [count, stride] device tensor,
     int32 [count] device tensor or None).  The tensors must stay alive (and
-    keep their storage) as long as the batch is used."""
+    keep their storage) as long as the batch is used.  The keywords are the
+    fields of fsp_batch_config: ``packed=False`` sets one_node_per_lane,
+    ``job_masks=True`` puts segments above 64 jobs on the job masks."""
 
     def __init__(self, items, blocks_per_cu: int = 0, autotune: bool = False,
                  packed: bool = True, job_masks: bool = False):
