@@ -323,7 +323,7 @@ __device__ __forceinline__ uint32_t lds_offset(const char *p) {
 // through the LDS, which bounded the rate when the records were staged there.
 // Groups of eight positions; two register sets take turns: records in
 // s[64:79] (set X) and s[80:95] (set Y), pair A at +0 and pair B at +8; flags
-// in v80..v95 (X) and v96..v111 (Y), A at +0 and B at +8; the job ids of a
+// in v32..v47 (X) and v48..v63 (Y), A at +0 and B at +8; the job ids of a
 // set's next group in s[48:51] (for X) and s[52:55] (for Y), A at +0, B at
 // +2; s[56:63] hold the extracted ids.  A half waits for everything
 // requested (scalar loads complete out of order, so the wait is for all),
@@ -380,51 +380,51 @@ __device__ __forceinline__ void walk2_b8(uint64_t ra, uint64_t rb, uint64_t ja, 
       "s_load_dwordx2 s[54:55], %[jb], %[jo]\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
       FSP_B8_IDS("s48", "s49")
-      FSP_B8_FLAGS("v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87")
+      FSP_B8_FLAGS("v32", "v33", "v34", "v35", "v36", "v37", "v38", "v39")
       FSP_B8_IDS("s50", "s51")
-      FSP_B8_FLAGS("v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95")
+      FSP_B8_FLAGS("v40", "v41", "v42", "v43", "v44", "v45", "v46", "v47")
       "1:\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
       FSP_B8_IDS("s52", "s53")
-      FSP_B8_FLAGS("v96", "v97", "v98", "v99", "v100", "v101", "v102", "v103")
+      FSP_B8_FLAGS("v48", "v49", "v50", "v51", "v52", "v53", "v54", "v55")
       FSP_B8_IDS("s54", "s55")
-      FSP_B8_FLAGS("v104", "v105", "v106", "v107", "v108", "v109", "v110", "v111")
+      FSP_B8_FLAGS("v56", "v57", "v58", "v59", "v60", "v61", "v62", "v63")
       "s_add_u32 %[ro], %[ro], 32\n\t"
       "s_add_u32 %[jo], %[jo], 8\n\t"
       "s_load_dwordx8 s[80:87], %[ra], %[ro]\n\t"
       "s_load_dwordx8 s[88:95], %[rb], %[ro]\n\t"
       "s_load_dwordx2 s[48:49], %[ja], %[jo]\n\t"
       "s_load_dwordx2 s[50:51], %[jb], %[jo]\n\t"
-      FSP_B8_STEP2("v80", "s64", "v88", "s72")
-      FSP_B8_STEP2("v81", "s65", "v89", "s73")
-      FSP_B8_STEP2("v82", "s66", "v90", "s74")
-      FSP_B8_STEP2("v83", "s67", "v91", "s75")
-      FSP_B8_STEP2("v84", "s68", "v92", "s76")
-      FSP_B8_STEP2("v85", "s69", "v93", "s77")
-      FSP_B8_STEP2("v86", "s70", "v94", "s78")
-      FSP_B8_STEP2("v87", "s71", "v95", "s79")
+      FSP_B8_STEP2("v32", "s64", "v40", "s72")
+      FSP_B8_STEP2("v33", "s65", "v41", "s73")
+      FSP_B8_STEP2("v34", "s66", "v42", "s74")
+      FSP_B8_STEP2("v35", "s67", "v43", "s75")
+      FSP_B8_STEP2("v36", "s68", "v44", "s76")
+      FSP_B8_STEP2("v37", "s69", "v45", "s77")
+      FSP_B8_STEP2("v38", "s70", "v46", "s78")
+      FSP_B8_STEP2("v39", "s71", "v47", "s79")
       "s_sub_u32 %[cnt], %[cnt], 1\n\t"
       "s_cmp_eq_u32 %[cnt], 0\n\t"
       "s_cbranch_scc1 2f\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
       FSP_B8_IDS("s48", "s49")
-      FSP_B8_FLAGS("v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87")
+      FSP_B8_FLAGS("v32", "v33", "v34", "v35", "v36", "v37", "v38", "v39")
       FSP_B8_IDS("s50", "s51")
-      FSP_B8_FLAGS("v88", "v89", "v90", "v91", "v92", "v93", "v94", "v95")
+      FSP_B8_FLAGS("v40", "v41", "v42", "v43", "v44", "v45", "v46", "v47")
       "s_add_u32 %[ro], %[ro], 32\n\t"
       "s_add_u32 %[jo], %[jo], 8\n\t"
       "s_load_dwordx8 s[64:71], %[ra], %[ro]\n\t"
       "s_load_dwordx8 s[72:79], %[rb], %[ro]\n\t"
       "s_load_dwordx2 s[52:53], %[ja], %[jo]\n\t"
       "s_load_dwordx2 s[54:55], %[jb], %[jo]\n\t"
-      FSP_B8_STEP2("v96", "s80", "v104", "s88")
-      FSP_B8_STEP2("v97", "s81", "v105", "s89")
-      FSP_B8_STEP2("v98", "s82", "v106", "s90")
-      FSP_B8_STEP2("v99", "s83", "v107", "s91")
-      FSP_B8_STEP2("v100", "s84", "v108", "s92")
-      FSP_B8_STEP2("v101", "s85", "v109", "s93")
-      FSP_B8_STEP2("v102", "s86", "v110", "s94")
-      FSP_B8_STEP2("v103", "s87", "v111", "s95")
+      FSP_B8_STEP2("v48", "s80", "v56", "s88")
+      FSP_B8_STEP2("v49", "s81", "v57", "s89")
+      FSP_B8_STEP2("v50", "s82", "v58", "s90")
+      FSP_B8_STEP2("v51", "s83", "v59", "s91")
+      FSP_B8_STEP2("v52", "s84", "v60", "s92")
+      FSP_B8_STEP2("v53", "s85", "v61", "s93")
+      FSP_B8_STEP2("v54", "s86", "v62", "s94")
+      FSP_B8_STEP2("v55", "s87", "v63", "s95")
       "s_sub_u32 %[cnt], %[cnt], 1\n\t"
       "s_cmp_eq_u32 %[cnt], 0\n\t"
       "s_cbranch_scc0 1b\n"
@@ -433,9 +433,9 @@ __device__ __forceinline__ void walk2_b8(uint64_t ra, uint64_t rb, uint64_t ja, 
       : [zA] "+v"(ZA), [zB] "+v"(ZB), [tA] "=&v"(tA), [uA] "=&v"(uA), [tB] "=&v"(tB),
         [uB] "=&v"(uB), [ro] "+s"(ro), [jo] "+s"(jo), [cnt] "+s"(cnt)
       : [ra] "s"(ra), [rb] "s"(rb), [ja] "s"(ja), [jb] "s"(jb), [lane] "v"(lane)
-      : "v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87", "v88", "v89", "v90",
-        "v91", "v92", "v93", "v94", "v95", "v96", "v97", "v98", "v99", "v100", "v101",
-        "v102", "v103", "v104", "v105", "v106", "v107", "v108", "v109", "v110", "v111",
+      : "v32", "v33", "v34", "v35", "v36", "v37", "v38", "v39", "v40", "v41", "v42",
+        "v43", "v44", "v45", "v46", "v47", "v48", "v49", "v50", "v51", "v52", "v53",
+        "v54", "v55", "v56", "v57", "v58", "v59", "v60", "v61", "v62", "v63",
         "s48", "s49", "s50", "s51", "s52", "s53", "s54", "s55", "s56", "s57", "s58",
         "s59", "s60", "s61", "s62", "s63", "s64", "s65", "s66", "s67", "s68", "s69",
         "s70", "s71", "s72", "s73", "s74", "s75", "s76", "s77", "s78", "s79", "s80",
@@ -456,33 +456,33 @@ __device__ __forceinline__ int walk1_b8(uint64_t ra, uint64_t ja, uint32_t lane,
       "s_load_dwordx2 s[52:53], %[ja], %[jo]\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
       FSP_B8_IDS("s48", "s49")
-      FSP_B8_FLAGS("v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87")
+      FSP_B8_FLAGS("v32", "v33", "v34", "v35", "v36", "v37", "v38", "v39")
       "1:\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
       FSP_B8_IDS("s52", "s53")
-      FSP_B8_FLAGS("v96", "v97", "v98", "v99", "v100", "v101", "v102", "v103")
+      FSP_B8_FLAGS("v48", "v49", "v50", "v51", "v52", "v53", "v54", "v55")
       "s_add_u32 %[ro], %[ro], 32\n\t"
       "s_add_u32 %[jo], %[jo], 8\n\t"
       "s_load_dwordx8 s[80:87], %[ra], %[ro]\n\t"
       "s_load_dwordx2 s[48:49], %[ja], %[jo]\n\t"
-      FSP_B8_STEP1("v80", "s64") FSP_B8_STEP1("v81", "s65")
-      FSP_B8_STEP1("v82", "s66") FSP_B8_STEP1("v83", "s67")
-      FSP_B8_STEP1("v84", "s68") FSP_B8_STEP1("v85", "s69")
-      FSP_B8_STEP1("v86", "s70") FSP_B8_STEP1("v87", "s71")
+      FSP_B8_STEP1("v32", "s64") FSP_B8_STEP1("v33", "s65")
+      FSP_B8_STEP1("v34", "s66") FSP_B8_STEP1("v35", "s67")
+      FSP_B8_STEP1("v36", "s68") FSP_B8_STEP1("v37", "s69")
+      FSP_B8_STEP1("v38", "s70") FSP_B8_STEP1("v39", "s71")
       "s_sub_u32 %[cnt], %[cnt], 1\n\t"
       "s_cmp_eq_u32 %[cnt], 0\n\t"
       "s_cbranch_scc1 2f\n\t"
       "s_waitcnt lgkmcnt(0)\n\t"
       FSP_B8_IDS("s48", "s49")
-      FSP_B8_FLAGS("v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87")
+      FSP_B8_FLAGS("v32", "v33", "v34", "v35", "v36", "v37", "v38", "v39")
       "s_add_u32 %[ro], %[ro], 32\n\t"
       "s_add_u32 %[jo], %[jo], 8\n\t"
       "s_load_dwordx8 s[64:71], %[ra], %[ro]\n\t"
       "s_load_dwordx2 s[52:53], %[ja], %[jo]\n\t"
-      FSP_B8_STEP1("v96", "s80") FSP_B8_STEP1("v97", "s81")
-      FSP_B8_STEP1("v98", "s82") FSP_B8_STEP1("v99", "s83")
-      FSP_B8_STEP1("v100", "s84") FSP_B8_STEP1("v101", "s85")
-      FSP_B8_STEP1("v102", "s86") FSP_B8_STEP1("v103", "s87")
+      FSP_B8_STEP1("v48", "s80") FSP_B8_STEP1("v49", "s81")
+      FSP_B8_STEP1("v50", "s82") FSP_B8_STEP1("v51", "s83")
+      FSP_B8_STEP1("v52", "s84") FSP_B8_STEP1("v53", "s85")
+      FSP_B8_STEP1("v54", "s86") FSP_B8_STEP1("v55", "s87")
       "s_sub_u32 %[cnt], %[cnt], 1\n\t"
       "s_cmp_eq_u32 %[cnt], 0\n\t"
       "s_cbranch_scc0 1b\n"
@@ -491,8 +491,8 @@ __device__ __forceinline__ int walk1_b8(uint64_t ra, uint64_t ja, uint32_t lane,
       : [zA] "+v"(Z), [tA] "=&v"(tA), [uA] "=&v"(uA), [ro] "+s"(ro), [jo] "+s"(jo),
         [cnt] "+s"(cnt)
       : [ra] "s"(ra), [ja] "s"(ja), [lane] "v"(lane)
-      : "v80", "v81", "v82", "v83", "v84", "v85", "v86", "v87", "v96", "v97", "v98",
-        "v99", "v100", "v101", "v102", "v103", "s48", "s49", "s52", "s53", "s56", "s57",
+      : "v32", "v33", "v34", "v35", "v36", "v37", "v38", "v39", "v48", "v49", "v50",
+        "v51", "v52", "v53", "v54", "v55", "s48", "s49", "s52", "s53", "s56", "s57",
         "s58", "s59", "s60", "s61", "s62", "s63", "s64", "s65", "s66", "s67", "s68",
         "s69", "s70", "s71", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87",
         "scc", "memory");
